@@ -1,0 +1,213 @@
+/*
+ * pm.h -- C ABI of the MI355X photon-mapping library (libpm.so).
+ *
+ * The library implements the data-parallel hot path of a stochastic
+ * progressive photon mapping renderer (Hachisuka, "Implementing a
+ * Photorealistic Rendering System using GLSL", EGSR 2015): a multiple-threaded
+ * BVH (Sec. 3.1) traversed stacklessly with closest-hit ray/triangle tests,
+ * the float-only combined-MLCG random number generator (Sec. 3.2), photon
+ * tracing with Russian roulette and path regeneration (Sec. 2, Sec. 3.3),
+ * and the range query plus progressive radius/flux update of each iteration
+ * (Sec. 2).
+ *
+ * Conventions
+ *   - Every call returns PM_OK (0) or a negative pm_status.  On error
+ *     pm_last_error() returns a thread-local message; nothing was enqueued
+ *     if the error is PM_ERR_ARG (arguments are validated on the host first).
+ *   - "host" pointers are ordinary CPU memory read during the call; "device"
+ *     pointers are HIP device allocations (e.g. PyTorch tensors) owned by the
+ *     caller unless stated otherwise.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously on it; the caller synchronises.
+ *   - Option/parameter structs start with `uint32_t size` = sizeof(struct),
+ *     so later versions can extend them.
+ *   - Handles are not thread-safe; use one handle per stream.
+ *   - No C++ exception crosses this boundary.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM_ABI_VERSION 1
+
+#if defined(__GNUC__)
+#define PM_API __attribute__((visibility("default")))
+#else
+#define PM_API
+#endif
+
+typedef enum {
+    PM_OK = 0,
+    PM_ERR_ARG = -1,      /* invalid argument (nothing enqueued) */
+    PM_ERR_HIP = -2,      /* HIP runtime error */
+    PM_ERR_OVERFLOW = -3, /* a fixed-capacity device buffer overflowed */
+    PM_ERR_STATE = -4,    /* call not valid in the handle's current state */
+    PM_ERR_NOMEM = -5     /* host or device allocation failed */
+} pm_status;
+
+/* Material kinds (diffuse is two-sided Lambertian; emission is one-sided,
+ * along the geometric normal n = normalize((v1-v0) x (v2-v0))). */
+enum { PM_MAT_DIFFUSE = 0, PM_MAT_MIRROR = 1, PM_MAT_GLASS = 2 };
+
+typedef struct pm_bvh pm_bvh;
+typedef struct pm_sppm pm_sppm;
+
+/* ABI version of the loaded library (PM_ABI_VERSION at build time). */
+PM_API int pm_abi_version(void);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+PM_API const char *pm_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Multiple-threaded BVH (Sec. 3.1)                                    */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t size;     /* sizeof(pm_bvh_opts) */
+    int32_t bins;      /* SAH bins per axis, 2..256 (default 32) */
+    int32_t max_leaf;  /* triangles per leaf, 1..7 (default 4) */
+    int32_t n_threads; /* host build threads, 0 = all */
+} pm_bvh_opts;
+
+typedef struct {
+    uint32_t size;        /* sizeof(pm_bvh_info) */
+    int64_t n_tri;
+    int64_t n_nodes;      /* nodes of the binary tree (each stored once per link set) */
+    int64_t n_leaves;
+    int32_t depth;
+    int32_t max_leaf;
+    double sah_cost;      /* C_trav = C_isect = 1, normalised by the root area */
+    int64_t device_bytes; /* nodes (6 link sets x 32 B) + triangles (48 B) */
+    double build_ms;      /* host build + threading time */
+} pm_bvh_info;
+
+/* Build the BVH on the host (top-down binned SAH, Sec. 3.1 "standard top-down
+ * sweeping algorithm ... based on SAH"), thread it six times with children
+ * pre-sorted along +x,-x,+y,-y,+z,-z (the multiple-threaded BVH), and copy it
+ * to the device on `stream`.
+ *   tri_verts  host, float32 [n_tri][3][3] vertex positions (finite)
+ *   tri_mat    host, uint32 [n_tri] material ids (may be NULL: all 0)
+ *   opts       may be NULL (defaults above)
+ *   out        receives a library-owned handle; free with pm_bvh_destroy.
+ * Errors: PM_ERR_ARG for n_tri < 1, n_tri >= 2^28, non-finite vertices or bad
+ * options; PM_ERR_HIP / PM_ERR_NOMEM for device failures. */
+PM_API int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
+                 void *stream, pm_bvh **out);
+
+/* Host-only build (no device needed), for inspection and tests.  Two-phase:
+ * call with nodes == tris == NULL to learn *n_nodes; then call again with
+ *   nodes  host, [6][n_nodes][8] 32-bit words per link set s, node i in that
+ *          set's preorder: lo.xyz, hi.xyz (float bits), skip (int32: preorder
+ *          index after this subtree, n_nodes at the end), leaf word (uint32:
+ *          0 for an inner node, else first_tri << 3 | count)
+ *   tris   host, [n_tri][12] 32-bit words in leaf order: v0.xyz, e1.xyz,
+ *          e2.xyz (float bits), original index, material, 0. */
+PM_API int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
+                      int64_t *n_nodes, uint32_t *nodes, uint32_t *tris, pm_bvh_info *info);
+
+PM_API int pm_bvh_destroy(pm_bvh *bvh);
+PM_API int pm_bvh_get_info(const pm_bvh *bvh, pm_bvh_info *info);
+
+/* Closest hit of every ray (the traversal loop of Sec. 3.1, Fig. "mtbvh").
+ *   rays  device, float32 [n][8] = o.xyz, tmin, d.xyz, tmax
+ *   hit   device, int32 [n]: ORIGINAL index of the closest triangle with
+ *         tmin < t < tmax (ties in t go to the lower index), or -1
+ *   t     device, float32 [n]: its distance along d, +inf on a miss
+ * The result is independent of which link set is traversed.
+ * Errors: PM_ERR_ARG for n < 0 or NULL pointers with n > 0. */
+PM_API int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t, void *stream);
+
+typedef struct {
+    uint32_t size;      /* sizeof(pm_trace_opts) */
+    int32_t link_set;   /* -1: pick by ray direction (MTBVH); 0..5: force one
+                           link set for every ray (single threaded BVH) */
+    uint32_t *counters; /* optional device [n][2]: AABB tests, triangle tests */
+} pm_trace_opts;
+
+/* pm_trace_rays with options (ablation of the link-set choice; per-ray
+ * traversal statistics for the algorithmic-bytes roofline). */
+PM_API int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
+                     const pm_trace_opts *opts, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Stochastic progressive photon mapping (Sec. 2)                      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint32_t size;            /* sizeof(pm_scene_desc) */
+    const float *tri_verts;   /* host [n_tri][3][3] */
+    const uint32_t *tri_mat;  /* host [n_tri] */
+    int64_t n_tri;
+    const int32_t *mat_type;  /* host [n_mat] PM_MAT_* */
+    const float *mat_rho;     /* host [n_mat] diffuse albedo in [0,1) */
+    const float *mat_q;       /* host [n_mat] Russian-roulette survival
+                                 probability (nominal albedo, held fixed) */
+    const float *mat_Le;      /* host [n_mat] emitted radiance, >= 0 */
+    const float *mat_ior;     /* host [n_mat] index of refraction (glass) */
+    int32_t n_mat;
+    float cam_pos[3], cam_look[3], cam_up[3];
+    float tan_half_fov;       /* tan(vertical field of view / 2) */
+    int32_t width, height;
+    const pm_bvh *bvh;        /* optional BVH already built over tri_verts */
+} pm_scene_desc;
+
+typedef struct {
+    uint32_t size;            /* sizeof(pm_sppm_params) */
+    int64_t n_photons;        /* photon paths per iteration, 1..2^26 */
+    double alpha;             /* radius reduction, (0,1] */
+    double r0;                /* initial radius, > 0 */
+    uint64_t seed;
+    int32_t max_eye_depth;    /* specular eye-path length cap (16) */
+    int32_t max_photon_bounces; /* photon path length cap (32) */
+    int32_t fixed_shift;      /* flux fixed point: value * 2^shift (40) */
+    int32_t store_factor;     /* photon store capacity = n_photons * factor (8) */
+} pm_sppm_params;
+
+/* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)
+ * and allocates the per-pixel state (N = 0, R^2 = r0^2, tau = 0, D = 0).
+ * The handle owns all device buffers it allocates. */
+PM_API int pm_sppm_create(const pm_scene_desc *desc, const pm_sppm_params *params, void *stream, pm_sppm **out);
+PM_API int pm_sppm_destroy(pm_sppm *s);
+
+/* Enqueue n_iter iterations (eye pass, photon pass, hashed-grid build,
+ * range query, progressive update).  Counts stay on the device; a photon
+ * store overflow sets a sticky device flag reported by pm_sppm_status. */
+PM_API int pm_sppm_iterate(pm_sppm *s, int32_t n_iter, void *stream);
+
+/* Radiance estimate of the iterations so far into `image` (device, float32
+ * [height][width]): tau / (pi R^2 K) + D / K.  PM_ERR_STATE if K == 0. */
+PM_API int pm_sppm_resolve(pm_sppm *s, float *image, void *stream);
+
+/* Synchronise `stream` and report sticky device errors (PM_ERR_OVERFLOW). */
+PM_API int pm_sppm_status(pm_sppm *s, void *stream);
+
+/* create -> K x iterate -> resolve -> status -> destroy. */
+PM_API int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream);
+
+/* Device buffers of a handle, for inspection (owned by the handle, valid
+ * until it is destroyed). */
+typedef struct {
+    uint32_t size;            /* sizeof(pm_sppm_views) */
+    int64_t n_pixels;
+    int32_t iterations;       /* K so far */
+    int64_t photon_capacity;
+    int64_t table_size;       /* hashed-grid buckets */
+    double *N, *R2, *tau, *D; /* [n_pixels] */
+    float *hp_pos;            /* [n_pixels][4]: x, y, z, W*rho/pi */
+    float *hp_nrm;            /* [n_pixels][4]: n (toward the eye), int bits: material or -1 */
+    float *photons;           /* [capacity][8]: x, y, z, phi, w.xyz, bits: path << 5 | bounce */
+    uint32_t *photon_count;   /* [1] photons stored in the last iteration */
+    uint32_t *gather_M;       /* [n_pixels] photons found in the last iteration */
+    uint64_t *gather_Phi;     /* [n_pixels] their fixed-point flux */
+} pm_sppm_views;
+
+PM_API int pm_sppm_get_views(pm_sppm *s, pm_sppm_views *v);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PM_H */

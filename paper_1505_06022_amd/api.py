@@ -1,0 +1,319 @@
+"""Python binding of libpm.so (ctypes).  Argument marshalling only.
+
+Every function here forwards to the C ABI declared in include/pm.h under the
+same name without the ``pm_`` prefix.  Device buffers are PyTorch tensors on
+the current HIP device; the stream is PyTorch's current stream unless one is
+given.  There is no CPU fallback: if the library is missing or fails to load,
+the import error is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpm.so")
+
+PM_OK, PM_ERR_ARG, PM_ERR_HIP, PM_ERR_OVERFLOW, PM_ERR_STATE, PM_ERR_NOMEM = 0, -1, -2, -3, -4, -5
+
+EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host", "pm_bvh_destroy",
+           "pm_bvh_get_info", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
+           "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views"]
+
+
+class PMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pm error {code}: {msg}")
+        self.code = code
+
+
+class BvhOpts(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("bins", C.c_int32), ("max_leaf", C.c_int32), ("n_threads", C.c_int32)]
+
+
+class BvhInfo(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("n_tri", C.c_int64), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64),
+                ("depth", C.c_int32), ("max_leaf", C.c_int32), ("sah_cost", C.c_double),
+                ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("link_set", C.c_int32), ("counters", C.c_void_p)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("tri_verts", C.c_void_p), ("tri_mat", C.c_void_p), ("n_tri", C.c_int64),
+                ("mat_type", C.c_void_p), ("mat_rho", C.c_void_p), ("mat_q", C.c_void_p),
+                ("mat_Le", C.c_void_p), ("mat_ior", C.c_void_p), ("n_mat", C.c_int32),
+                ("cam_pos", C.c_float * 3), ("cam_look", C.c_float * 3), ("cam_up", C.c_float * 3),
+                ("tan_half_fov", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("bvh", C.c_void_p)]
+
+
+class SppmParams(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("n_photons", C.c_int64), ("alpha", C.c_double), ("r0", C.c_double),
+                ("seed", C.c_uint64), ("max_eye_depth", C.c_int32), ("max_photon_bounces", C.c_int32),
+                ("fixed_shift", C.c_int32), ("store_factor", C.c_int32)]
+
+
+class SppmViews(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("n_pixels", C.c_int64), ("iterations", C.c_int32),
+                ("photon_capacity", C.c_int64), ("table_size", C.c_int64),
+                ("N", C.c_void_p), ("R2", C.c_void_p), ("tau", C.c_void_p), ("D", C.c_void_p),
+                ("hp_pos", C.c_void_p), ("hp_nrm", C.c_void_p), ("photons", C.c_void_p),
+                ("photon_count", C.c_void_p), ("gather_M", C.c_void_p), ("gather_Phi", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libpm.so (raises if it is absent: build it with paper_1505_06022_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1505_06022_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32 = C.c_void_p, C.c_int64, C.c_int32
+        L.pm_abi_version.restype = C.c_int
+        L.pm_last_error.restype = C.c_char_p
+        L.pm_build_bvh.argtypes = [P, P, I64, P, P, P]
+        L.pm_build_bvh_host.argtypes = [P, P, I64, P, P, P, P, P]
+        L.pm_bvh_destroy.argtypes = [P]
+        L.pm_bvh_get_info.argtypes = [P, P]
+        L.pm_trace_rays.argtypes = [P, P, I64, P, P, P]
+        L.pm_trace_rays_ex.argtypes = [P, P, I64, P, P, P, P]
+        L.pm_sppm_create.argtypes = [P, P, P, P]
+        L.pm_sppm_destroy.argtypes = [P]
+        L.pm_sppm_iterate.argtypes = [P, I32, P]
+        L.pm_sppm_resolve.argtypes = [P, P, P]
+        L.pm_sppm_status.argtypes = [P, P]
+        L.pm_render.argtypes = [P, P, I32, P, P]
+        L.pm_sppm_get_views.argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PM_OK:
+        raise PMError(rc, lib().pm_last_error().decode())
+
+
+def _ptr(a) -> int:
+    return a.ctypes.data if isinstance(a, np.ndarray) else a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _opts(bins, max_leaf, n_threads):
+    o = BvhOpts()
+    o.size, o.bins, o.max_leaf, o.n_threads = C.sizeof(BvhOpts), bins, max_leaf, n_threads
+    return o
+
+
+def abi_version() -> int:
+    return lib().pm_abi_version()
+
+
+# ---------------------------------------------------------------------------
+# BVH
+# ---------------------------------------------------------------------------
+class Bvh:
+    """Device multiple-threaded BVH owned by the library."""
+
+    def __init__(self, handle: int, n_tri: int):
+        self.h = C.c_void_p(handle)
+        self.n_tri = n_tri
+
+    def info(self) -> dict:
+        inf = BvhInfo()
+        inf.size = C.sizeof(BvhInfo)
+        _check(lib().pm_bvh_get_info(self.h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in BvhInfo._fields_ if k != "size"}
+
+    def destroy(self):
+        if self.h:
+            _check(lib().pm_bvh_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def build_bvh(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0,
+              stream=None) -> Bvh:
+    v = np.ascontiguousarray(verts, np.float32)
+    m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
+    out = C.c_void_p()
+    o = _opts(bins, max_leaf, n_threads)
+    _check(lib().pm_build_bvh(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), _stream(stream),
+                              C.byref(out)))
+    return Bvh(out.value, v.shape[0])
+
+
+def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0):
+    """Host-only build: returns (nodes uint32 [6, n_nodes, 8], tris uint32 [T, 12], info dict)."""
+    v = np.ascontiguousarray(verts, np.float32)
+    m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
+    o = _opts(bins, max_leaf, n_threads)
+    nn = C.c_int64()
+    L = lib()
+    _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
+                               None, None, None))
+    nodes = np.zeros((6, nn.value, 8), np.uint32)
+    tris = np.zeros((v.shape[0], 12), np.uint32)
+    inf = BvhInfo()
+    inf.size = C.sizeof(BvhInfo)
+    _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
+                               _ptr(nodes), _ptr(tris), C.byref(inf)))
+    return nodes, tris, {k: getattr(inf, k) for k, _ in BvhInfo._fields_ if k != "size"}
+
+
+def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=None, stream=None):
+    """Closest hit of each ray.  rays: float32 cuda tensor [n, 8]; returns (hit int32 [n], t float32 [n])."""
+    import torch
+    assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
+    n = rays.shape[0]
+    if hit is None:
+        hit = torch.empty(n, dtype=torch.int32, device=rays.device)
+    if t is None:
+        t = torch.empty(n, dtype=torch.float32, device=rays.device)
+    if link_set == -1 and counters is None:
+        _check(lib().pm_trace_rays(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), _stream(stream)))
+    else:
+        o = TraceOpts()
+        o.size, o.link_set = C.sizeof(TraceOpts), link_set
+        o.counters = None if counters is None else counters.data_ptr()
+        _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
+    return hit, t
+
+
+# ---------------------------------------------------------------------------
+# SPPM
+# ---------------------------------------------------------------------------
+def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, max_photon_bounces=32,
+                fixed_shift=40, store_factor=8) -> SppmParams:
+    p = SppmParams()
+    p.size = C.sizeof(SppmParams)
+    p.n_photons, p.alpha, p.r0, p.seed = n_photons, alpha, float(r0), seed
+    p.max_eye_depth, p.max_photon_bounces = max_eye_depth, max_photon_bounces
+    p.fixed_shift, p.store_factor = fixed_shift, store_factor
+    return p
+
+
+class _SceneArgs:
+    """Scene description plus the host arrays it points into (kept alive)."""
+
+    def __init__(self, scene, bvh: Bvh | None = None):
+        self.keep = [np.ascontiguousarray(scene.verts, np.float32), np.ascontiguousarray(scene.tri_mat, np.uint32),
+                     np.ascontiguousarray(scene.mat_type, np.int32), np.ascontiguousarray(scene.mat_rho, np.float32),
+                     np.ascontiguousarray(scene.mat_q, np.float32), np.ascontiguousarray(scene.mat_Le, np.float32),
+                     np.ascontiguousarray(scene.mat_ior, np.float32)]
+        v, tm, mt, rho, q, Le, ior = self.keep
+        d = SceneDesc()
+        d.size = C.sizeof(SceneDesc)
+        d.tri_verts, d.tri_mat, d.n_tri = _ptr(v), _ptr(tm), v.shape[0]
+        d.mat_type, d.mat_rho, d.mat_q, d.mat_Le, d.mat_ior = _ptr(mt), _ptr(rho), _ptr(q), _ptr(Le), _ptr(ior)
+        d.n_mat = len(mt)
+        cam = scene.camera
+        d.cam_pos[:] = cam.pos
+        d.cam_look[:] = cam.look
+        d.cam_up[:] = cam.up
+        d.tan_half_fov = cam.tan_half_fov
+        d.width, d.height = cam.width, cam.height
+        d.bvh = bvh.h.value if bvh is not None else None
+        self.desc = d
+        self.bvh = bvh
+
+
+def _device_view(ptr: int, shape, dtype):
+    """Zero-copy tensor over a library-owned device buffer."""
+    import torch
+    typestr = {torch.float32: "<f4", torch.float64: "<f8", torch.int32: "<i4", torch.uint32: "<u4",
+               torch.int64: "<i8", torch.uint64: "<u8"}[dtype]
+
+    class _Iface:
+        __cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (ptr, False), "version": 2,
+                                    "strides": None}
+    return torch.as_tensor(_Iface(), device="cuda")
+
+
+class Sppm:
+    """One progressive photon mapping renderer (library-owned device state)."""
+
+    def __init__(self, scene, params: SppmParams, bvh: Bvh | None = None, stream=None):
+        self.args = _SceneArgs(scene, bvh)
+        self.params = params
+        self.width, self.height = scene.camera.width, scene.camera.height
+        out = C.c_void_p()
+        _check(lib().pm_sppm_create(C.byref(self.args.desc), C.byref(params), _stream(stream), C.byref(out)))
+        self.h = out
+
+    def iterate(self, n: int = 1, stream=None):
+        _check(lib().pm_sppm_iterate(self.h, n, _stream(stream)))
+
+    def resolve(self, image=None, stream=None):
+        import torch
+        if image is None:
+            image = torch.empty((self.height, self.width), dtype=torch.float32, device="cuda")
+        _check(lib().pm_sppm_resolve(self.h, _ptr(image), _stream(stream)))
+        return image
+
+    def status(self, stream=None):
+        _check(lib().pm_sppm_status(self.h, _stream(stream)))
+
+    def views(self) -> dict:
+        """Tensors aliasing the handle's device buffers (valid until destroy)."""
+        import torch
+        v = SppmViews()
+        v.size = C.sizeof(SppmViews)
+        _check(lib().pm_sppm_get_views(self.h, C.byref(v)))
+        P, cap = v.n_pixels, v.photon_capacity
+        return dict(
+            iterations=v.iterations, table_size=v.table_size,
+            N=_device_view(v.N, (P,), torch.float64), R2=_device_view(v.R2, (P,), torch.float64),
+            tau=_device_view(v.tau, (P,), torch.float64), D=_device_view(v.D, (P,), torch.float64),
+            hp_pos=_device_view(v.hp_pos, (P, 4), torch.float32),
+            hp_nrm=_device_view(v.hp_nrm, (P, 4), torch.float32),
+            photons=_device_view(v.photons, (cap, 8), torch.float32),
+            photon_count=_device_view(v.photon_count, (4,), torch.int32),
+            M=_device_view(v.gather_M, (P,), torch.int32),
+            Phi=_device_view(v.gather_Phi, (P,), torch.int64),
+        )
+
+    def destroy(self):
+        if self.h:
+            _check(lib().pm_sppm_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def sppm_create(scene, params: SppmParams, bvh: Bvh | None = None, stream=None) -> Sppm:
+    return Sppm(scene, params, bvh, stream)
+
+
+def render(scene, params: SppmParams, K: int, image=None, bvh: Bvh | None = None, stream=None):
+    """create -> K iterations -> resolve -> destroy, in one call."""
+    import torch
+    if image is None:
+        image = torch.empty((scene.camera.height, scene.camera.width), dtype=torch.float32, device="cuda")
+    args = _SceneArgs(scene, bvh)
+    _check(lib().pm_render(C.byref(args.desc), C.byref(params), K, _ptr(image), _stream(stream)))
+    return image

@@ -1,0 +1,312 @@
+// Host construction of the multiple-threaded BVH (Sec. 3.1).
+//
+// 1. Top-down SAH build with binned centroids (bins per axis, leaves of at
+//    most max_leaf triangles; a node larger than max_leaf is always split).
+// 2. Threading: for each of the six principal directions the tree is walked
+//    in preorder with, at every inner node, the child whose box centre comes
+//    first along that direction visited first.  Each node stores its skip
+//    ("miss") link; the "hit" link of an inner node is implicitly the next
+//    node of that preorder, so a hit walks forward through memory.
+// 3. Packing into 32-byte nodes (one copy per direction) and 48-byte
+//    triangles in leaf order.
+#include "bvh_build.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <future>
+#include <thread>
+
+namespace pm {
+namespace {
+
+struct Box {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void grow(const Box &b) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], b.lo[a]);
+            hi[a] = std::max(hi[a], b.hi[a]);
+        }
+    }
+    void grow(const float *p) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], p[a]);
+            hi[a] = std::max(hi[a], p[a]);
+        }
+    }
+    double area() const {
+        double d[3];
+        for (int a = 0; a < 3; ++a) d[a] = hi[a] >= lo[a] ? (double)hi[a] - lo[a] : 0.0;
+        return 2.0 * (d[0] * d[1] + d[1] * d[2] + d[2] * d[0]);
+    }
+};
+
+struct TNode {
+    Box box;
+    int32_t left = -1, right = -1;  // left < 0: leaf
+    int32_t start = 0, count = 0;
+};
+
+struct Builder {
+    const float *V;
+    int64_t n;
+    int bins, max_leaf;
+    std::vector<Box> tb;
+    std::vector<float> cen;
+    std::vector<int32_t> idx;
+    int par_depth;
+
+    int32_t build(int32_t start, int32_t count, int depth, std::vector<TNode> &out) {
+        int32_t ni = (int32_t)out.size();
+        out.emplace_back();
+        Box nb, cb;
+        for (int32_t i = start; i < start + count; ++i) {
+            nb.grow(tb[idx[i]]);
+            cb.grow(&cen[3 * (size_t)idx[i]]);
+        }
+        out[ni].box = nb;
+        auto make_leaf = [&]() {
+            out[ni].left = out[ni].right = -1;
+            out[ni].start = start;
+            out[ni].count = count;
+            return ni;
+        };
+        if (count == 1) return make_leaf();
+
+        // binned SAH over the three axes
+        double best_cost = INFINITY;
+        int best_axis = -1, best_split = -1;
+        const int B = bins;
+        std::vector<Box> bb(B);
+        std::vector<int32_t> bc(B);
+        std::vector<double> rarea(B);
+        std::vector<int32_t> rcnt(B);
+        for (int a = 0; a < 3; ++a) {
+            float ext = cb.hi[a] - cb.lo[a];
+            if (!(ext > 0.0f)) continue;
+            double scale = (double)B / (double)ext;
+            for (int b = 0; b < B; ++b) { bb[b] = Box(); bc[b] = 0; }
+            for (int32_t i = start; i < start + count; ++i) {
+                int32_t t = idx[i];
+                int b = (int)(((double)cen[3 * (size_t)t + a] - cb.lo[a]) * scale);
+                b = std::min(std::max(b, 0), B - 1);
+                bb[b].grow(tb[t]);
+                bc[b]++;
+            }
+            Box acc;
+            int32_t c = 0;
+            for (int b = B - 1; b > 0; --b) {
+                acc.grow(bb[b]);
+                c += bc[b];
+                rarea[b] = acc.area();
+                rcnt[b] = c;
+            }
+            acc = Box();
+            c = 0;
+            for (int b = 0; b < B - 1; ++b) {
+                acc.grow(bb[b]);
+                c += bc[b];
+                int32_t cr = rcnt[b + 1];
+                if (c == 0 || cr == 0) continue;
+                double cost = acc.area() * c + rarea[b + 1] * cr;
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_axis = a;
+                    best_split = b;
+                }
+            }
+        }
+        double parea = nb.area();
+        double split_cost = best_axis >= 0 ? 1.0 + (parea > 0 ? best_cost / parea : 0.0) : INFINITY;
+        if (count <= max_leaf && (double)count <= split_cost) return make_leaf();
+
+        int32_t nl;
+        if (best_axis < 0) {
+            if (count <= max_leaf) return make_leaf();
+            nl = count / 2;  // coincident centroids: split the index range
+        } else {
+            int a = best_axis;
+            float ext = cb.hi[a] - cb.lo[a];
+            double scale = (double)B / (double)ext;
+            auto mid = std::partition(idx.begin() + start, idx.begin() + start + count, [&](int32_t t) {
+                int b = (int)(((double)cen[3 * (size_t)t + a] - cb.lo[a]) * scale);
+                b = std::min(std::max(b, 0), B - 1);
+                return b <= best_split;
+            });
+            nl = (int32_t)(mid - (idx.begin() + start));
+            if (nl == 0 || nl == count) nl = count / 2;
+        }
+        int32_t l, r;
+        if (depth < par_depth && count > 50000) {
+            std::vector<TNode> right_nodes;
+            auto fut = std::async(std::launch::async, [&]() {
+                return build(start + nl, count - nl, depth + 1, right_nodes);
+            });
+            l = build(start, nl, depth + 1, out);
+            fut.get();
+            int32_t off = (int32_t)out.size();
+            for (auto &nd : right_nodes) {
+                if (nd.left >= 0) {
+                    nd.left += off;
+                    nd.right += off;
+                }
+                out.push_back(nd);
+            }
+            r = off;
+        } else {
+            l = build(start, nl, depth + 1, out);
+            r = build(start + nl, count - nl, depth + 1, out);
+        }
+        out[ni].left = l;
+        out[ni].right = r;
+        out[ni].start = out[ni].count = 0;
+        return ni;
+    }
+};
+
+inline uint32_t fbits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+
+}  // namespace
+
+bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, const BuildOptions &opt, HostBvh &out,
+                    std::string &err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (n_tri < 1 || n_tri >= (int64_t(1) << 28)) {
+        err = "n_tri must be in [1, 2^28)";
+        return false;
+    }
+    if (opt.bins < 2 || opt.bins > 256 || opt.max_leaf < 1 || opt.max_leaf > 7) {
+        err = "bins must be in [2,256] and max_leaf in [1,7]";
+        return false;
+    }
+    for (int64_t i = 0; i < 9 * n_tri; ++i)
+        if (!std::isfinite(verts[i])) {
+            err = "non-finite vertex coordinate at triangle " + std::to_string(i / 9);
+            return false;
+        }
+    Builder b;
+    b.V = verts;
+    b.n = n_tri;
+    b.bins = opt.bins;
+    b.max_leaf = opt.max_leaf;
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int nth = opt.n_threads > 0 ? opt.n_threads : (int)std::min(hw, 16u);
+    b.par_depth = 0;
+    while ((1 << b.par_depth) < nth) b.par_depth++;
+    b.tb.resize((size_t)n_tri);
+    b.cen.resize(3 * (size_t)n_tri);
+    b.idx.resize((size_t)n_tri);
+    Box scene;
+    for (int64_t i = 0; i < n_tri; ++i) {
+        Box t;
+        for (int k = 0; k < 3; ++k) t.grow(verts + 9 * i + 3 * k);
+        b.tb[i] = t;
+        scene.grow(t);
+        for (int a = 0; a < 3; ++a) b.cen[3 * i + a] = 0.5f * (t.lo[a] + t.hi[a]);
+        b.idx[i] = (int32_t)i;
+    }
+    std::vector<TNode> tree;
+    tree.reserve((size_t)(2 * n_tri));
+    b.build(0, (int32_t)n_tri, 0, tree);
+    const int64_t nn = (int64_t)tree.size();
+
+    // statistics: depth, leaves, SAH cost
+    std::vector<int32_t> dep((size_t)nn, 0), size((size_t)nn, 1);
+    double root_area = tree[0].box.area();
+    double sah = 0.0;
+    int64_t leaves = 0;
+    int32_t maxdep = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+        const TNode &t = tree[i];
+        double rel = root_area > 0 ? t.box.area() / root_area : 1.0;
+        if (t.left >= 0) {
+            dep[t.left] = dep[i] + 1;
+            dep[t.right] = dep[i] + 1;
+            sah += rel;
+        } else {
+            leaves++;
+            sah += rel * t.count;
+        }
+        maxdep = std::max(maxdep, dep[i]);
+    }
+    for (int64_t i = nn - 1; i >= 0; --i)
+        if (tree[i].left >= 0) size[i] = 1 + size[tree[i].left] + size[tree[i].right];
+
+    // box padding keeps the slab test conservative for accepted triangle hits
+    float ext = 0.0f;
+    for (int a = 0; a < 3; ++a) ext = std::max(ext, scene.hi[a] - scene.lo[a]);
+    float mag = 0.0f;
+    for (int a = 0; a < 3; ++a) mag = std::max(mag, std::max(std::fabs(scene.lo[a]), std::fabs(scene.hi[a])));
+    const float pad = std::max(ext * 0x1p-15f, mag * 0x1p-20f);
+
+    out.n_tri = n_tri;
+    out.n_nodes = nn;
+    out.n_leaves = leaves;
+    out.depth = maxdep;
+    out.max_leaf = opt.max_leaf;
+    out.sah_cost = sah;
+    for (int a = 0; a < 3; ++a) {
+        out.lo[a] = scene.lo[a];
+        out.hi[a] = scene.hi[a];
+    }
+    out.nodes.assign((size_t)kLinkSets * nn * kNodeWords, 0u);
+    auto thread_set = [&](int s) {
+        const int axis = s >> 1;
+        const bool neg = s & 1;
+        std::vector<int32_t> stack;
+        stack.reserve(256);
+        stack.push_back(0);
+        int64_t pre = 0;
+        uint32_t *base = out.nodes.data() + (size_t)s * nn * kNodeWords;
+        while (!stack.empty()) {
+            int32_t v = stack.back();
+            stack.pop_back();
+            const TNode &t = tree[v];
+            uint32_t *w = base + (size_t)pre * kNodeWords;
+            for (int a = 0; a < 3; ++a) {
+                w[a] = fbits(t.box.lo[a] - pad);
+                w[3 + a] = fbits(t.box.hi[a] + pad);
+            }
+            w[6] = (uint32_t)(pre + size[v]);
+            w[7] = t.left < 0 ? ((uint32_t)t.start << 3) | (uint32_t)t.count : 0u;
+            pre++;
+            if (t.left >= 0) {
+                const Box &L = tree[t.left].box, &R = tree[t.right].box;
+                float kl = L.lo[axis] + L.hi[axis], kr = R.lo[axis] + R.hi[axis];
+                bool right_first = neg ? (kr > kl) : (kr < kl);
+                int32_t first = right_first ? t.right : t.left;
+                int32_t second = right_first ? t.left : t.right;
+                stack.push_back(second);
+                stack.push_back(first);
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int s = 0; s < kLinkSets; ++s) th.emplace_back(thread_set, s);
+    for (auto &x : th) x.join();
+
+    out.tris.assign((size_t)n_tri * kTriWords, 0u);
+    for (int64_t k = 0; k < n_tri; ++k) {
+        int32_t t = b.idx[k];
+        const float *v = verts + 9 * (size_t)t;
+        uint32_t *w = out.tris.data() + (size_t)k * kTriWords;
+        for (int a = 0; a < 3; ++a) {
+            w[a] = fbits(v[a]);
+            w[3 + a] = fbits(v[3 + a] - v[a]);
+            w[6 + a] = fbits(v[6 + a] - v[a]);
+        }
+        w[9] = (uint32_t)t;
+        w[10] = mats ? mats[t] : 0u;
+        w[11] = 0u;
+    }
+    out.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return true;
+}
+
+}  // namespace pm

@@ -1,0 +1,194 @@
+// extern "C" boundary of libpm.so: argument validation, error reporting and
+// dispatch to the host runtime.  No C++ exception escapes these functions.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bvh_build.h"
+#include "pm.h"
+#include "runtime.h"
+#include "sppm.h"
+
+namespace pm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+const char *last_error() { return g_err.c_str(); }
+
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PM_ERR_NOMEM : PM_ERR_HIP;
+}
+
+static bool read_opts(const pm_bvh_opts *o, BuildOptions &bo) {
+    if (!o) return true;
+    if (o->size < sizeof(pm_bvh_opts)) {
+        set_error("pm_bvh_opts.size too small");
+        return false;
+    }
+    bo.bins = o->bins;
+    bo.max_leaf = o->max_leaf;
+    bo.n_threads = o->n_threads;
+    return true;
+}
+
+}  // namespace pm
+
+#define PM_GUARD(...)                                    \
+    try {                                                \
+        pm::clear_error();                               \
+        __VA_ARGS__                                      \
+    } catch (const std::bad_alloc &) {                   \
+        pm::set_error("host allocation failed");         \
+        return PM_ERR_NOMEM;                             \
+    } catch (const std::exception &e) {                  \
+        pm::set_error(e.what());                         \
+        return PM_ERR_STATE;                             \
+    } catch (...) {                                      \
+        pm::set_error("unknown C++ exception");          \
+        return PM_ERR_STATE;                             \
+    }
+
+extern "C" {
+
+int pm_abi_version(void) { return PM_ABI_VERSION; }
+
+const char *pm_last_error(void) { return pm::last_error(); }
+
+int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
+                      int64_t *n_nodes, uint32_t *nodes, uint32_t *tris, pm_bvh_info *info) {
+    PM_GUARD({
+        if (!tri_verts || !n_nodes) return pm::set_error("tri_verts and n_nodes must not be NULL"), PM_ERR_ARG;
+        if (info && info->size < sizeof(pm_bvh_info)) return pm::set_error("pm_bvh_info.size too small"), PM_ERR_ARG;
+        pm::BuildOptions bo;
+        if (!pm::read_opts(opts, bo)) return PM_ERR_ARG;
+        pm::HostBvh hb;
+        std::string err;
+        if (!pm::build_bvh_host(tri_verts, tri_mat, n_tri, bo, hb, err)) return pm::set_error(err), PM_ERR_ARG;
+        *n_nodes = hb.n_nodes;
+        if (nodes) std::memcpy(nodes, hb.nodes.data(), hb.nodes.size() * sizeof(uint32_t));
+        if (tris) std::memcpy(tris, hb.tris.data(), hb.tris.size() * sizeof(uint32_t));
+        if (info) {
+            info->n_tri = hb.n_tri;
+            info->n_nodes = hb.n_nodes;
+            info->n_leaves = hb.n_leaves;
+            info->depth = hb.depth;
+            info->max_leaf = hb.max_leaf;
+            info->sah_cost = hb.sah_cost;
+            info->device_bytes = (int64_t)(hb.nodes.size() + hb.tris.size()) * 4;
+            info->build_ms = hb.build_ms;
+        }
+        return PM_OK;
+    })
+}
+
+int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
+                 void *stream, pm_bvh **out) {
+    PM_GUARD({
+        if (!tri_verts || !out) return pm::set_error("tri_verts and out must not be NULL"), PM_ERR_ARG;
+        *out = nullptr;
+        pm::BuildOptions bo;
+        if (!pm::read_opts(opts, bo)) return PM_ERR_ARG;
+        pm::HostBvh hb;
+        std::string err;
+        if (!pm::build_bvh_host(tri_verts, tri_mat, n_tri, bo, hb, err)) return pm::set_error(err), PM_ERR_ARG;
+        pm_bvh *b = new pm_bvh();
+        int rc = pm::upload_bvh(hb, (hipStream_t)stream, b);
+        if (rc) {
+            pm::free_bvh(b);
+            delete b;
+            return rc;
+        }
+        *out = b;
+        return PM_OK;
+    })
+}
+
+int pm_bvh_destroy(pm_bvh *bvh) {
+    PM_GUARD({
+        if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
+        pm::free_bvh(bvh);
+        delete bvh;
+        return PM_OK;
+    })
+}
+
+int pm_bvh_get_info(const pm_bvh *b, pm_bvh_info *info) {
+    PM_GUARD({
+        if (!b || !info || info->size < sizeof(pm_bvh_info)) return pm::set_error("invalid bvh or info"), PM_ERR_ARG;
+        info->n_tri = b->n_tri;
+        info->n_nodes = b->n_nodes;
+        info->n_leaves = b->n_leaves;
+        info->depth = b->depth;
+        info->max_leaf = b->max_leaf;
+        info->sah_cost = b->sah_cost;
+        info->device_bytes = b->n_nodes * 6 * 32 + b->n_tri * 48;
+        info->build_ms = b->build_ms;
+        return PM_OK;
+    })
+}
+
+int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
+                     const pm_trace_opts *opts, void *stream) {
+    PM_GUARD({
+        if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
+        if (n < 0) return pm::set_error("n must be >= 0"), PM_ERR_ARG;
+        if (n > 0 && (!rays || !hit || !t)) return pm::set_error("NULL ray or output pointer"), PM_ERR_ARG;
+        int set = -1;
+        uint32_t *counters = nullptr;
+        if (opts) {
+            if (opts->size < sizeof(pm_trace_opts)) return pm::set_error("pm_trace_opts.size too small"), PM_ERR_ARG;
+            if (opts->link_set < -1 || opts->link_set > 5) return pm::set_error("link_set must be in [-1,5]"), PM_ERR_ARG;
+            set = opts->link_set;
+            counters = opts->counters;
+        }
+        return pm::launch_trace(bvh, rays, n, hit, t, set, counters, (hipStream_t)stream);
+    })
+}
+
+int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t, void *stream) {
+    return pm_trace_rays_ex(bvh, rays, n, hit, t, nullptr, stream);
+}
+
+int pm_sppm_create(const pm_scene_desc *desc, const pm_sppm_params *params, void *stream, pm_sppm **out) {
+    PM_GUARD({
+        if (!out) return pm::set_error("out must not be NULL"), PM_ERR_ARG;
+        *out = nullptr;
+        return pm::sppm_create(desc, params, (hipStream_t)stream, out);
+    })
+}
+
+int pm_sppm_destroy(pm_sppm *s) { PM_GUARD({ return pm::sppm_destroy(s); }) }
+
+int pm_sppm_iterate(pm_sppm *s, int32_t n_iter, void *stream) {
+    PM_GUARD({ return pm::sppm_iterate(s, n_iter, (hipStream_t)stream); })
+}
+
+int pm_sppm_resolve(pm_sppm *s, float *image, void *stream) {
+    PM_GUARD({ return pm::sppm_resolve(s, image, (hipStream_t)stream); })
+}
+
+int pm_sppm_status(pm_sppm *s, void *stream) { PM_GUARD({ return pm::sppm_status(s, (hipStream_t)stream); }) }
+
+int pm_sppm_get_views(pm_sppm *s, pm_sppm_views *v) { PM_GUARD({ return pm::sppm_views(s, v); }) }
+
+int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream) {
+    PM_GUARD({
+        if (K < 1 || !image) return pm::set_error("K must be >= 1 and image non-NULL"), PM_ERR_ARG;
+        int rc = pm::sppm_validate(desc, params);
+        if (rc) return rc;
+        pm_sppm *s = nullptr;
+        hipStream_t st = (hipStream_t)stream;
+        if ((rc = pm::sppm_create(desc, params, st, &s))) return rc;
+        if (!(rc = pm::sppm_iterate(s, K, st)))
+            if (!(rc = pm::sppm_resolve(s, image, st))) rc = pm::sppm_status(s, st);
+        (void)hipStreamSynchronize(st);
+        pm::sppm_destroy(s);
+        return rc;
+    })
+}
+
+}  // extern "C"

@@ -1,0 +1,319 @@
+// Device building blocks of the photon-mapping hot path (gfx950 / CDNA4).
+//
+// Floating-point rules (the same rules the method is specified with):
+// float32 geometry, no contraction of a*b+c into FMA (explicit fmaf only in
+// the conservative box test), correctly rounded division and square root,
+// fixed evaluation order for dot/cross/normalize, no transcendental calls.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace pmd {
+
+// ---------------------------------------------------------------------------
+// Random numbers (Sec. 3.2): four multiplicative LCGs s <- a*s mod m, each
+// evaluated with Schrage's decomposition (q = m div a, r = m mod a) exactly
+// as the paper's float code does, but in 32-bit integers; output is the
+// fractional part of s0/m0 - s1/m1 + s2/m2 - s3/m3 of the advanced state.
+// ---------------------------------------------------------------------------
+struct Rng {
+    int32_t s0, s1, s2, s3;
+};
+
+enum : uint32_t { kKindEye = 1u, kKindPhoton = 2u };
+
+__device__ __forceinline__ int32_t lcg_step(int32_t s, int32_t a, int32_t q, int32_t r, int32_t m) {
+    int32_t hi = s / q;
+    int32_t lo = s - hi * q;
+    int32_t t = a * lo - r * hi;
+    return t < 0 ? t + m : t;
+}
+
+__device__ __forceinline__ float rng_next(Rng &g) {
+    g.s0 = lcg_step(g.s0, 3423, 1225, 1112, 4194287);
+    g.s1 = lcg_step(g.s1, 2646, 1585, 367, 4194277);
+    g.s2 = lcg_step(g.s2, 1707, 2457, 92, 4194191);
+    g.s3 = lcg_step(g.s3, 1999, 2098, 265, 4194167);
+    float f0 = (float)g.s0 / 4194287.0f;
+    float f1 = (float)g.s1 / 4194277.0f;
+    float f2 = (float)g.s2 / 4194191.0f;
+    float f3 = (float)g.s3 / 4194167.0f;
+    float x = ((f0 - f1) + f2) - f3;
+    float u = x - floorf(x);
+    return u >= 1.0f ? 0x1.fffffep-1f : u;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014)
+__device__ __forceinline__ uint64_t splitmix64(uint64_t &st) {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Per-stream state from a counter key: splitmix64 mixes (seed, kind,
+// iteration, index) into a Marsaglia xorshift128 seed (the generator the
+// paper seeds its per-thread states with), whose outputs 9..12 are reduced
+// into [1, m_j - 1].
+__device__ __forceinline__ Rng rng_seed(uint64_t seed, uint32_t kind, uint32_t k, uint64_t index) {
+    uint64_t st = seed;
+    uint64_t h = splitmix64(st);
+    st = h ^ (((uint64_t)kind << 32) | (uint64_t)k);
+    h = splitmix64(st);
+    st = h ^ index;
+    uint64_t w01 = splitmix64(st);
+    uint64_t w23 = splitmix64(st);
+    uint32_t x = (uint32_t)w01, y = (uint32_t)(w01 >> 32), z = (uint32_t)w23, w = (uint32_t)(w23 >> 32);
+    if ((x | y | z | w) == 0u) x = 1u;
+    uint32_t o[4];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        uint32_t t = x ^ (x << 11);
+        x = y;
+        y = z;
+        z = w;
+        w = (w ^ (w >> 19)) ^ (t ^ (t >> 8));
+        if (i >= 8) o[i - 8] = w;
+    }
+    Rng g;
+    g.s0 = (int32_t)(1u + o[0] % 4194286u);
+    g.s1 = (int32_t)(1u + o[1] % 4194276u);
+    g.s2 = (int32_t)(1u + o[2] % 4194190u);
+    g.s3 = (int32_t)(1u + o[3] % 4194166u);
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// float3 arithmetic with a fixed evaluation order
+// ---------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 vsub(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float vdot(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ V3 vcross(V3 a, V3 b) {
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 vnorm(V3 v) {
+    float l = sqrtf(vdot(v, v));
+    return v3(v.x / l, v.y / l, v.z / l);
+}
+__device__ __forceinline__ V3 vneg(V3 a) { return v3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ V3 vray(V3 o, float t, V3 d) { return v3(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z); }
+
+// ---------------------------------------------------------------------------
+// Scene layout on the device
+// ---------------------------------------------------------------------------
+struct Tri {
+    V3 v0, e1, e2;
+    int32_t id;
+    uint32_t mat;
+};
+
+// 48-byte triangle record: v0.xyz e1.x | e1.yz e2.xy | e2.z id mat 0
+__device__ __forceinline__ Tri load_tri(const float4 *__restrict__ tris, uint32_t k) {
+    const float4 *p = tris + 3 * (size_t)k;
+    float4 a = p[0], b = p[1], c = p[2];
+    Tri t;
+    t.v0 = v3(a.x, a.y, a.z);
+    t.e1 = v3(a.w, b.x, b.y);
+    t.e2 = v3(b.z, b.w, c.x);
+    t.id = __float_as_int(c.y);
+    t.mat = __float_as_uint(c.z);
+    return t;
+}
+
+__device__ __forceinline__ V3 tri_normal(const Tri &t) { return vnorm(vcross(t.e1, t.e2)); }
+
+// Moller-Trumbore, two-sided, fixed operation order; returns t or a NaN-free
+// "no hit" flag.
+__device__ __forceinline__ bool mt_hit(V3 o, V3 d, const Tri &tr, float &t_out) {
+    V3 p = vcross(d, tr.e2);
+    float det = vdot(tr.e1, p);
+    if (det == 0.0f) return false;
+    float inv = 1.0f / det;
+    V3 s = vsub(o, tr.v0);
+    float u = vdot(s, p) * inv;
+    if (u < 0.0f || u > 1.0f) return false;
+    V3 q = vcross(s, tr.e1);
+    float v = vdot(d, q) * inv;
+    if (v < 0.0f || u + v > 1.0f) return false;
+    t_out = vdot(tr.e2, q) * inv;
+    return true;
+}
+
+// Closest-hit acceptance: inside (tmin, tbest), ties in t to the lower index.
+__device__ __forceinline__ bool accept_hit(float t, int32_t id, float tmin, float tbest, int32_t best) {
+    if (!(t > tmin)) return false;
+    if (t < tbest) return true;
+    return t == tbest && best >= 0 && id < best;
+}
+
+// Link set of a ray: the principal direction = major axis of d (ties x, y,
+// z), signed by that component (the cube-map lookup of Fig. "mtbvh").
+__device__ __forceinline__ int link_set(V3 d) {
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    if (ax >= ay && ax >= az) return d.x < 0.0f ? 1 : 0;
+    if (ay >= az) return d.y < 0.0f ? 3 : 2;
+    return d.z < 0.0f ? 5 : 4;
+}
+
+struct Bvh {
+    const float4 *nodes;  // [6][n_nodes][2] float4
+    const float4 *tris;   // [n_tri][3] float4
+    uint32_t n_nodes;
+};
+
+struct TraceStats {
+    uint32_t boxes, tris;
+};
+
+// Stackless closest-hit traversal of one link set (Sec. 3.1, Fig. "mtbvh"):
+// follow the hit link (next node) when the ray meets the node's box, else the
+// miss (skip) link; at a leaf test its triangles and continue with the miss
+// link.  The box test is conservative (boxes are padded at build time and the
+// interval is closed at tbest) so the result equals the brute-force closest
+// hit.
+// Returns the original index of the closest triangle (-1: none); t_out gets
+// its distance (+inf on a miss) and k_out its position in the triangle array.
+template <bool kStats>
+__device__ __forceinline__ int32_t closest_hit(const Bvh &bvh, int set, V3 o, V3 d, float tmin, float tmax,
+                                               int32_t exclude, float &t_out, uint32_t &k_out, TraceStats &st) {
+    const float4 *__restrict__ nodes = bvh.nodes + (size_t)set * bvh.n_nodes * 2;
+    // reciprocal direction; zero components replaced by a tiny signed value
+    float dx = fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x);
+    float dy = fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y);
+    float dz = fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z);
+    float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
+    float ox = -o.x * ix, oy = -o.y * iy, oz = -o.z * iz;
+    int32_t best = -1;
+    uint32_t best_k = 0;
+    float tbest = tmax;
+    uint32_t i = 0;
+    const uint32_t n = bvh.n_nodes;
+    while (i < n) {
+        float4 a = nodes[2 * i];
+        float4 b = nodes[2 * i + 1];
+        float tx0 = fmaf(a.x, ix, ox), tx1 = fmaf(a.w, ix, ox);
+        float ty0 = fmaf(a.y, iy, oy), ty1 = fmaf(b.x, iy, oy);
+        float tz0 = fmaf(a.z, iz, oz), tz1 = fmaf(b.y, iz, oz);
+        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tbest));
+        uint32_t skip = __float_as_uint(b.z);
+        uint32_t leaf = __float_as_uint(b.w);
+        if (kStats) st.boxes++;
+        if (tn <= tf) {
+            if (leaf) {
+                uint32_t first = leaf >> 3, cnt = leaf & 7u;
+                for (uint32_t k = 0; k < cnt; ++k) {
+                    Tri tr = load_tri(bvh.tris, first + k);
+                    if (kStats) st.tris++;
+                    if (tr.id == exclude) continue;
+                    float t;
+                    if (mt_hit(o, d, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
+                        tbest = t;
+                        best = tr.id;
+                        best_k = first + k;
+                    }
+                }
+                i = skip;
+            } else {
+                i = i + 1;
+            }
+        } else {
+            i = skip;
+        }
+    }
+    t_out = best >= 0 ? tbest : __builtin_inff();
+    k_out = best_k;
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// Sampling (only + - * / sqrt; the same rules as the method's definition)
+// ---------------------------------------------------------------------------
+// Orthonormal basis about unit n (Duff et al. 2017).
+__device__ __forceinline__ void onb(V3 n, V3 &b1, V3 &b2) {
+    float sign = copysignf(1.0f, n.z);
+    float a = -1.0f / (sign + n.z);
+    float b = n.x * n.y * a;
+    b1 = v3(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+    b2 = v3(b, sign + n.y * n.y * a, -n.y);
+}
+
+// Cosine-weighted direction about unit n: disk point by rejection from the
+// square (at most 64 tries), lifted to the hemisphere (Malley's method).
+__device__ __forceinline__ V3 cosine_dir(V3 n, Rng &g) {
+    float a = 0.0f, b = 0.0f, r2 = 0.0f;
+    bool ok = false;
+    for (int tries = 0; tries < 64; ++tries) {
+        a = 2.0f * rng_next(g) - 1.0f;
+        b = 2.0f * rng_next(g) - 1.0f;
+        r2 = a * a + b * b;
+        if (r2 < 1.0f) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) {
+        a = 0.0f;
+        b = 0.0f;
+        r2 = 0.0f;
+    }
+    float z = sqrtf(1.0f - r2);
+    V3 t1, t2;
+    onb(n, t1, t2);
+    V3 w = v3((a * t1.x + b * t2.x) + z * n.x, (a * t1.y + b * t2.y) + z * n.y, (a * t1.z + b * t2.z) + z * n.z);
+    return vnorm(w);
+}
+
+__device__ __forceinline__ V3 reflect(V3 d, V3 n) {
+    float c = 2.0f * vdot(d, n);
+    return v3(d.x - c * n.x, d.y - c * n.y, d.z - c * n.z);
+}
+
+// Smooth dielectric: unpolarised Fresnel reflectance picks reflection or
+// refraction with one draw (also drawn under total internal reflection).
+__device__ __forceinline__ V3 glass_dir(V3 d, V3 n, float ior, Rng &g) {
+    float cosi = -vdot(d, n);
+    float eta, ci;
+    V3 nn;
+    if (cosi > 0.0f) {
+        eta = 1.0f / ior;
+        nn = n;
+        ci = cosi;
+    } else {
+        eta = ior;
+        nn = vneg(n);
+        ci = -cosi;
+    }
+    float sin2t = (eta * eta) * (1.0f - ci * ci);
+    float k = 1.0f - sin2t;
+    float F = 1.0f, ct = 0.0f;
+    if (k >= 0.0f) {
+        ct = sqrtf(k);
+        float rs = (eta * ci - ct) / (eta * ci + ct);
+        float rp = (ci - eta * ct) / (ci + eta * ct);
+        F = 0.5f * (rs * rs + rp * rp);
+    }
+    float u = rng_next(g);
+    if (u < F) return reflect(d, n);
+    float c = eta * ci - ct;
+    return vnorm(v3(eta * d.x + c * nn.x, eta * d.y + c * nn.y, eta * d.z + c * nn.z));
+}
+
+constexpr float kInvPiF = 0.318309886183790671538f;
+constexpr double kPiD = 3.14159265358979323846;
+
+// XCD-aware block order: hardware hands consecutive workgroups to the 8 XCDs
+// round robin; remap so each XCD (and its L2) owns a contiguous range.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblk) {
+    uint32_t per = nblk >> 3, rem = nblk & 7u;
+    uint32_t x = bid & 7u, k = bid >> 3;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+}  // namespace pmd

@@ -1,0 +1,50 @@
+// Host runtime shared by the C ABI and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bvh_build.h"
+#include "pm.h"
+
+namespace pm {
+
+void set_error(const std::string &msg);
+void clear_error();
+const char *last_error();
+
+// Record a HIP failure and return PM_ERR_HIP.
+int hip_fail(hipError_t e, const char *what);
+
+#define PM_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return pm::hip_fail(e_, #call); \
+    } while (0)
+
+}  // namespace pm
+
+struct pm_bvh {
+    int64_t n_tri = 0, n_nodes = 0, n_leaves = 0;
+    int32_t depth = 0, max_leaf = 0;
+    double sah_cost = 0.0, build_ms = 0.0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    float4 *d_nodes = nullptr;  // [6][n_nodes][2]
+    float4 *d_tris = nullptr;   // [n_tri][3]
+    int device = 0;
+    std::vector<int32_t> pos_of;  // original triangle index -> position in d_tris
+};
+
+namespace pm {
+
+// Upload a host-built BVH; fills b (device buffers owned by b).
+int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b);
+void free_bvh(pm_bvh *b);
+
+// Launch the closest-hit kernel.  link_set < 0 selects by direction.
+int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
+                 uint32_t *counters, hipStream_t s);
+
+}  // namespace pm

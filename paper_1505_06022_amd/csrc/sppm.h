@@ -1,0 +1,17 @@
+// Host driver of the SPPM iteration (implemented in sppm.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pm.h"
+
+namespace pm {
+
+int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p);
+int sppm_create(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t st, pm_sppm **out);
+int sppm_destroy(pm_sppm *s);
+int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st);
+int sppm_resolve(pm_sppm *s, float *image, hipStream_t st);
+int sppm_status(pm_sppm *s, hipStream_t st);
+int sppm_views(pm_sppm *s, pm_sppm_views *v);
+
+}  // namespace pm

@@ -1,0 +1,195 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol,
+validates arguments on the host, and its host-built multiple-threaded BVH has
+the structure the traversal relies on (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1505_06022_amd import api, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "pm.h")).read()
+    return sorted(set(re.findall(r"PM_API\s+[\w\s\*]*?\b(pm_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = api.lib()
+    decl = _declared_symbols()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(api.EXPORTS) == decl
+    assert api.abi_version() == 1
+
+
+def test_host_validation_errors_without_gpu():
+    L = api.lib()
+    v = np.zeros((1, 3, 3), np.float32)
+    nn = C.c_int64()
+    assert L.pm_build_bvh_host(None, None, 1, None, C.byref(nn), None, None, None) == api.PM_ERR_ARG
+    assert L.pm_build_bvh_host(v.ctypes.data, None, 0, None, C.byref(nn), None, None, None) == api.PM_ERR_ARG
+    bad = v.copy()
+    bad[0, 1, 2] = np.nan
+    assert L.pm_build_bvh_host(bad.ctypes.data, None, 1, None, C.byref(nn), None, None, None) == api.PM_ERR_ARG
+    assert b"non-finite" in L.pm_last_error()
+    o = api.BvhOpts(C.sizeof(api.BvhOpts), 32, 9, 0)
+    assert L.pm_build_bvh_host(v.ctypes.data, None, 1, C.byref(o), C.byref(nn), None, None, None) == api.PM_ERR_ARG
+    assert L.pm_trace_rays(None, None, 0, None, None, None) == api.PM_ERR_ARG
+    # scene/param validation happens before any device work
+    sc = scenes.box_scene(8, 8)
+    args = api._SceneArgs(sc)
+    p = api.sppm_params(0)
+    out = C.c_void_p()
+    assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+    p = api.sppm_params(1024, alpha=1.5)
+    assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+    assert b"alpha" in L.pm_last_error()
+    sc.tri_mat[3] = 99
+    args = api._SceneArgs(sc)
+    p = api.sppm_params(1024)
+    assert L.pm_render(C.byref(args.desc), C.byref(p), 1, C.c_void_p(1), None) == api.PM_ERR_ARG
+    assert L.pm_sppm_iterate(None, 1, None) == api.PM_ERR_ARG
+    assert L.pm_sppm_resolve(None, None, None) == api.PM_ERR_ARG
+
+
+def _f(words):
+    return words.view(np.float32)
+
+
+def _check_structure(verts, nodes, tris, max_leaf):
+    T = len(verts)
+    S, n, _ = nodes.shape
+    assert S == 6
+    # triangles: every original index exactly once, edges = fl32(v - v0)
+    ids = tris[:, 9].astype(np.int64)
+    assert np.array_equal(np.sort(ids), np.arange(T))
+    tf = _f(tris)
+    v = verts[ids]
+    assert np.array_equal(tf[:, 0:3], v[:, 0])
+    assert np.array_equal(tf[:, 3:6], (v[:, 1] - v[:, 0]).astype(np.float32))
+    assert np.array_equal(tf[:, 6:9], (v[:, 2] - v[:, 0]).astype(np.float32))
+    for s in range(6):
+        nd = nodes[s]
+        lo, hi = _f(nd[:, 0:3]), _f(nd[:, 3:6])
+        skip, leaf = nd[:, 6].astype(np.int64), nd[:, 7]
+        assert skip[0] == n                              # root's miss link ends the walk
+        assert np.all(skip > np.arange(n)) and np.all(skip <= n)
+        cnt = leaf & 7
+        first = leaf >> 3
+        is_leaf = leaf != 0
+        assert np.all(cnt[is_leaf] >= 1) and np.all(cnt[is_leaf] <= max_leaf)
+        assert np.all(skip[is_leaf] == np.arange(n)[is_leaf] + 1)   # a leaf spans one preorder slot
+        # every triangle in exactly one leaf
+        cover = np.zeros(T, np.int64)
+        for i in np.nonzero(is_leaf)[0]:
+            cover[first[i]:first[i] + cnt[i]] += 1
+            tv = verts[ids[first[i]:first[i] + cnt[i]]].reshape(-1, 3)
+            assert np.all(tv >= lo[i]) and np.all(tv <= hi[i])
+        assert np.all(cover == 1)
+        # inner nodes: children are i+1 and skip[i+1]; their boxes nest
+        for i in np.nonzero(~is_leaf)[0]:
+            a = i + 1
+            b = skip[a]
+            assert skip[b] == skip[i]
+            for c in (a, b):
+                assert np.all(lo[c] >= lo[i]) and np.all(hi[c] <= hi[i])
+            # children pre-sorted along the set's direction
+            axis, neg = s // 2, s % 2
+            ka = lo[a][axis] + hi[a][axis]
+            kb = lo[b][axis] + hi[b][axis]
+            assert (ka >= kb) if neg else (ka <= kb)
+    return True
+
+
+def _py_traverse(nodes, tris, ray, s):
+    """Stackless walk of one link set (hit link = next node, miss = skip)."""
+    lo, hi = _f(nodes[s][:, 0:3]).astype(np.float64), _f(nodes[s][:, 3:6]).astype(np.float64)
+    skip, leaf = nodes[s][:, 6], nodes[s][:, 7]
+    o, d = ray[0:3].astype(np.float64), ray[4:7].astype(np.float64)
+    tmin, tmax = float(ray[3]), float(ray[7])
+    tf = _f(tris)
+    best, tb = -1, tmax
+    i, n = 0, nodes.shape[1]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / d
+    while i < n:
+        t0 = (lo[i] - o) * inv
+        t1 = (hi[i] - o) * inv
+        tn = np.nanmax(np.concatenate([np.minimum(t0, t1), [tmin]]))
+        tf_ = np.nanmin(np.concatenate([np.maximum(t0, t1), [tb]]))
+        if tn <= tf_ * (1 + 1e-6) + 1e-12:
+            if leaf[i]:
+                for k in range(leaf[i] >> 3, (leaf[i] >> 3) + (leaf[i] & 7)):
+                    t = _mt32(ray, tf[k])
+                    idx = int(tris[k, 9])
+                    if t is not None and t > tmin and (t < tb or (t == tb and best >= 0 and idx < best)):
+                        tb, best = t, idx
+                i = skip[i]
+            else:
+                i += 1
+        else:
+            i = skip[i]
+    return best, tb
+
+
+def _mt32(ray, tri):
+    f = np.float32
+    o, d = ray[0:3], ray[4:7]
+    v0, e1, e2 = tri[0:3], tri[3:6], tri[6:9]
+
+    def cross(a, b):
+        return np.array([f(a[1] * b[2]) - f(a[2] * b[1]), f(a[2] * b[0]) - f(a[0] * b[2]),
+                         f(a[0] * b[1]) - f(a[1] * b[0])], np.float32)
+
+    def dot(a, b):
+        return f(f(f(a[0] * b[0]) + f(a[1] * b[1])) + f(a[2] * b[2]))
+    p = cross(d, e2)
+    det = dot(e1, p)
+    if det == 0:
+        return None
+    inv = f(f(1) / det)
+    s = (o - v0).astype(np.float32)
+    u = f(dot(s, p) * inv)
+    if u < 0 or u > 1:
+        return None
+    q = cross(s, e1)
+    v = f(dot(d, q) * inv)
+    if v < 0 or f(u + v) > 1:
+        return None
+    return float(f(dot(e2, q) * inv))
+
+
+@pytest.mark.parametrize("seed,n", [(0, 1), (1, 5), (2, 33), (3, 64), (4, 300)])
+def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, seed, n):
+    sc = scenes.small_soup(n, seed, spread=0.4 / max(1.0, np.cbrt(n)))
+    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
+    assert _check_structure(sc.verts, nodes, tris, 4)
+    assert info["n_nodes"] == nodes.shape[1] and info["n_tri"] == n
+    rays = scenes.random_rays(60, seed)
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+    for s in range(6):
+        for r in range(len(rays)):
+            h, t = _py_traverse(nodes, tris, rays[r], s)
+            assert h == h_ref[r], (s, r)
+            if h >= 0:
+                assert np.float32(t) == t_ref[r]
+
+
+def test_host_bvh_box_scene_and_soup_statistics():
+    sc = scenes.box_scene()
+    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
+    _check_structure(sc.verts, nodes, tris, 4)
+    assert np.array_equal(tris[:, 10], sc.tri_mat[tris[:, 9]])
+    sc = scenes.soup_scene(1 << 14, seed=9)
+    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8)
+    _check_structure(sc.verts, nodes, tris, 2)
+    # SAH tree: cheaper than the worst case of one leaf per 2 triangles in a chain
+    assert info["depth"] < 64 and info["sah_cost"] > 0
+    # storage: 6 link sets x 32 B per node + 48 B per triangle
+    assert info["device_bytes"] == 6 * 32 * info["n_nodes"] + 48 * info["n_tri"]
