@@ -22,6 +22,29 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRACE_SOURCES = ["paper_1505_06022_amd/csrc/pm_device.h", "paper_1505_06022_amd/csrc/trace.hip",
+                 "paper_1505_06022_amd/csrc/bvh_build.cpp"]
+
+
+def measured_traffic():
+    """HBM bytes per traversal launch from the committed counter record, or None
+    when the traversal sources changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(os.path.join(ROOT, "profiles", "k_trace_pmc_soup1M.md")) as fh:
+            line = next(ln for ln in fh if ln.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    if rec["sources_sha256_16"] != h.hexdigest()[:16]:
+        return None
+    n = len(rec["fetch_kib"])
+    return 1024.0 * (rec["fetch_factor"] * sum(rec["fetch_kib"]) + rec["write_factor"] * sum(rec["write_kib"])) / n
 
 
 def _parse():
@@ -32,6 +55,9 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sppm", action="store_true")
     ap.add_argument("--sppm-iters", type=int, default=4)
+    ap.add_argument("--no-variants", action="store_true", help="skip the comparison of traversal kernels")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -63,7 +89,8 @@ def traversal_bench(args, torch, api, scenes):
         c = cnt.to(torch.float64).sum(0).cpu().numpy()
         per_batch.append((c[0], c[1], len(r)))
     torch.cuda.synchronize()
-    alg_bytes = sum(40.0 * n + 32.0 * vn + 48.0 * vt for vn, vt, n in per_batch)
+    # per ray: 32 B ray + 8 B result + 16 B per node visited + 48 B per triangle tested
+    alg_bytes = sum(40.0 * n + 16.0 * vn + 48.0 * vt for vn, vt, n in per_batch)
 
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -82,13 +109,31 @@ def traversal_bench(args, torch, api, scenes):
     kern_ms = [[ev[s][2 * b].elapsed_time(ev[s][2 * b + 1]) for b in range(len(batches))] for s in range(args.steps)]
     kern_ms = np.asarray(kern_ms)
     step_ms = wall * 1e3 / args.steps
+    # the other traversal kernels, for comparison (not part of the timed steps)
+    variants = {}
+    for name, kw in () if args.no_variants else (("per_ray", dict(kernel=1)), ("persistent_refill8", dict(kernel=2, refill=8)),
+                     ("persistent_refill16", dict(kernel=2, refill=16)),
+                     ("persistent_refill32", dict(kernel=2, refill=32))):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
+        ms = np.zeros(len(batches))
+        for rep in range(4):
+            for b, (r, (h, t)) in enumerate(zip(batches, outs)):
+                e[2 * b].record(stream)
+                api.trace_rays(bvh, r, h, t, **kw)
+                e[2 * b + 1].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                ms += [e[2 * b].elapsed_time(e[2 * b + 1]) for b in range(len(batches))]
+        ms /= 3
+        variants[name] = {"coherent_mrays_s": round(len(rc) / ms[0] / 1e3, 1),
+                          "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1)}
     avg_launch_ms = kern_ms.mean()
     per_launch_bytes = alg_bytes / len(batches)
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     hit_frac = float((outs[0][0] >= 0).float().mean().item())
     return dict(
         n_rays=n_rays, step_ms=step_ms, kern_ms=kern_ms, info=info, per_batch=per_batch,
-        achieved=achieved, per_launch_bytes=per_launch_bytes, hit_frac=hit_frac,
+        achieved=achieved, per_launch_bytes=per_launch_bytes, hit_frac=hit_frac, variants=variants,
         coherent_mrays=len(rc) / (kern_ms[:, 0].mean() * 1e-3) / 1e6,
         incoherent_mrays=len(ri) / (kern_ms[:, 1].mean() * 1e-3) / 1e6,
         scene=sc, rays=(coh, inc),
@@ -150,10 +195,17 @@ def main():
     import torch
     from paper_1505_06022_amd import api, scenes
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tb = traversal_bench(args, torch, api, scenes)
     out = {
         "metric": "Mrays/s traversal (closest hit, MTBVH)",
-        "value": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6, 2),
+        "value": round(tb["n_rays"] / (tb["step_ms"] * 1e-3) / 1e6, 2),
         "unit": "Mrays/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -169,12 +221,13 @@ def main():
                    "n_rays": tb["n_rays"], "n_tri": 1 << 20, "parallelism": "none"},
         "coherent_mrays_s": round(tb["coherent_mrays"], 2),
         "incoherent_mrays_s": round(tb["incoherent_mrays"], 2),
-        "wall_mrays_s": round(tb["n_rays"] / (tb["step_ms"] * 1e-3) / 1e6, 2),
+        "kernel_mrays_s": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6, 2),
         "bvh": {k: tb["info"][k] for k in ("n_nodes", "n_leaves", "depth", "sah_cost", "device_bytes", "build_ms")},
+        "kernel_variants": tb["variants"],
         "traversal_stats": [{"rays": int(n), "boxes_per_ray": round(vn / n, 2), "tris_per_ray": round(vt / n, 2)}
                             for vn, vt, n in tb["per_batch"]],
         "roofline": {"bound": "hbm", "achieved": round(tb["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(tb["achieved"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(tb["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_trace", "bytes_per_launch": tb["per_launch_bytes"],
                      "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4)},
     }

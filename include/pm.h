@@ -81,8 +81,10 @@ typedef struct {
     int32_t depth;
     int32_t max_leaf;
     double sah_cost;      /* C_trav = C_isect = 1, normalised by the root area */
-    int64_t device_bytes; /* nodes (6 link sets x 32 B) + triangles (48 B) */
+    int64_t device_bytes; /* nodes (6 link sets x 16 B) + triangles (48 B) */
     double build_ms;      /* host build + threading time */
+    float grid_lo[3];     /* node boxes: coordinate = grid_lo + q * grid_step */
+    float grid_step[3];
 } pm_bvh_info;
 
 /* Build the BVH on the host (top-down binned SAH, Sec. 3.1 "standard top-down
@@ -100,10 +102,13 @@ PM_API int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t
 
 /* Host-only build (no device needed), for inspection and tests.  Two-phase:
  * call with nodes == tris == NULL to learn *n_nodes; then call again with
- *   nodes  host, [6][n_nodes][8] 32-bit words per link set s, node i in that
- *          set's preorder: lo.xyz, hi.xyz (float bits), skip (int32: preorder
- *          index after this subtree, n_nodes at the end), leaf word (uint32:
- *          0 for an inner node, else first_tri << 3 | count)
+ *   nodes  host, [6][n_nodes][4] 32-bit words per link set s (0:+x 1:-x 2:+y
+ *          3:-y 4:+z 5:-z), node i in that set's preorder: its padded box
+ *          rounded outward to 16-bit grid coordinates (lo.x | lo.y << 16,
+ *          lo.z | hi.x << 16, hi.y | hi.z << 16; see info->grid_*), then the
+ *          link word: an inner node stores its skip link (preorder index after
+ *          its subtree, n_nodes at the end; its hit link is i + 1); a leaf has
+ *          bit 31 set and first_tri << 3 | count (both of its links are i + 1)
  *   tris   host, [n_tri][12] 32-bit words in leaf order: v0.xyz, e1.xyz,
  *          e2.xyz (float bits), original index, material, 0. */
 PM_API int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
@@ -118,14 +123,23 @@ PM_API int pm_bvh_get_info(const pm_bvh *bvh, pm_bvh_info *info);
  *         tmin < t < tmax (ties in t go to the lower index), or -1
  *   t     device, float32 [n]: its distance along d, +inf on a miss
  * The result is independent of which link set is traversed.
- * Errors: PM_ERR_ARG for n < 0 or NULL pointers with n > 0. */
+ * Concurrent calls on one BVH must be on the same stream (a per-BVH work
+ * counter is reset by each call).
+ * Errors: PM_ERR_ARG for n < 0, n >= 2^31 or NULL pointers with n > 0. */
 PM_API int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t, void *stream);
+
+/* Traversal kernels: one ray per lane for the whole walk, or persistent
+ * wavefronts whose finished lanes take new rays from a work counter. */
+enum { PM_TRACE_AUTO = 0, PM_TRACE_PER_RAY = 1, PM_TRACE_PERSISTENT = 2 };
 
 typedef struct {
     uint32_t size;      /* sizeof(pm_trace_opts) */
     int32_t link_set;   /* -1: pick by ray direction (MTBVH); 0..5: force one
                            link set for every ray (single threaded BVH) */
     uint32_t *counters; /* optional device [n][2]: AABB tests, triangle tests */
+    int32_t kernel;     /* PM_TRACE_* */
+    int32_t refill;     /* persistent kernel: idle lanes that trigger a refill
+                           (1..64; 0 = default 16) */
 } pm_trace_opts;
 
 /* pm_trace_rays with options (ablation of the link-set choice; per-ray

@@ -36,11 +36,16 @@ class BvhOpts(C.Structure):
 class BvhInfo(C.Structure):
     _fields_ = [("size", C.c_uint32), ("n_tri", C.c_int64), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64),
                 ("depth", C.c_int32), ("max_leaf", C.c_int32), ("sah_cost", C.c_double),
-                ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
+                ("device_bytes", C.c_int64), ("build_ms", C.c_double),
+                ("grid_lo", C.c_float * 3), ("grid_step", C.c_float * 3)]
 
 
 class TraceOpts(C.Structure):
-    _fields_ = [("size", C.c_uint32), ("link_set", C.c_int32), ("counters", C.c_void_p)]
+    _fields_ = [("size", C.c_uint32), ("link_set", C.c_int32), ("counters", C.c_void_p), ("kernel", C.c_int32),
+                ("refill", C.c_int32)]
+
+
+TRACE_AUTO, TRACE_PER_RAY, TRACE_PERSISTENT = 0, 1, 2
 
 
 class SceneDesc(C.Structure):
@@ -120,6 +125,16 @@ def _opts(bins, max_leaf, n_threads):
     return o
 
 
+def _info_dict(inf) -> dict:
+    d = {}
+    for k, _ in BvhInfo._fields_:
+        if k == "size":
+            continue
+        v = getattr(inf, k)
+        d[k] = list(v) if k.startswith("grid_") else v
+    return d
+
+
 def abi_version() -> int:
     return lib().pm_abi_version()
 
@@ -138,7 +153,7 @@ class Bvh:
         inf = BvhInfo()
         inf.size = C.sizeof(BvhInfo)
         _check(lib().pm_bvh_get_info(self.h, C.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in BvhInfo._fields_ if k != "size"}
+        return _info_dict(inf)
 
     def destroy(self):
         if self.h:
@@ -164,7 +179,7 @@ def build_bvh(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max
 
 
 def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0):
-    """Host-only build: returns (nodes uint32 [6, n_nodes, 8], tris uint32 [T, 12], info dict)."""
+    """Host-only build: returns (nodes uint32 [6, n_nodes, 4], tris uint32 [T, 12], info dict)."""
     v = np.ascontiguousarray(verts, np.float32)
     m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
     o = _opts(bins, max_leaf, n_threads)
@@ -172,16 +187,17 @@ def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32
     L = lib()
     _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
                                None, None, None))
-    nodes = np.zeros((6, nn.value, 8), np.uint32)
+    nodes = np.zeros((6, nn.value, 4), np.uint32)
     tris = np.zeros((v.shape[0], 12), np.uint32)
     inf = BvhInfo()
     inf.size = C.sizeof(BvhInfo)
     _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
                                _ptr(nodes), _ptr(tris), C.byref(inf)))
-    return nodes, tris, {k: getattr(inf, k) for k, _ in BvhInfo._fields_ if k != "size"}
+    return nodes, tris, _info_dict(inf)
 
 
-def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=None, stream=None):
+def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=None, kernel: int = 0, refill: int = 0,
+               stream=None):
     """Closest hit of each ray.  rays: float32 cuda tensor [n, 8]; returns (hit int32 [n], t float32 [n])."""
     import torch
     assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
@@ -190,11 +206,11 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
         hit = torch.empty(n, dtype=torch.int32, device=rays.device)
     if t is None:
         t = torch.empty(n, dtype=torch.float32, device=rays.device)
-    if link_set == -1 and counters is None:
+    if link_set == -1 and counters is None and kernel == 0 and refill == 0:
         _check(lib().pm_trace_rays(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), _stream(stream)))
     else:
         o = TraceOpts()
-        o.size, o.link_set = C.sizeof(TraceOpts), link_set
+        o.size, o.link_set, o.kernel, o.refill = C.sizeof(TraceOpts), link_set, kernel, refill
         o.counters = None if counters is None else counters.data_ptr()
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t

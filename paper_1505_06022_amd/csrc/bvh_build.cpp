@@ -7,8 +7,8 @@
 //    first along that direction visited first.  Each node stores its skip
 //    ("miss") link; the "hit" link of an inner node is implicitly the next
 //    node of that preorder, so a hit walks forward through memory.
-// 3. Packing into 32-byte nodes (one copy per direction) and 48-byte
-//    triangles in leaf order.
+// 3. Packing into 16-byte nodes (box quantised outward to a 16-bit scene
+//    grid, one copy per direction) and 48-byte triangles in leaf order.
 #include "bvh_build.h"
 
 #include <algorithm>
@@ -243,7 +243,33 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     for (int a = 0; a < 3; ++a) ext = std::max(ext, scene.hi[a] - scene.lo[a]);
     float mag = 0.0f;
     for (int a = 0; a < 3; ++a) mag = std::max(mag, std::max(std::fabs(scene.lo[a]), std::fabs(scene.hi[a])));
-    const float pad = std::max(ext * 0x1p-15f, mag * 0x1p-20f);
+    const double pad = std::max((double)ext * 0x1p-15, (double)mag * 0x1p-20) + 1e-30;
+
+    // 16-bit quantisation grid over the padded scene box: a node's box is
+    // rounded outward to grid lines, so the stored box contains the padded one
+    float qlo[3], qstep[3];
+    for (int a = 0; a < 3; ++a) {
+        double lo = (double)scene.lo[a] - pad, hi = (double)scene.hi[a] + pad;
+        float l = (float)lo;
+        if ((double)l > lo) l = std::nextafter(l, -INFINITY);
+        double st = (hi - (double)l) / 65535.0;
+        float sf = (float)st;
+        while ((double)l + 65535.0 * (double)sf < hi) sf = std::nextafter(sf, INFINITY);
+        qlo[a] = l;
+        qstep[a] = sf;
+    }
+    auto q_down = [&](int a, double x) -> uint32_t {
+        double q = std::floor((x - (double)qlo[a]) / (double)qstep[a]);
+        q = std::min(std::max(q, 0.0), 65535.0);
+        while (q > 0.0 && (double)qlo[a] + q * (double)qstep[a] > x) q -= 1.0;
+        return (uint32_t)q;
+    };
+    auto q_up = [&](int a, double x) -> uint32_t {
+        double q = std::ceil((x - (double)qlo[a]) / (double)qstep[a]);
+        q = std::min(std::max(q, 0.0), 65535.0);
+        while (q < 65535.0 && (double)qlo[a] + q * (double)qstep[a] < x) q += 1.0;
+        return (uint32_t)q;
+    };
 
     out.n_tri = n_tri;
     out.n_nodes = nn;
@@ -254,6 +280,21 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     for (int a = 0; a < 3; ++a) {
         out.lo[a] = scene.lo[a];
         out.hi[a] = scene.hi[a];
+        out.qlo[a] = qlo[a];
+        out.qstep[a] = qstep[a];
+    }
+    // quantised boxes once per node (shared by the six orders)
+    std::vector<uint32_t> qbox((size_t)nn * 3);
+    for (int64_t v = 0; v < nn; ++v) {
+        const Box &bx = tree[v].box;
+        uint32_t lo3[3], hi3[3];
+        for (int a = 0; a < 3; ++a) {
+            lo3[a] = q_down(a, (double)bx.lo[a] - pad);
+            hi3[a] = q_up(a, (double)bx.hi[a] + pad);
+        }
+        qbox[3 * v] = lo3[0] | (lo3[1] << 16);
+        qbox[3 * v + 1] = lo3[2] | (hi3[0] << 16);
+        qbox[3 * v + 2] = hi3[1] | (hi3[2] << 16);
     }
     out.nodes.assign((size_t)kLinkSets * nn * kNodeWords, 0u);
     auto thread_set = [&](int s) {
@@ -269,12 +310,10 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
             stack.pop_back();
             const TNode &t = tree[v];
             uint32_t *w = base + (size_t)pre * kNodeWords;
-            for (int a = 0; a < 3; ++a) {
-                w[a] = fbits(t.box.lo[a] - pad);
-                w[3 + a] = fbits(t.box.hi[a] + pad);
-            }
-            w[6] = (uint32_t)(pre + size[v]);
-            w[7] = t.left < 0 ? ((uint32_t)t.start << 3) | (uint32_t)t.count : 0u;
+            w[0] = qbox[3 * (size_t)v];
+            w[1] = qbox[3 * (size_t)v + 1];
+            w[2] = qbox[3 * (size_t)v + 2];
+            w[3] = t.left < 0 ? (0x80000000u | ((uint32_t)t.start << 3) | (uint32_t)t.count) : (uint32_t)(pre + size[v]);
             pre++;
             if (t.left >= 0) {
                 const Box &L = tree[t.left].box, &R = tree[t.right].box;

@@ -13,13 +13,16 @@ struct BuildOptions {
 };
 
 // Device layout (words are 32-bit):
-//   nodes: 6 link sets x n_nodes x 8 words.  Set s lists the nodes in the
+//   nodes: 6 link sets x n_nodes x 4 words.  Set s lists the nodes in the
 //          preorder whose children are visited along direction s
-//          (0:+x 1:-x 2:+y 3:-y 4:+z 5:-z).  Node = lo.xyz, hi.xyz (padded
-//          AABB), skip (preorder index after the subtree = the "miss" link;
-//          n_nodes terminates), leaf word (0 inner; first_tri << 3 | count).
-//          The "hit" link of an inner node is the next node (i + 1); a leaf's
-//          hit link equals its miss link.
+//          (0:+x 1:-x 2:+y 3:-y 4:+z 5:-z).  Node = padded AABB quantised
+//          outward to a 16-bit grid over the scene (lo.x|lo.y<<16,
+//          lo.z|hi.x<<16, hi.y|hi.z<<16; coordinate = qlo + q * qstep) and a
+//          link word: inner node -> skip (preorder index after its subtree,
+//          the "miss" link; n_nodes terminates); leaf -> bit 31 set,
+//          first_tri << 3 | count.  The "hit" link of an inner node is the
+//          next node (i + 1); a leaf occupies one slot, so both of its links
+//          are i + 1.
 //   tris:  n_tri x 12 words in leaf order: v0.xyz, e1 = v1-v0, e2 = v2-v0,
 //          original triangle index, material id, 0.
 struct HostBvh {
@@ -27,11 +30,12 @@ struct HostBvh {
     int32_t depth = 0, max_leaf = 0;
     double sah_cost = 0.0, build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // scene bounds (unpadded)
+    float qlo[3] = {0, 0, 0}, qstep[3] = {1, 1, 1};  // node quantisation grid
     std::vector<uint32_t> nodes;
     std::vector<uint32_t> tris;
 };
 
-constexpr int kNodeWords = 8;
+constexpr int kNodeWords = 4;
 constexpr int kTriWords = 12;
 constexpr int kLinkSets = 6;
 

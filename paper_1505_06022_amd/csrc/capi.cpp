@@ -80,6 +80,10 @@ int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n
             info->sah_cost = hb.sah_cost;
             info->device_bytes = (int64_t)(hb.nodes.size() + hb.tris.size()) * 4;
             info->build_ms = hb.build_ms;
+            for (int a = 0; a < 3; ++a) {
+                info->grid_lo[a] = hb.qlo[a];
+                info->grid_step[a] = hb.qstep[a];
+            }
         }
         return PM_OK;
     })
@@ -125,8 +129,12 @@ int pm_bvh_get_info(const pm_bvh *b, pm_bvh_info *info) {
         info->depth = b->depth;
         info->max_leaf = b->max_leaf;
         info->sah_cost = b->sah_cost;
-        info->device_bytes = b->n_nodes * 6 * 32 + b->n_tri * 48;
+        info->device_bytes = b->n_nodes * 6 * 16 + b->n_tri * 48;
         info->build_ms = b->build_ms;
+        for (int a = 0; a < 3; ++a) {
+            info->grid_lo[a] = b->qlo[a];
+            info->grid_step[a] = b->qstep[a];
+        }
         return PM_OK;
     })
 }
@@ -137,15 +145,20 @@ int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *h
         if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
         if (n < 0) return pm::set_error("n must be >= 0"), PM_ERR_ARG;
         if (n > 0 && (!rays || !hit || !t)) return pm::set_error("NULL ray or output pointer"), PM_ERR_ARG;
-        int set = -1;
+        int set = -1, kernel = PM_TRACE_AUTO, refill = 0;
         uint32_t *counters = nullptr;
         if (opts) {
             if (opts->size < sizeof(pm_trace_opts)) return pm::set_error("pm_trace_opts.size too small"), PM_ERR_ARG;
             if (opts->link_set < -1 || opts->link_set > 5) return pm::set_error("link_set must be in [-1,5]"), PM_ERR_ARG;
+            if (opts->kernel < 0 || opts->kernel > 2) return pm::set_error("unknown traversal kernel"), PM_ERR_ARG;
+            if (opts->refill < 0 || opts->refill > 64) return pm::set_error("refill must be in [0,64]"), PM_ERR_ARG;
             set = opts->link_set;
             counters = opts->counters;
+            kernel = opts->kernel;
+            refill = opts->refill;
         }
-        return pm::launch_trace(bvh, rays, n, hit, t, set, counters, (hipStream_t)stream);
+        if (n >= (int64_t(1) << 31)) return pm::set_error("n must be below 2^31"), PM_ERR_ARG;
+        return pm::launch_trace(bvh, rays, n, hit, t, set, counters, kernel, refill, (hipStream_t)stream);
     })
 }
 

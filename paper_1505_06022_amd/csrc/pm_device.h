@@ -162,9 +162,10 @@ __device__ __forceinline__ int link_set(V3 d) {
 }
 
 struct Bvh {
-    const float4 *nodes;  // [6][n_nodes][2] float4
+    const uint4 *nodes;   // [6][n_nodes] 16-byte nodes
     const float4 *tris;   // [n_tri][3] float4
     uint32_t n_nodes;
+    float qlo[3], qstep[3];  // node box grid: coordinate = qlo + q * qstep
 };
 
 struct TraceStats {
@@ -176,60 +177,99 @@ struct TraceStats {
 // miss (skip) link; at a leaf test its triangles and continue with the miss
 // link.  The box test is conservative (boxes are padded at build time and the
 // interval is closed at tbest) so the result equals the brute-force closest
-// hit.
+// hit.  Walker holds one lane's traversal state so that a persistent kernel
+// can interleave node steps of different rays.
+struct Walker {
+    const uint4 *nodes;
+    uint32_t n, i;
+    V3 o, d;
+    float sx, sy, sz, bx, by, bz;  // slab planes: t = q * s + b per axis
+    float tmin, tbest;
+    int32_t best, exclude;
+    uint32_t best_k;
+
+    __device__ __forceinline__ void init(const Bvh &bvh, int set, V3 o_, V3 d_, float tmin_, float tmax_,
+                                         int32_t exclude_) {
+        nodes = bvh.nodes + (size_t)set * bvh.n_nodes;
+        n = bvh.n_nodes;
+        i = 0;
+        o = o_;
+        d = d_;
+        // reciprocal direction; zero components replaced by a tiny signed value
+        float dx = fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x);
+        float dy = fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y);
+        float dz = fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z);
+        float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
+        sx = bvh.qstep[0] * ix;
+        sy = bvh.qstep[1] * iy;
+        sz = bvh.qstep[2] * iz;
+        bx = (bvh.qlo[0] - o.x) * ix;
+        by = (bvh.qlo[1] - o.y) * iy;
+        bz = (bvh.qlo[2] - o.z) * iz;
+        tmin = tmin_;
+        tbest = tmax_;
+        best = -1;
+        best_k = 0;
+        exclude = exclude_;
+    }
+
+    __device__ __forceinline__ bool done() const { return i >= n; }
+
+    // One node visit (and, at a leaf, its triangles).  Requires !done().
+    // Next node: i + 1 after an inner-node hit or any leaf, else the skip link.
+    template <bool kStats>
+    __device__ __forceinline__ void step(const float4 *__restrict__ tris, TraceStats &st) {
+        uint4 q = nodes[i];
+        float tx0 = fmaf((float)(q.x & 0xffffu), sx, bx), tx1 = fmaf((float)(q.y >> 16), sx, bx);
+        float ty0 = fmaf((float)(q.x >> 16), sy, by), ty1 = fmaf((float)(q.z & 0xffffu), sy, by);
+        float tz0 = fmaf((float)(q.y & 0xffffu), sz, bz), tz1 = fmaf((float)(q.z >> 16), sz, bz);
+        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tbest));
+        const bool leaf = (q.w >> 31) != 0u;
+        const bool hit = tn <= tf;
+        if (kStats) st.boxes++;
+        if (hit && leaf) {
+            uint32_t first = (q.w >> 3) & 0x0fffffffu, cnt = q.w & 7u;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                Tri tr = load_tri(tris, first + k);
+                if (kStats) st.tris++;
+                if (tr.id == exclude) continue;
+                float t;
+                if (mt_hit(o, d, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
+                    tbest = t;
+                    best = tr.id;
+                    best_k = first + k;
+                }
+            }
+        }
+        i = (hit || leaf) ? i + 1 : q.w;
+    }
+
+    __device__ __forceinline__ float t_hit() const { return best >= 0 ? tbest : __builtin_inff(); }
+};
+
 // Returns the original index of the closest triangle (-1: none); t_out gets
 // its distance (+inf on a miss) and k_out its position in the triangle array.
 template <bool kStats>
 __device__ __forceinline__ int32_t closest_hit(const Bvh &bvh, int set, V3 o, V3 d, float tmin, float tmax,
                                                int32_t exclude, float &t_out, uint32_t &k_out, TraceStats &st) {
-    const float4 *__restrict__ nodes = bvh.nodes + (size_t)set * bvh.n_nodes * 2;
-    // reciprocal direction; zero components replaced by a tiny signed value
-    float dx = fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x);
-    float dy = fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y);
-    float dz = fabsf(d.z) > 1e-30f ? d.z : copysignf(1e-30f, d.z);
-    float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
-    float ox = -o.x * ix, oy = -o.y * iy, oz = -o.z * iz;
-    int32_t best = -1;
-    uint32_t best_k = 0;
-    float tbest = tmax;
-    uint32_t i = 0;
-    const uint32_t n = bvh.n_nodes;
-    while (i < n) {
-        float4 a = nodes[2 * i];
-        float4 b = nodes[2 * i + 1];
-        float tx0 = fmaf(a.x, ix, ox), tx1 = fmaf(a.w, ix, ox);
-        float ty0 = fmaf(a.y, iy, oy), ty1 = fmaf(b.x, iy, oy);
-        float tz0 = fmaf(a.z, iz, oz), tz1 = fmaf(b.y, iz, oz);
-        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tbest));
-        uint32_t skip = __float_as_uint(b.z);
-        uint32_t leaf = __float_as_uint(b.w);
-        if (kStats) st.boxes++;
-        if (tn <= tf) {
-            if (leaf) {
-                uint32_t first = leaf >> 3, cnt = leaf & 7u;
-                for (uint32_t k = 0; k < cnt; ++k) {
-                    Tri tr = load_tri(bvh.tris, first + k);
-                    if (kStats) st.tris++;
-                    if (tr.id == exclude) continue;
-                    float t;
-                    if (mt_hit(o, d, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
-                        tbest = t;
-                        best = tr.id;
-                        best_k = first + k;
-                    }
-                }
-                i = skip;
-            } else {
-                i = i + 1;
-            }
-        } else {
-            i = skip;
-        }
-    }
-    t_out = best >= 0 ? tbest : __builtin_inff();
-    k_out = best_k;
-    return best;
+    Walker w;
+    w.init(bvh, set, o, d, tmin, tmax, exclude);
+    while (!w.done()) w.step<kStats>(bvh.tris, st);
+    t_out = w.t_hit();
+    k_out = w.best_k;
+    return w.best;
+}
+
+// Wave-aggregated counter increment for the lanes in `mask` (uniform across
+// the wave): returns base + rank of this lane within mask.
+__device__ __forceinline__ uint32_t wave_fetch_add(uint32_t *counter, uint64_t mask, bool member) {
+    uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (member && rank == 0) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    return base + rank;
 }
 
 // ---------------------------------------------------------------------------

@@ -31,13 +31,22 @@ struct pm_bvh {
     int32_t depth = 0, max_leaf = 0;
     double sah_cost = 0.0, build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    float4 *d_nodes = nullptr;  // [6][n_nodes][2]
+    float qlo[3] = {0, 0, 0}, qstep[3] = {1, 1, 1};
+    uint4 *d_nodes = nullptr;   // [6][n_nodes] 16-byte nodes
     float4 *d_tris = nullptr;   // [n_tri][3]
+    uint32_t *d_next = nullptr; // work counter of the persistent traversal kernel
     int device = 0;
     std::vector<int32_t> pos_of;  // original triangle index -> position in d_tris
 };
 
+namespace pmd {
+struct Bvh;
+}
+
 namespace pm {
+
+// Device view of a BVH handle (node/triangle pointers and the box grid).
+pmd::Bvh make_device_bvh(const pm_bvh *b);
 
 // Upload a host-built BVH; fills b (device buffers owned by b).
 int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b);
@@ -45,6 +54,6 @@ void free_bvh(pm_bvh *b);
 
 // Launch the closest-hit kernel.  link_set < 0 selects by direction.
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, hipStream_t s);
+                 uint32_t *counters, int kernel, int refill, hipStream_t s);
 
 }  // namespace pm

@@ -624,7 +624,7 @@ int sppm_create(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t st,
     PM_HIP(hipStreamSynchronize(st));
 
     SceneDev &sc = s->sc;
-    sc.bvh = pmd::Bvh{b->d_nodes, b->d_tris, (uint32_t)b->n_nodes};
+    sc.bvh = make_device_bvh(b);
     sc.mat_type = s->mat_type;
     sc.mat_rho = s->mat_f;
     sc.mat_q = s->mat_f + nm;

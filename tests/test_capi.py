@@ -62,7 +62,24 @@ def _f(words):
     return words.view(np.float32)
 
 
-def _check_structure(verts, nodes, tris, max_leaf):
+def _decode(nodes_s, info):
+    """Dequantised boxes (float64), leaf flags, leaf ranges and next-on-miss links."""
+    w = nodes_s.astype(np.int64)
+    q = np.stack([w[:, 0] & 0xffff, w[:, 0] >> 16, w[:, 1] & 0xffff,
+                  w[:, 1] >> 16, w[:, 2] & 0xffff, w[:, 2] >> 16], 1).astype(np.float64)
+    g0 = np.asarray(info["grid_lo"], np.float64)
+    gs = np.asarray(info["grid_step"], np.float64)
+    lo = g0 + q[:, 0:3] * gs
+    hi = g0 + q[:, 3:6] * gs
+    leaf = (w[:, 3] >> 31) != 0
+    first = (w[:, 3] >> 3) & 0x0fffffff
+    cnt = w[:, 3] & 7
+    n = len(w)
+    skip = np.where(leaf, np.arange(n) + 1, w[:, 3])
+    return lo, hi, leaf, first, cnt, skip
+
+
+def _check_structure(verts, nodes, tris, max_leaf, info):
     T = len(verts)
     S, n, _ = nodes.shape
     assert S == 6
@@ -75,22 +92,16 @@ def _check_structure(verts, nodes, tris, max_leaf):
     assert np.array_equal(tf[:, 3:6], (v[:, 1] - v[:, 0]).astype(np.float32))
     assert np.array_equal(tf[:, 6:9], (v[:, 2] - v[:, 0]).astype(np.float32))
     for s in range(6):
-        nd = nodes[s]
-        lo, hi = _f(nd[:, 0:3]), _f(nd[:, 3:6])
-        skip, leaf = nd[:, 6].astype(np.int64), nd[:, 7]
+        lo, hi, is_leaf, first, cnt, skip = _decode(nodes[s], info)
         assert skip[0] == n                              # root's miss link ends the walk
         assert np.all(skip > np.arange(n)) and np.all(skip <= n)
-        cnt = leaf & 7
-        first = leaf >> 3
-        is_leaf = leaf != 0
         assert np.all(cnt[is_leaf] >= 1) and np.all(cnt[is_leaf] <= max_leaf)
-        assert np.all(skip[is_leaf] == np.arange(n)[is_leaf] + 1)   # a leaf spans one preorder slot
-        # every triangle in exactly one leaf
+        # every triangle in exactly one leaf, inside its (padded, quantised) box
         cover = np.zeros(T, np.int64)
         for i in np.nonzero(is_leaf)[0]:
             cover[first[i]:first[i] + cnt[i]] += 1
-            tv = verts[ids[first[i]:first[i] + cnt[i]]].reshape(-1, 3)
-            assert np.all(tv >= lo[i]) and np.all(tv <= hi[i])
+            tv = verts[ids[first[i]:first[i] + cnt[i]]].reshape(-1, 3).astype(np.float64)
+            assert np.all(tv > lo[i]) and np.all(tv < hi[i])
         assert np.all(cover == 1)
         # inner nodes: children are i+1 and skip[i+1]; their boxes nest
         for i in np.nonzero(~is_leaf)[0]:
@@ -99,18 +110,19 @@ def _check_structure(verts, nodes, tris, max_leaf):
             assert skip[b] == skip[i]
             for c in (a, b):
                 assert np.all(lo[c] >= lo[i]) and np.all(hi[c] <= hi[i])
-            # children pre-sorted along the set's direction
+            # children pre-sorted along the set's direction (centres of the
+            # quantised boxes can tie; the order then follows the exact boxes)
             axis, neg = s // 2, s % 2
             ka = lo[a][axis] + hi[a][axis]
             kb = lo[b][axis] + hi[b][axis]
-            assert (ka >= kb) if neg else (ka <= kb)
+            tol = 4 * info["grid_step"][axis]
+            assert (ka >= kb - tol) if neg else (ka <= kb + tol)
     return True
 
 
-def _py_traverse(nodes, tris, ray, s):
+def _py_traverse(nodes, tris, info, ray, s):
     """Stackless walk of one link set (hit link = next node, miss = skip)."""
-    lo, hi = _f(nodes[s][:, 0:3]).astype(np.float64), _f(nodes[s][:, 3:6]).astype(np.float64)
-    skip, leaf = nodes[s][:, 6], nodes[s][:, 7]
+    lo, hi, leaf, first, cnt, skip = _decode(nodes[s], info)
     o, d = ray[0:3].astype(np.float64), ray[4:7].astype(np.float64)
     tmin, tmax = float(ray[3]), float(ray[7])
     tf = _f(tris)
@@ -123,18 +135,14 @@ def _py_traverse(nodes, tris, ray, s):
         t1 = (hi[i] - o) * inv
         tn = np.nanmax(np.concatenate([np.minimum(t0, t1), [tmin]]))
         tf_ = np.nanmin(np.concatenate([np.maximum(t0, t1), [tb]]))
-        if tn <= tf_ * (1 + 1e-6) + 1e-12:
-            if leaf[i]:
-                for k in range(leaf[i] >> 3, (leaf[i] >> 3) + (leaf[i] & 7)):
-                    t = _mt32(ray, tf[k])
-                    idx = int(tris[k, 9])
-                    if t is not None and t > tmin and (t < tb or (t == tb and best >= 0 and idx < best)):
-                        tb, best = t, idx
-                i = skip[i]
-            else:
-                i += 1
-        else:
-            i = skip[i]
+        hit = tn <= tf_ * (1 + 1e-6) + 1e-12
+        if hit and leaf[i]:
+            for k in range(first[i], first[i] + cnt[i]):
+                t = _mt32(ray, tf[k])
+                idx = int(tris[k, 9])
+                if t is not None and t > tmin and (t < tb or (t == tb and best >= 0 and idx < best)):
+                    tb, best = t, idx
+        i = i + 1 if (hit or leaf[i]) else skip[i]
     return best, tb
 
 
@@ -169,13 +177,13 @@ def _mt32(ray, tri):
 def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, seed, n):
     sc = scenes.small_soup(n, seed, spread=0.4 / max(1.0, np.cbrt(n)))
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
-    assert _check_structure(sc.verts, nodes, tris, 4)
+    assert _check_structure(sc.verts, nodes, tris, 4, info)
     assert info["n_nodes"] == nodes.shape[1] and info["n_tri"] == n
     rays = scenes.random_rays(60, seed)
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
     for s in range(6):
         for r in range(len(rays)):
-            h, t = _py_traverse(nodes, tris, rays[r], s)
+            h, t = _py_traverse(nodes, tris, info, rays[r], s)
             assert h == h_ref[r], (s, r)
             if h >= 0:
                 assert np.float32(t) == t_ref[r]
@@ -184,12 +192,12 @@ def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, s
 def test_host_bvh_box_scene_and_soup_statistics():
     sc = scenes.box_scene()
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
-    _check_structure(sc.verts, nodes, tris, 4)
+    _check_structure(sc.verts, nodes, tris, 4, info)
     assert np.array_equal(tris[:, 10], sc.tri_mat[tris[:, 9]])
     sc = scenes.soup_scene(1 << 14, seed=9)
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8)
-    _check_structure(sc.verts, nodes, tris, 2)
+    _check_structure(sc.verts, nodes, tris, 2, info)
     # SAH tree: cheaper than the worst case of one leaf per 2 triangles in a chain
     assert info["depth"] < 64 and info["sah_cost"] > 0
-    # storage: 6 link sets x 32 B per node + 48 B per triangle
-    assert info["device_bytes"] == 6 * 32 * info["n_nodes"] + 48 * info["n_tri"]
+    # storage: 6 link sets x 16 B per node + 48 B per triangle
+    assert info["device_bytes"] == 6 * 16 * info["n_nodes"] + 48 * info["n_tri"]
