@@ -55,6 +55,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sppm", action="store_true")
     ap.add_argument("--sppm-iters", type=int, default=4)
+    ap.add_argument("--adjoint-iters", type=int, default=8)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the comparison of traversal kernels")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -163,6 +165,37 @@ def sppm_bench(args, torch, api, scenes):
                 workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
+def adjoint_bench(args, torch, api, scenes):
+    """Forward K iterations + resolve, then the replay adjoint of an L2 image
+    loss, on the 250k-triangle scene at full size (same K and photon count for
+    both, so the forward image and its RMSE are identical by construction)."""
+    sc = scenes.procedural_scene()
+    v = sc.verts.reshape(-1, 3)
+    diag = float(np.linalg.norm(v.max(0) - v.min(0)))
+    Np, K = 1 << 20, args.adjoint_iters
+    p = api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, record_iterations=K)
+    s = api.Sppm(sc, p)
+    st = torch.cuda.current_stream()
+    target = torch.zeros((720, 1280), dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    s.iterate(K)
+    img = s.resolve()
+    ev[1].record(st)
+    g = 2.0 * (img - target) / img.numel()
+    grad = s.adjoint(g, sc.albedo_params)
+    ev[2].record(st)
+    torch.cuda.synchronize()
+    t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    s.status()
+    s.destroy()
+    return {"fwd_ms": round(t_fwd, 2), "adjoint_ms": round(t_adj, 2),
+            "ratio_fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 3), "iterations": K,
+            "n_params": len(sc.albedo_params) + 1, "grad_finite": bool(torch.isfinite(grad).all().item()),
+            "workload": "procedural 250,094 triangles, 1280x720, 2^20 photons/iteration, L2 loss"}
+
+
 def cpu_baseline(tb, scenes):
     import oracle
     nth = _cpu_threads()
@@ -235,6 +268,8 @@ def main():
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
                        "stored_photons": sp["n_stored"], "workload": sp["workload"]}
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench(args, torch, api, scenes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tb, scenes)
     print(json.dumps(out), flush=True)

@@ -178,6 +178,10 @@ typedef struct {
     int32_t max_photon_bounces; /* photon path length cap (32) */
     int32_t fixed_shift;      /* flux fixed point: value * 2^shift (40) */
     int32_t store_factor;     /* photon store capacity = n_photons * factor (8) */
+    int32_t record_iterations; /* > 0: record what pm_sppm_adjoint needs for
+                                  up to this many iterations (8 B per pixel
+                                  per iteration, plus 9 B x n_photons x
+                                  max_photon_bounces of replay scratch) */
 } pm_sppm_params;
 
 /* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)
@@ -200,6 +204,21 @@ PM_API int pm_sppm_status(pm_sppm *s, void *stream);
 
 /* create -> K x iterate -> resolve -> status -> destroy. */
 PM_API int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream);
+
+/* Gradient of a scalar image loss by replay (the adjoint of the K iterations
+ * run so far; requires params.record_iterations >= K).
+ *   dloss_dimage  device float32 [height][width]: dLoss/dL_p
+ *   param_mats    host int32 [n_par]: materials whose diffuse albedo is a
+ *                 parameter (each with rho > 0; n_par < 256)
+ *   grad          device float64 [n_par + 1]: dLoss/drho for each listed
+ *                 material, then dLoss/dLe of the single emitting material (0
+ *                 when the scene has no or several emitting materials)
+ * Sampling is held fixed (Russian roulette uses the nominal q), so every path,
+ * hit point and radius is replayed from its counter-keyed random stream and
+ * only the flux terms are differentiated.  Asynchronous on `stream`.
+ * Errors: PM_ERR_STATE if nothing was recorded; PM_ERR_ARG for bad ids. */
+PM_API int pm_sppm_adjoint(pm_sppm *s, const float *dloss_dimage, const int32_t *param_mats, int32_t n_par,
+                           double *grad, void *stream);
 
 /* Device buffers of a handle, for inspection (owned by the handle, valid
  * until it is destroyed). */

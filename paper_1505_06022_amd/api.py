@@ -20,7 +20,8 @@ PM_OK, PM_ERR_ARG, PM_ERR_HIP, PM_ERR_OVERFLOW, PM_ERR_STATE, PM_ERR_NOMEM = 0, 
 
 EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host", "pm_bvh_destroy",
            "pm_bvh_get_info", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
-           "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views"]
+           "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
+           "pm_sppm_adjoint"]
 
 
 class PMError(RuntimeError):
@@ -60,7 +61,7 @@ class SceneDesc(C.Structure):
 class SppmParams(C.Structure):
     _fields_ = [("size", C.c_uint32), ("n_photons", C.c_int64), ("alpha", C.c_double), ("r0", C.c_double),
                 ("seed", C.c_uint64), ("max_eye_depth", C.c_int32), ("max_photon_bounces", C.c_int32),
-                ("fixed_shift", C.c_int32), ("store_factor", C.c_int32)]
+                ("fixed_shift", C.c_int32), ("store_factor", C.c_int32), ("record_iterations", C.c_int32)]
 
 
 class SppmViews(C.Structure):
@@ -97,6 +98,7 @@ def lib() -> C.CDLL:
         L.pm_sppm_status.argtypes = [P, P]
         L.pm_render.argtypes = [P, P, I32, P, P]
         L.pm_sppm_get_views.argtypes = [P, P]
+        L.pm_sppm_adjoint.argtypes = [P, P, P, I32, P, P]
         _lib = L
     return _lib
 
@@ -220,12 +222,13 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
 # SPPM
 # ---------------------------------------------------------------------------
 def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, max_photon_bounces=32,
-                fixed_shift=40, store_factor=8) -> SppmParams:
+                fixed_shift=40, store_factor=8, record_iterations=0) -> SppmParams:
     p = SppmParams()
     p.size = C.sizeof(SppmParams)
     p.n_photons, p.alpha, p.r0, p.seed = n_photons, alpha, float(r0), seed
     p.max_eye_depth, p.max_photon_bounces = max_eye_depth, max_photon_bounces
     p.fixed_shift, p.store_factor = fixed_shift, store_factor
+    p.record_iterations = record_iterations
     return p
 
 
@@ -309,6 +312,18 @@ class Sppm:
             Phi=_device_view(v.gather_Phi, (P,), torch.int64),
         )
 
+    def adjoint(self, dloss_dimage, param_mats, grad=None, stream=None):
+        """dLoss/drho for each material in param_mats, then dLoss/dLe (float64 cuda tensor)."""
+        import torch
+        g = dloss_dimage.to(torch.float32).contiguous()
+        assert g.is_cuda and g.numel() == self.width * self.height
+        pm = np.ascontiguousarray(param_mats, np.int32)
+        if grad is None:
+            grad = torch.empty(len(pm) + 1, dtype=torch.float64, device=g.device)
+        _check(lib().pm_sppm_adjoint(self.h, _ptr(g), _ptr(pm) if len(pm) else None, len(pm), _ptr(grad),
+                                     _stream(stream)))
+        return grad
+
     def destroy(self):
         if self.h:
             _check(lib().pm_sppm_destroy(self.h))
@@ -333,3 +348,55 @@ def render(scene, params: SppmParams, K: int, image=None, bvh: Bvh | None = None
     args = _SceneArgs(scene, bvh)
     _check(lib().pm_render(C.byref(args.desc), C.byref(params), K, _ptr(image), _stream(stream)))
     return image
+
+
+def _render_function():
+    import torch
+
+    class SPPMRender(torch.autograd.Function):
+        """Differentiable SPPM render: image(albedos, Le).
+
+        forward: K iterations with the given albedos of ``param_mats`` and the
+        emitting material's Le (Russian roulette keeps the scene's nominal q);
+        backward: pm_sppm_adjoint replays the K iterations.
+        """
+
+        @staticmethod
+        def forward(ctx, albedos, Le, scene, param_mats, params, K, stream=None):
+            sc = scene.with_rho(scene.mat_rho.copy())
+            rho = sc.mat_rho
+            rho[np.asarray(param_mats, np.int64)] = albedos.detach().cpu().numpy().astype(np.float32)
+            em = np.nonzero(scene.mat_Le > 0)[0]
+            if len(em) != 1:
+                raise ValueError("Le is a parameter only for scenes with exactly one emitting material")
+            sc.mat_Le = scene.mat_Le.copy()
+            sc.mat_Le[em[0]] = np.float32(float(Le))
+            p = SppmParams.from_buffer_copy(params)
+            p.record_iterations = max(int(params.record_iterations), int(K))
+            s = Sppm(sc, p, stream=stream)
+            s.iterate(K, stream=stream)
+            img = s.resolve(stream=stream)
+            ctx.s, ctx.param_mats, ctx.stream = s, np.asarray(param_mats, np.int32), stream
+            ctx.dtypes = (albedos.dtype, Le.dtype if hasattr(Le, "dtype") else torch.float32)
+            ctx.devices = (albedos.device, Le.device if hasattr(Le, "device") else albedos.device)
+            return img
+
+        @staticmethod
+        def backward(ctx, g):
+            grad = ctx.s.adjoint(g, ctx.param_mats, stream=ctx.stream)
+            n = len(ctx.param_mats)
+            return (grad[:n].to(device=ctx.devices[0], dtype=ctx.dtypes[0]),
+                    grad[n].to(device=ctx.devices[1], dtype=ctx.dtypes[1]), None, None, None, None, None)
+
+    return SPPMRender
+
+
+_SPPMRender = None
+
+
+def sppm_render_diff(albedos, Le, scene, param_mats, params: SppmParams, K: int, stream=None):
+    """Differentiable render (torch.autograd): returns the [H, W] image."""
+    global _SPPMRender
+    if _SPPMRender is None:
+        _SPPMRender = _render_function()
+    return _SPPMRender.apply(albedos, Le, scene, param_mats, params, K, stream)

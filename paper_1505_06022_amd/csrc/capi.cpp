@@ -188,6 +188,11 @@ int pm_sppm_status(pm_sppm *s, void *stream) { PM_GUARD({ return pm::sppm_status
 
 int pm_sppm_get_views(pm_sppm *s, pm_sppm_views *v) { PM_GUARD({ return pm::sppm_views(s, v); }) }
 
+int pm_sppm_adjoint(pm_sppm *s, const float *dloss_dimage, const int32_t *param_mats, int32_t n_par, double *grad,
+                    void *stream) {
+    PM_GUARD({ return pm::sppm_adjoint(s, dloss_dimage, param_mats, n_par, grad, (hipStream_t)stream); })
+}
+
 int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream) {
     PM_GUARD({
         if (K < 1 || !image) return pm::set_error("K must be >= 1 and image non-NULL"), PM_ERR_ARG;

@@ -13,5 +13,6 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st);
 int sppm_resolve(pm_sppm *s, float *image, hipStream_t st);
 int sppm_status(pm_sppm *s, hipStream_t st);
 int sppm_views(pm_sppm *s, pm_sppm_views *v);
+int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par, double *grad, hipStream_t st);
 
 }  // namespace pm

@@ -41,6 +41,7 @@ struct SceneDev {
 __global__ __launch_bounds__(kBlock) void k_eye(SceneDev sc, uint64_t seed, uint32_t k, int32_t max_depth,
                                                 float4 *__restrict__ hp_pos, float4 *__restrict__ hp_nrm,
                                                 double *__restrict__ D) {
+    // D == nullptr: replay (adjoint) -- hit points only
     int64_t p = (int64_t)pmd::xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     int64_t P = (int64_t)sc.W * sc.H;
     if (p >= P) return;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_eye(SceneDev sc, uint64_t seed, uint
     }
     hp_pos[p] = pos;
     hp_nrm[p] = nrm;
-    D[p] += dadd;
+    if (D) D[p] += dadd;
 }
 
 // Wave-aggregated append: one atomic per wavefront for all lanes currently
@@ -114,11 +115,20 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter) {
 // absorbing surface, Russian roulette or the bounce cap.  A photon is stored
 // at every diffuse hit.  Record: (x, phi), (w, path << 5 | bounce).
 // ---------------------------------------------------------------------------
+// kRecord (adjoint replay): row n of mat_tab gets, per bounce, the material
+// of a stored photon (0xff: no photon at that bounce; 0xfe: the path ended),
+// and the matching entries of adj_tab are cleared for the adjoint gather.
+template <bool kRecord>
 __global__ __launch_bounds__(kBlock) void k_photon(SceneDev sc, uint64_t seed, uint32_t k, uint32_t n_paths,
                                                    float phi0, int32_t max_bounces, float4 *__restrict__ store,
-                                                   uint32_t cap, uint32_t *__restrict__ counters) {
+                                                   uint32_t cap, uint32_t *__restrict__ counters,
+                                                   uint8_t *__restrict__ mat_tab, double *__restrict__ adj_tab) {
     uint32_t n = pmd::xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (n >= n_paths || sc.n_emit == 0) return;
+    if (n >= n_paths) return;
+    if (sc.n_emit == 0) {
+        if (kRecord) mat_tab[(size_t)n * max_bounces] = 0xfeu;
+        return;
+    }
     pmd::Rng g = pmd::rng_seed(seed, pmd::kKindPhoton, k, (uint64_t)n);
     float u0 = pmd::rng_next(g);
     double target = (double)u0 * sc.power;
@@ -141,6 +151,8 @@ __global__ __launch_bounds__(kBlock) void k_photon(SceneDev sc, uint64_t seed, u
     float phi = phi0;
     int32_t excl = et.id;
     pmd::TraceStats st;
+    uint8_t *row = kRecord ? mat_tab + (size_t)n * max_bounces : nullptr;
+    int last = -1;  // last bounce written to the row
     for (int b = 0; b < max_bounces; ++b) {
         float t;
         uint32_t kp;
@@ -152,9 +164,17 @@ __global__ __launch_bounds__(kBlock) void k_photon(SceneDev sc, uint64_t seed, u
         V3 nrm = pmd::tri_normal(tr);
         uint32_t m = tr.mat;
         int type = sc.mat_type[m];
+        if (kRecord) {
+            row[b] = 0xffu;
+            last = b;
+        }
         if (type == PM_MAT_DIFFUSE) {
             float rho = sc.mat_rho[m];
             if (!(rho > 0.0f)) break;
+            if (kRecord) {
+                row[b] = (uint8_t)m;
+                adj_tab[(size_t)n * max_bounces + b] = 0.0;
+            }
             uint32_t slot = wave_append(&counters[0]);
             if (slot < cap) {
                 store[2 * (size_t)slot] = make_float4(x.x, x.y, x.z, phi);
@@ -176,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_photon(SceneDev sc, uint64_t seed, u
         org = x;
         excl = h;
     }
+    if (kRecord && last + 1 < max_bounces) row[last + 1] = 0xfeu;
 }
 
 // ---------------------------------------------------------------------------
@@ -397,12 +418,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float4 *__restrict__ hp
 }
 
 // Progressive update (radius reduction and flux rescaling of SPPM).
+// hist (optional) receives the radius used in this iteration, for the adjoint.
 __global__ __launch_bounds__(kBlock) void k_update(const float4 *__restrict__ hp_nrm, const uint32_t *__restrict__ M_in,
                                                    const unsigned long long *__restrict__ Phi_in, int64_t P,
                                                    double alpha, double inv_scale, double *__restrict__ N,
-                                                   double *__restrict__ R2, double *__restrict__ tau) {
+                                                   double *__restrict__ R2, double *__restrict__ tau,
+                                                   double *__restrict__ hist) {
     int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= P) return;
+    if (hist) hist[p] = R2[p];
     uint32_t Mi = M_in[p];
     if (__float_as_int(hp_nrm[p].w) < 0 || Mi == 0) return;
     double m = (double)Mi;
@@ -412,6 +436,128 @@ __global__ __launch_bounds__(kBlock) void k_update(const float4 *__restrict__ hp
     R2[p] = R2[p] * ratio;
     tau[p] = (tau[p] + (double)Phi_in[p] * inv_scale) * ratio;
     N[p] = nn;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradient of an image loss by replay).  With sampling held fixed the
+// radiance of pixel p is sum_k sum_c c / (pi R2_{p,k} K) + D_p / K, each
+// contribution c = W rho_h / pi * phi_j, where phi_j carries rho_m / q_m for
+// every earlier diffuse bounce on m.  Per iteration the replayed gather adds
+// G_h = g_h / (pi R2_{h,k} K) times c to the photon's (path, bounce) entry and
+// the hit point's own albedo term G_h * sum c / rho_h; a per-path suffix sum
+// then gives the earlier-bounce terms.  Material sums are reduced in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kMaxAdjMat = 256;
+
+__device__ __forceinline__ void lds_flush(double *lds, int n_mat, double *__restrict__ grad_mat) {
+    __syncthreads();
+    for (int m = threadIdx.x; m < n_mat; m += kBlock)
+        if (lds[m] != 0.0) unsafeAtomicAdd(&grad_mat[m], lds[m]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_adj(const float4 *__restrict__ hp_pos, const float4 *__restrict__ hp_nrm,
+                                                       const double *__restrict__ R2k, int64_t P, SceneDev sc,
+                                                       const unsigned long long *r2max_bits, uint32_t mask,
+                                                       const uint32_t *__restrict__ start,
+                                                       const float4 *__restrict__ sorted, const float *__restrict__ g,
+                                                       double K, int32_t max_bounces, double *__restrict__ adj_tab,
+                                                       int32_t n_mat, double *__restrict__ grad_mat) {
+    __shared__ double lds[kMaxAdjMat];
+    for (int m = threadIdx.x; m < n_mat; m += kBlock) lds[m] = 0.0;
+    __syncthreads();
+    int64_t p = (int64_t)pmd::xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    float4 hn = p < P ? hp_nrm[p] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    if (__float_as_int(hn.w) >= 0 && g[p] != 0.0f) {
+        float4 hx = hp_pos[p];
+        double r2 = R2k[p];
+        double G = (double)g[p] / ((pmd::kPiD * r2) * K);
+        Grid gr = make_grid(sc, r2max_bits, mask);
+        int32_t bx = (int32_t)floorf((hx.x - gr.lo[0]) * gr.inv_h - 0.5f);
+        int32_t by = (int32_t)floorf((hx.y - gr.lo[1]) * gr.inv_h - 0.5f);
+        int32_t bz = (int32_t)floorf((hx.z - gr.lo[2]) * gr.inv_h - 0.5f);
+        uint32_t seen[8];
+        double wk = (double)hx.w, csum = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            uint32_t hb = cell_hash(bx + (c & 1), by + ((c >> 1) & 1), bz + (c >> 2), mask);
+            bool dup = false;
+            for (int e = 0; e < c; ++e) dup |= (seen[e] == hb);
+            seen[c] = hb;
+            if (dup) continue;
+            uint32_t q0 = start[hb], q1 = start[hb + 1];
+            for (uint32_t q = q0; q < q1; ++q) {
+                float4 a = sorted[2 * (size_t)q];
+                float dx = a.x - hx.x, dy = a.y - hx.y, dz = a.z - hx.z;
+                float d2 = (dx * dx + dy * dy) + dz * dz;
+                if ((double)d2 < r2) {
+                    float4 b = sorted[2 * (size_t)q + 1];
+                    float c2 = (b.x * hn.x + b.y * hn.y) + b.z * hn.z;
+                    if (c2 < 0.0f) {
+                        double cc = wk * (double)a.w;
+                        uint32_t meta = __float_as_uint(b.w);
+                        unsafeAtomicAdd(&adj_tab[(size_t)(meta >> 5) * max_bounces + (meta & 31u)], G * cc);
+                        csum += cc;
+                    }
+                }
+            }
+        }
+        uint32_t m = __float_as_uint(hn.w);
+        if (csum != 0.0) atomicAdd(&lds[m], G * csum / (double)sc.mat_rho[m]);
+    }
+    lds_flush(lds, n_mat, grad_mat);
+}
+
+__global__ __launch_bounds__(kBlock) void k_path_adj(const uint8_t *__restrict__ mat_tab,
+                                                     const double *__restrict__ adj_tab, uint32_t n_paths,
+                                                     int32_t max_bounces, const float *__restrict__ mat_rho,
+                                                     int32_t n_mat, double *__restrict__ grad_mat) {
+    __shared__ double lds[kMaxAdjMat];
+    for (int m = threadIdx.x; m < n_mat; m += kBlock) lds[m] = 0.0;
+    __syncthreads();
+    uint32_t n = blockIdx.x * kBlock + threadIdx.x;
+    if (n < n_paths) {
+        const uint8_t *row = mat_tab + (size_t)n * max_bounces;
+        const double *arow = adj_tab + (size_t)n * max_bounces;
+        int end = 0;
+        while (end < max_bounces && row[end] != 0xfeu) end++;
+        double S = 0.0;  // sensitivity of the photons stored after bounce b
+        for (int b = end - 1; b >= 0; --b) {
+            uint32_t m = row[b];
+            if (m == 0xffu) continue;
+            if (S != 0.0) atomicAdd(&lds[m], S / (double)mat_rho[m]);
+            S += arow[b];
+        }
+    }
+    lds_flush(lds, n_mat, grad_mat);
+}
+
+// sum_p g_p L_p (every term of L_p is proportional to the emitted radiance)
+__global__ __launch_bounds__(kBlock) void k_le_grad(const double *__restrict__ R2, const double *__restrict__ tau,
+                                                    const double *__restrict__ D, int64_t P, double K,
+                                                    const float *__restrict__ g, double *__restrict__ out) {
+    __shared__ double lds[kBlock / 64];
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (p < P) v = (double)g[p] * (tau[p] / ((pmd::kPiD * R2[p]) * K) + D[p] / K);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
+        unsafeAtomicAdd(out, t);
+    }
+}
+
+__global__ void k_fill_f64(double *p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_collect_grad(const double *__restrict__ grad_mat, const int32_t *__restrict__ pmat, int32_t n_par,
+                               const double *__restrict__ le_sum, double inv_Le, double *__restrict__ out) {
+    int i = threadIdx.x;
+    if (i < n_par) out[i] = grad_mat[pmat[i]];
+    if (i == n_par) out[i] = *le_sum * inv_Le;
 }
 
 __global__ __launch_bounds__(kBlock) void k_resolve(const double *__restrict__ R2, const double *__restrict__ tau,
@@ -472,6 +618,15 @@ struct pm_sppm {
     uint32_t *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *bsum = nullptr;
     uint32_t *M = nullptr;
     unsigned long long *Phi = nullptr;
+    // adjoint recording / replay buffers (record_iterations > 0)
+    int32_t rec_iters = 0;
+    int32_t n_mat = 0;
+    double le_single = 0.0;  // Le of the single emitting material, 0 if not exactly one
+    double *R2_hist = nullptr;    // [rec_iters][P] radius used in each iteration
+    double *adj_tab = nullptr;    // [n_photons][max_bounces] photon sensitivities
+    uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
+    double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
+    int32_t *d_pmat = nullptr;    // [256] parameter materials
 };
 
 namespace pm {
@@ -481,7 +636,8 @@ static void sppm_free(pm_sppm *s) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
-                    s->cell_fill, s->bsum, s->M, s->Phi};
+                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
+                    s->d_pmat};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (s->own_bvh && s->bvh) {
@@ -522,6 +678,10 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->store_factor < 1 || p->n_photons * p->store_factor > (int64_t(1) << 30))
         return set_error("store_factor must be >= 1 and the store below 2^30 photons"), PM_ERR_ARG;
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
+    if (p->record_iterations < 0 || p->record_iterations > 100000)
+        return set_error("record_iterations must be in [0, 100000]"), PM_ERR_ARG;
+    if (p->record_iterations > 0 && d->n_mat > kMaxAdjMat)
+        return set_error("the adjoint supports at most 256 materials"), PM_ERR_ARG;
     return PM_OK;
 }
 
@@ -598,6 +758,25 @@ int sppm_create(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t st,
     PM_HIP(hipMalloc(&s->bsum, sizeof(uint32_t) * (nb + 1)));
     PM_HIP(hipMalloc(&s->M, sizeof(uint32_t) * s->P));
     PM_HIP(hipMalloc(&s->Phi, sizeof(unsigned long long) * s->P));
+    s->n_mat = nm;
+    s->rec_iters = p->record_iterations;
+    if (s->rec_iters > 0) {
+        PM_HIP(hipMalloc(&s->R2_hist, sizeof(double) * (size_t)s->rec_iters * s->P));
+        PM_HIP(hipMalloc(&s->adj_tab, sizeof(double) * (size_t)p->n_photons * p->max_photon_bounces));
+        PM_HIP(hipMalloc(&s->mat_tab, (size_t)p->n_photons * p->max_photon_bounces));
+        PM_HIP(hipMalloc(&s->grad_mat, sizeof(double) * (nm + 1)));
+        PM_HIP(hipMalloc(&s->d_pmat, sizeof(int32_t) * kMaxAdjMat));
+    }
+    {
+        int n_emit_mat = 0;
+        double le = 0.0;
+        for (int32_t m = 0; m < nm; ++m)
+            if (d->mat_Le[m] > 0.0f) {
+                n_emit_mat++;
+                le = d->mat_Le[m];
+            }
+        s->le_single = n_emit_mat == 1 ? le : 0.0;
+    }
 
     std::vector<float> mf(4 * (size_t)nm);
     for (int32_t m = 0; m < nm; ++m) {
@@ -672,8 +851,8 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
                            s->prm.max_eye_depth, s->hp_pos, s->hp_nrm, s->D);
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, s->counters, s->r2max);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
-        hipLaunchKernelGGL(k_photon, dim3(blocks_for(np)), dim3(kBlock), 0, st, s->sc, s->prm.seed, k, np, s->phi0,
-                           s->prm.max_photon_bounces, s->store, s->cap, s->counters);
+        hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, s->sc, s->prm.seed, k, np,
+                           s->phi0, s->prm.max_photon_bounces, s->store, s->cap, s->counters, nullptr, nullptr);
         hipLaunchKernelGGL(k_rmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->hp_nrm, s->R2, s->P, s->r2max);
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, s->store, s->counters, s->cap, s->sc,
                            s->r2max, mask, s->cell_count);
@@ -684,8 +863,9 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
                            s->r2max, mask, s->cell_fill, s->sorted);
         hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->hp_pos, s->hp_nrm, s->R2, s->P,
                            s->sc, s->r2max, mask, s->cell_start, s->sorted, scale, s->M, s->Phi);
+        double *hist = (int32_t)k < s->rec_iters ? s->R2_hist + (size_t)k * s->P : nullptr;
         hipLaunchKernelGGL(k_update, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->hp_nrm, s->M, s->Phi, s->P,
-                           s->prm.alpha, inv_scale, s->N, s->R2, s->tau);
+                           s->prm.alpha, inv_scale, s->N, s->R2, s->tau, hist);
         PM_HIP(hipGetLastError());
         s->K++;
     }
@@ -706,6 +886,58 @@ int sppm_status(pm_sppm *s, hipStream_t st) {
     PM_HIP(hipMemcpyAsync(c, s->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     PM_HIP(hipStreamSynchronize(st));
     if (c[1]) return set_error("photon store overflow: raise store_factor"), PM_ERR_OVERFLOW;
+    return PM_OK;
+}
+
+int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par, double *grad, hipStream_t st) {
+    if (!s || !g || !grad || n_par < 0 || (n_par > 0 && !pmat))
+        return set_error("invalid handle, gradient or parameter pointers"), PM_ERR_ARG;
+    if (s->K < 1) return set_error("no iteration has run"), PM_ERR_STATE;
+    if (s->K > s->rec_iters)
+        return set_error("the forward iterations were not recorded: set record_iterations >= K"), PM_ERR_STATE;
+    if (n_par >= kMaxAdjMat) return set_error("too many parameters"), PM_ERR_ARG;
+    std::vector<float> rho(s->n_mat);
+    PM_HIP(hipMemcpy(rho.data(), s->mat_f, sizeof(float) * s->n_mat, hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < n_par; ++i) {
+        if (pmat[i] < 0 || pmat[i] >= s->n_mat) return set_error("parameter material out of range"), PM_ERR_ARG;
+        if (!(rho[pmat[i]] > 0.0f)) return set_error("albedo parameters must have rho > 0"), PM_ERR_ARG;
+    }
+    const uint32_t T = 1u << s->table_bits, mask = T - 1u, nb = T / kScanTile;
+    const uint32_t np = (uint32_t)s->prm.n_photons;
+    const int32_t mb = s->prm.max_photon_bounces;
+    const uint32_t ph_blocks = std::min<uint32_t>(blocks_for(s->cap), 256u * 64u);
+    const double K = (double)s->K;
+    PM_HIP(hipMemcpyAsync(s->d_pmat, pmat, sizeof(int32_t) * std::max(1, n_par), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(s->n_mat + 1)), dim3(kBlock), 0, st, s->grad_mat,
+                       (int64_t)s->n_mat + 1);
+    for (int32_t k = 0; k < s->K; ++k) {
+        const double *R2k = s->R2_hist + (size_t)k * s->P;
+        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->sc, s->prm.seed, (uint32_t)k,
+                           s->prm.max_eye_depth, s->hp_pos, s->hp_nrm, (double *)nullptr);
+        hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, s->counters, s->r2max);
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
+        hipLaunchKernelGGL(k_photon<true>, dim3(blocks_for(np)), dim3(kBlock), 0, st, s->sc, s->prm.seed,
+                           (uint32_t)k, np, s->phi0, mb, s->store, s->cap, s->counters, s->mat_tab, s->adj_tab);
+        hipLaunchKernelGGL(k_rmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->hp_nrm, R2k, s->P, s->r2max);
+        hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, s->store, s->counters, s->cap, s->sc,
+                           s->r2max, mask, s->cell_count);
+        hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kBlock), 0, st, s->cell_count, s->cell_start, s->bsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, st, s->bsum, nb);
+        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kBlock), 0, st, s->cell_start, s->cell_fill, s->bsum, nb);
+        hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, s->store, s->counters, s->cap, s->sc,
+                           s->r2max, mask, s->cell_fill, s->sorted);
+        hipLaunchKernelGGL(k_gather_adj, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->hp_pos, s->hp_nrm, R2k, s->P,
+                           s->sc, s->r2max, mask, s->cell_start, s->sorted, g, K, mb, s->adj_tab, s->n_mat,
+                           s->grad_mat);
+        hipLaunchKernelGGL(k_path_adj, dim3(blocks_for(np)), dim3(kBlock), 0, st, s->mat_tab, s->adj_tab, np, mb,
+                           s->sc.mat_rho, s->n_mat, s->grad_mat);
+        PM_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_le_grad, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, s->R2, s->tau, s->D, s->P, K, g,
+                       s->grad_mat + s->n_mat);
+    hipLaunchKernelGGL(k_collect_grad, dim3(1), dim3(kMaxAdjMat), 0, st, s->grad_mat, s->d_pmat, n_par,
+                       s->grad_mat + s->n_mat, s->le_single > 0.0 ? 1.0 / s->le_single : 0.0, grad);
+    PM_HIP(hipGetLastError());
     return PM_OK;
 }
 
