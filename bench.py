@@ -57,6 +57,8 @@ def _parse():
     ap.add_argument("--sppm-iters", type=int, default=4)
     ap.add_argument("--adjoint-iters", type=int, default=8)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batch-iters", type=int, default=16)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the comparison of traversal kernels")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
@@ -196,6 +198,49 @@ def adjoint_bench(args, torch, api, scenes):
             "workload": "procedural 250,094 triangles, 1280x720, 2^20 photons/iteration, L2 loss"}
 
 
+def batch_bench(args, torch, api, scenes):
+    """32 procedural scenes of 1k-200k triangles at 128^2-512^2 with 2^16-2^20
+    photons each: K iterations of all of them, one persistent launch per stage
+    (autotuned chunk/block, hipGraph per iteration), against the same scenes
+    rendered one handle after another."""
+    work = scenes.batch_workload()
+    K = args.batch_iters
+    prm = [api.sppm_params(Np, alpha=0.7, r0=r0, seed=100 + i) for i, (_, Np, r0) in enumerate(work)]
+    st = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    b = api.Batch([w[0] for w in work], prm, autotune=True)
+    t_setup = time.perf_counter() - t0
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    e[0].record(st)
+    b.iterate(K)
+    e[1].record(st)
+    torch.cuda.synchronize()
+    t_batch = e[0].elapsed_time(e[1])
+    b.status()
+    info = b.info()
+    b.destroy()
+    singles = [api.Sppm(w[0], p) for w, p in zip(work, prm)]
+    torch.cuda.synchronize()
+    e[2].record(st)
+    for s in singles:
+        s.iterate(K)
+    e[3].record(st)
+    torch.cuda.synchronize()
+    t_seq = e[2].elapsed_time(e[3])
+    for s in singles:
+        s.destroy()
+    photons = sum(Np for _, Np, _ in work) * K
+    return {"photons_per_s": round(photons / (t_batch * 1e-3), 1), "ms": round(t_batch, 2),
+            "sequential_ms": round(t_seq, 2), "speedup_vs_sequential": round(t_seq / t_batch, 3),
+            "iterations": K, "scenes": len(work), "triangles": int(sum(w[0].n_tri for w in work)),
+            "pixels": int(sum(w[0].camera.width * w[0].camera.height for w in work)),
+            "photons_per_iteration": int(sum(Np for _, Np, _ in work)),
+            "chunk": info["chunk"], "block": info["block"], "graph": info["uses_graph"],
+            "autotune_ms_per_iter": [[c, bl, round(ms, 3)] for c, bl, ms in info["candidates"]],
+            "setup_s": round(t_setup, 2)}
+
+
 def cpu_baseline(tb, scenes):
     import oracle
     nth = _cpu_threads()
@@ -270,6 +315,9 @@ def main():
                        "stored_photons": sp["n_stored"], "workload": sp["workload"]}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, torch, api, scenes)
+    if not args.no_batch:
+        os.environ.setdefault("PM_AUTOTUNE_CACHE", os.path.join("/tmp", "pm_autotune_bench.txt"))
+        out["batch"] = batch_bench(args, torch, api, scenes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tb, scenes)
     print(json.dumps(out), flush=True)

@@ -239,6 +239,49 @@ typedef struct {
 
 PM_API int pm_sppm_get_views(pm_sppm *s, pm_sppm_views *v);
 
+/* ------------------------------------------------------------------ */
+/* Batched rendering: many scenes of uneven size in one launch per stage */
+/* ------------------------------------------------------------------ */
+typedef struct pm_batch pm_batch;
+
+typedef struct {
+    uint32_t size;     /* sizeof(pm_batch_opts) */
+    int32_t chunk;     /* elements (pixels, paths, photons) per work item; 0 = 1024 */
+    int32_t block;     /* workgroup size: 0 (= 256), 128 or 256 */
+    int32_t autotune;  /* 1: time every (chunk, block) candidate and keep the fastest
+                          (result cached on disk: $PM_AUTOTUNE_CACHE, default
+                          ~/.cache/pm_autotune.txt); overrides chunk/block */
+    int32_t use_graph; /* 1: capture one iteration as a hipGraph and replay it */
+} pm_batch_opts;
+
+typedef struct {
+    uint32_t size;     /* sizeof(pm_batch_info) */
+    int32_t n_scenes, iterations, chunk, block, uses_graph, tuned_from_cache;
+    int32_t n_candidates;          /* autotuner candidates timed (<= 8) */
+    int32_t cand_chunk[8], cand_block[8];
+    double cand_ms[8];             /* ms per iteration of each candidate */
+} pm_batch_info;
+
+/* Create a batch of SPPM renderers (one per scene; descs[i]/params[i] as for
+ * pm_sppm_create, record_iterations ignored).  Every stage of an iteration is
+ * one persistent launch for all scenes: workgroups take (scene, chunk) items
+ * from a device work counter.  The library owns all device buffers. */
+PM_API int pm_batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
+                           const pm_batch_opts *opts, void *stream, pm_batch **out);
+PM_API int pm_batch_destroy(pm_batch *b);
+/* Enqueue n_iter iterations of every scene (graph replays when use_graph). */
+PM_API int pm_batch_iterate(pm_batch *b, int32_t n_iter, void *stream);
+/* images: host array of n_scenes device pointers, each float32 [height][width]. */
+PM_API int pm_batch_resolve(pm_batch *b, float *const *images, void *stream);
+/* Synchronise and report sticky device errors of every scene. */
+PM_API int pm_batch_status(pm_batch *b, void *stream);
+PM_API int pm_batch_get_info(const pm_batch *b, pm_batch_info *info);
+/* Device buffers of scene i (bucket fields refer to the batch's shared arrays). */
+PM_API int pm_batch_get_views(pm_batch *b, int32_t scene, pm_sppm_views *v);
+/* create -> K iterations -> resolve -> status -> destroy. */
+PM_API int pm_render_batch(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
+                           int32_t K, float *const *images, const pm_batch_opts *opts, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

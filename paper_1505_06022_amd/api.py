@@ -21,7 +21,8 @@ PM_OK, PM_ERR_ARG, PM_ERR_HIP, PM_ERR_OVERFLOW, PM_ERR_STATE, PM_ERR_NOMEM = 0, 
 EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host", "pm_bvh_destroy",
            "pm_bvh_get_info", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
-           "pm_sppm_adjoint"]
+           "pm_sppm_adjoint", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
+           "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch"]
 
 
 class PMError(RuntimeError):
@@ -72,6 +73,18 @@ class SppmViews(C.Structure):
                 ("photon_count", C.c_void_p), ("gather_M", C.c_void_p), ("gather_Phi", C.c_void_p)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("chunk", C.c_int32), ("block", C.c_int32), ("autotune", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("n_scenes", C.c_int32), ("iterations", C.c_int32), ("chunk", C.c_int32),
+                ("block", C.c_int32), ("uses_graph", C.c_int32), ("tuned_from_cache", C.c_int32),
+                ("n_candidates", C.c_int32), ("cand_chunk", C.c_int32 * 8), ("cand_block", C.c_int32 * 8),
+                ("cand_ms", C.c_double * 8)]
+
+
 _lib = None
 
 
@@ -99,6 +112,14 @@ def lib() -> C.CDLL:
         L.pm_render.argtypes = [P, P, I32, P, P]
         L.pm_sppm_get_views.argtypes = [P, P]
         L.pm_sppm_adjoint.argtypes = [P, P, P, I32, P, P]
+        L.pm_batch_create.argtypes = [P, P, I32, P, P, P]
+        L.pm_batch_destroy.argtypes = [P]
+        L.pm_batch_iterate.argtypes = [P, I32, P]
+        L.pm_batch_resolve.argtypes = [P, P, P]
+        L.pm_batch_status.argtypes = [P, P]
+        L.pm_batch_get_info.argtypes = [P, P]
+        L.pm_batch_get_views.argtypes = [P, I32, P]
+        L.pm_render_batch.argtypes = [P, P, I32, I32, P, P, P]
         _lib = L
     return _lib
 
@@ -269,6 +290,22 @@ def _device_view(ptr: int, shape, dtype):
     return torch.as_tensor(_Iface(), device="cuda")
 
 
+def _views_dict(v) -> dict:
+    import torch
+    P, cap = v.n_pixels, v.photon_capacity
+    return dict(
+        iterations=v.iterations, table_size=v.table_size,
+        N=_device_view(v.N, (P,), torch.float64), R2=_device_view(v.R2, (P,), torch.float64),
+        tau=_device_view(v.tau, (P,), torch.float64), D=_device_view(v.D, (P,), torch.float64),
+        hp_pos=_device_view(v.hp_pos, (P, 4), torch.float32),
+        hp_nrm=_device_view(v.hp_nrm, (P, 4), torch.float32),
+        photons=_device_view(v.photons, (cap, 8), torch.float32),
+        photon_count=_device_view(v.photon_count, (4,), torch.int32),
+        M=_device_view(v.gather_M, (P,), torch.int32),
+        Phi=_device_view(v.gather_Phi, (P,), torch.int64),
+    )
+
+
 class Sppm:
     """One progressive photon mapping renderer (library-owned device state)."""
 
@@ -295,22 +332,11 @@ class Sppm:
 
     def views(self) -> dict:
         """Tensors aliasing the handle's device buffers (valid until destroy)."""
-        import torch
         v = SppmViews()
         v.size = C.sizeof(SppmViews)
         _check(lib().pm_sppm_get_views(self.h, C.byref(v)))
-        P, cap = v.n_pixels, v.photon_capacity
-        return dict(
-            iterations=v.iterations, table_size=v.table_size,
-            N=_device_view(v.N, (P,), torch.float64), R2=_device_view(v.R2, (P,), torch.float64),
-            tau=_device_view(v.tau, (P,), torch.float64), D=_device_view(v.D, (P,), torch.float64),
-            hp_pos=_device_view(v.hp_pos, (P, 4), torch.float32),
-            hp_nrm=_device_view(v.hp_nrm, (P, 4), torch.float32),
-            photons=_device_view(v.photons, (cap, 8), torch.float32),
-            photon_count=_device_view(v.photon_count, (4,), torch.int32),
-            M=_device_view(v.gather_M, (P,), torch.int32),
-            Phi=_device_view(v.gather_Phi, (P,), torch.int64),
-        )
+        return _views_dict(v)
+
 
     def adjoint(self, dloss_dimage, param_mats, grad=None, stream=None):
         """dLoss/drho for each material in param_mats, then dLoss/dLe (float64 cuda tensor)."""
@@ -400,3 +426,87 @@ def sppm_render_diff(albedos, Le, scene, param_mats, params: SppmParams, K: int,
     if _SPPMRender is None:
         _SPPMRender = _render_function()
     return _SPPMRender.apply(albedos, Le, scene, param_mats, params, K, stream)
+
+
+# ---------------------------------------------------------------------------
+# Batched rendering
+# ---------------------------------------------------------------------------
+def batch_opts(chunk=0, block=0, autotune=False, use_graph=True) -> BatchOpts:
+    o = BatchOpts()
+    o.size, o.chunk, o.block, o.autotune, o.use_graph = C.sizeof(BatchOpts), chunk, block, int(autotune), int(use_graph)
+    return o
+
+
+class Batch:
+    """Many SPPM renderers advanced together, one persistent launch per stage."""
+
+    def __init__(self, scenes, params, chunk=0, block=0, autotune=False, use_graph=True, stream=None):
+        if isinstance(params, SppmParams):
+            params = [params] * len(scenes)
+        self.args = [_SceneArgs(sc) for sc in scenes]
+        self.params = list(params)
+        self.sizes = [(sc.camera.height, sc.camera.width) for sc in scenes]
+        descs = (C.c_void_p * len(scenes))(*[C.addressof(a.desc) for a in self.args])
+        prms = (C.c_void_p * len(scenes))(*[C.addressof(p) for p in self.params])
+        self.opts = batch_opts(chunk, block, autotune, use_graph)
+        out = C.c_void_p()
+        _check(lib().pm_batch_create(descs, prms, len(scenes), C.byref(self.opts), _stream(stream), C.byref(out)))
+        self.h = out
+
+    def iterate(self, n: int = 1, stream=None):
+        _check(lib().pm_batch_iterate(self.h, n, _stream(stream)))
+
+    def resolve(self, images=None, stream=None):
+        import torch
+        if images is None:
+            images = [torch.empty(hw, dtype=torch.float32, device="cuda") for hw in self.sizes]
+        ptrs = (C.c_void_p * len(images))(*[im.data_ptr() for im in images])
+        _check(lib().pm_batch_resolve(self.h, ptrs, _stream(stream)))
+        return images
+
+    def status(self, stream=None):
+        _check(lib().pm_batch_status(self.h, _stream(stream)))
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        inf.size = C.sizeof(BatchInfo)
+        _check(lib().pm_batch_get_info(self.h, C.byref(inf)))
+        n = inf.n_candidates
+        return dict(n_scenes=inf.n_scenes, iterations=inf.iterations, chunk=inf.chunk, block=inf.block,
+                    uses_graph=bool(inf.uses_graph), tuned_from_cache=bool(inf.tuned_from_cache),
+                    candidates=[(inf.cand_chunk[i], inf.cand_block[i], inf.cand_ms[i]) for i in range(n)])
+
+    def views(self, scene: int) -> dict:
+        v = SppmViews()
+        v.size = C.sizeof(SppmViews)
+        _check(lib().pm_batch_get_views(self.h, scene, C.byref(v)))
+        return _views_dict(v)
+
+    def destroy(self):
+        if self.h:
+            _check(lib().pm_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def render_batch(scenes, params, K: int, images=None, chunk=0, block=0, autotune=False, use_graph=True, stream=None):
+    """create -> K iterations of every scene -> resolve -> destroy."""
+    import torch
+    if isinstance(params, SppmParams):
+        params = [params] * len(scenes)
+    args = [_SceneArgs(sc) for sc in scenes]
+    params = list(params)
+    if images is None:
+        images = [torch.empty((sc.camera.height, sc.camera.width), dtype=torch.float32, device="cuda")
+                  for sc in scenes]
+    descs = (C.c_void_p * len(scenes))(*[C.addressof(a.desc) for a in args])
+    prms = (C.c_void_p * len(scenes))(*[C.addressof(p) for p in params])
+    ptrs = (C.c_void_p * len(images))(*[im.data_ptr() for im in images])
+    o = batch_opts(chunk, block, autotune, use_graph)
+    _check(lib().pm_render_batch(descs, prms, len(scenes), K, ptrs, C.byref(o), _stream(stream)))
+    return images

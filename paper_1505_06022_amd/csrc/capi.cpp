@@ -209,4 +209,47 @@ int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K
     })
 }
 
+int pm_batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
+                    const pm_batch_opts *opts, void *stream, pm_batch **out) {
+    PM_GUARD({
+        if (!out) return pm::set_error("out must not be NULL"), PM_ERR_ARG;
+        *out = nullptr;
+        return pm::batch_create(descs, params, n_scenes, opts, (hipStream_t)stream, out);
+    })
+}
+
+int pm_batch_destroy(pm_batch *b) { PM_GUARD({ return pm::batch_destroy(b); }) }
+
+int pm_batch_iterate(pm_batch *b, int32_t n_iter, void *stream) {
+    PM_GUARD({ return pm::batch_iterate(b, n_iter, (hipStream_t)stream); })
+}
+
+int pm_batch_resolve(pm_batch *b, float *const *images, void *stream) {
+    PM_GUARD({ return pm::batch_resolve(b, images, (hipStream_t)stream); })
+}
+
+int pm_batch_status(pm_batch *b, void *stream) { PM_GUARD({ return pm::batch_status(b, (hipStream_t)stream); }) }
+
+int pm_batch_get_info(const pm_batch *b, pm_batch_info *info) { PM_GUARD({ return pm::batch_info(b, info); }) }
+
+int pm_batch_get_views(pm_batch *b, int32_t scene, pm_sppm_views *v) {
+    PM_GUARD({ return pm::batch_views(b, scene, v); })
+}
+
+int pm_render_batch(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
+                    int32_t K, float *const *images, const pm_batch_opts *opts, void *stream) {
+    PM_GUARD({
+        if (K < 1 || !images) return pm::set_error("K must be >= 1 and images non-NULL"), PM_ERR_ARG;
+        pm_batch *b = nullptr;
+        hipStream_t st = (hipStream_t)stream;
+        int rc = pm::batch_create(descs, params, n_scenes, opts, st, &b);
+        if (rc) return rc;
+        if (!(rc = pm::batch_iterate(b, K, st)))
+            if (!(rc = pm::batch_resolve(b, images, st))) rc = pm::batch_status(b, st);
+        (void)hipStreamSynchronize(st);
+        pm::batch_destroy(b);
+        return rc;
+    })
+}
+
 }  // extern "C"

@@ -15,4 +15,13 @@ int sppm_status(pm_sppm *s, hipStream_t st);
 int sppm_views(pm_sppm *s, pm_sppm_views *v);
 int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par, double *grad, hipStream_t st);
 
+int batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n,
+                 const pm_batch_opts *opts, hipStream_t st, pm_batch **out);
+int batch_destroy(pm_batch *b);
+int batch_iterate(pm_batch *b, int32_t n, hipStream_t st);
+int batch_resolve(pm_batch *b, float *const *images, hipStream_t st);
+int batch_status(pm_batch *b, hipStream_t st);
+int batch_info(const pm_batch *b, pm_batch_info *info);
+int batch_views(pm_batch *b, int32_t scene, pm_sppm_views *v);
+
 }  // namespace pm

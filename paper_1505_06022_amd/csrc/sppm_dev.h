@@ -1,0 +1,360 @@
+// Device side of one SPPM iteration (Sec. 2), written per element so that the
+// single-scene kernels and the batched persistent kernels share it.
+#pragma once
+#include "pm.h"
+#include "pm_device.h"
+
+namespace pmd {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 16;                  // per thread
+constexpr int kScanTile = kBlock * kScanItems;  // buckets per scan tile
+constexpr int kMaxAdjMat = 256;
+
+struct SceneDev {
+    Bvh bvh;
+    const int32_t *mat_type;
+    const float *mat_rho, *mat_q, *mat_Le, *mat_ior;
+    const uint32_t *emit_pos;  // triangle-array position of each emitter (original order)
+    const double *emit_cdf;
+    int32_t n_emit;
+    double power;
+    float eps;
+    float lo[3];
+    V3 cpos, cf, cr, cu;
+    float tanh_fov, aspect;
+    int32_t W, H;
+};
+
+// One scene's parameters and device buffers.  Bucket arrays may be shared by
+// several scenes: this scene owns buckets [table_off, table_off + mask + 1).
+struct SppmDev {
+    SceneDev sc;
+    uint64_t seed;
+    int32_t max_depth, max_bounces;
+    uint32_t n_paths, cap;
+    float phi0;
+    double alpha, scale, inv_scale;
+    int64_t P;
+    uint32_t mask, table_off;
+    float4 *hp_pos, *hp_nrm;  // (x, W*rho/pi), (n toward the eye, material bits | -1)
+    double *N, *R2, *tau, *D;
+    float4 *store;            // [cap][2]: (x, phi), (w, path << 5 | bounce)
+    uint32_t *counters;       // [0] photons stored, [1] overflow flag
+    unsigned long long *r2max;
+    uint32_t *M;
+    unsigned long long *Phi;
+};
+
+// ---------------------------------------------------------------------------
+// Eye pass: a jittered pinhole ray followed through mirror and glass to the
+// first diffuse (rho > 0) surface, which becomes the pixel's hit point;
+// directly seen emission is accumulated into D (skipped when replaying).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p, bool accumulate_D) {
+    const SceneDev &sc = d.sc;
+    int32_t px = (int32_t)(p % sc.W), py = (int32_t)(p / sc.W);
+    Rng g = rng_seed(d.seed, kKindEye, k, (uint64_t)p);
+    float j0 = rng_next(g), j1 = rng_next(g);
+    float fx = ((float)px + j0) / (float)sc.W;
+    float fy = ((float)py + j1) / (float)sc.H;
+    float sx = (2.0f * fx - 1.0f) * (sc.tanh_fov * sc.aspect);
+    float sy = (1.0f - 2.0f * fy) * sc.tanh_fov;
+    V3 dir = vnorm(v3((sc.cf.x + sx * sc.cr.x) + sy * sc.cu.x, (sc.cf.y + sx * sc.cr.y) + sy * sc.cu.y,
+                      (sc.cf.z + sx * sc.cr.z) + sy * sc.cu.z));
+    V3 org = sc.cpos;
+    float tmin = 0.0f, thr = 1.0f;
+    int32_t excl = -1;
+    double dadd = 0.0;
+    float4 pos = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 nrm = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    TraceStats st;
+    for (int depth = 0; depth < d.max_depth; ++depth) {
+        float t;
+        uint32_t kp;
+        int32_t h = closest_hit<false>(sc.bvh, link_set(dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st);
+        if (h < 0) break;
+        V3 x = vray(org, t, dir);
+        Tri tr = load_tri(sc.bvh.tris, kp);
+        V3 n = tri_normal(tr);
+        uint32_t m = tr.mat;
+        bool front = vdot(dir, n) < 0.0f;
+        float Le = sc.mat_Le[m];
+        if (Le > 0.0f && front) dadd += (double)(thr * Le);
+        int type = sc.mat_type[m];
+        if (type == PM_MAT_DIFFUSE) {
+            float rho = sc.mat_rho[m];
+            if (rho > 0.0f) {
+                V3 nh = front ? n : vneg(n);
+                pos = make_float4(x.x, x.y, x.z, (thr * rho) * kInvPiF);
+                nrm = make_float4(nh.x, nh.y, nh.z, __uint_as_float(m));
+            }
+            break;
+        } else if (type == PM_MAT_MIRROR) {
+            dir = reflect(dir, n);
+        } else {
+            dir = glass_dir(dir, n, sc.mat_ior[m], g);
+        }
+        org = x;
+        tmin = sc.eps;
+        excl = h;
+    }
+    d.hp_pos[p] = pos;
+    d.hp_nrm[p] = nrm;
+    if (accumulate_D) d.D[p] += dadd;
+}
+
+// Wave-aggregated append: one atomic per wavefront for all lanes currently
+// active at this call site (they must share `counter`).  Returns the slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter) {
+    uint64_t mask = __ballot(1);
+    uint32_t lane_rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane_rank == 0) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    return base + lane_rank;
+}
+
+// ---------------------------------------------------------------------------
+// Photon path n (Sec. 2, Sec. 3.3): emitter by power, point by folding,
+// cosine direction, then bounces until a miss, an absorbing surface, Russian
+// roulette or the cap; a photon is stored at every diffuse hit.
+// kRecord (adjoint replay): row n of mat_tab gets, per bounce, the material of
+// a stored photon (0xff: none at that bounce; 0xfe: the path ended), and the
+// matching entries of adj_tab are cleared for the adjoint gather.
+// ---------------------------------------------------------------------------
+template <bool kRecord>
+__device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32_t n, uint8_t *__restrict__ mat_tab,
+                                            double *__restrict__ adj_tab) {
+    const SceneDev &sc = d.sc;
+    const int32_t mb = d.max_bounces;
+    uint8_t *row = kRecord ? mat_tab + (size_t)n * mb : nullptr;
+    if (sc.n_emit == 0) {
+        if (kRecord) row[0] = 0xfeu;
+        return;
+    }
+    Rng g = rng_seed(d.seed, kKindPhoton, k, (uint64_t)n);
+    float u0 = rng_next(g);
+    double target = (double)u0 * sc.power;
+    // first emitter whose cumulative power exceeds the target
+    int32_t lo = 0, hi = sc.n_emit - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (target < sc.emit_cdf[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    Tri et = load_tri(sc.bvh.tris, sc.emit_pos[lo]);
+    float u1 = rng_next(g), u2 = rng_next(g);
+    if (u1 + u2 > 1.0f) {
+        u1 = 1.0f - u1;
+        u2 = 1.0f - u2;
+    }
+    V3 org = v3((et.v0.x + u1 * et.e1.x) + u2 * et.e2.x, (et.v0.y + u1 * et.e1.y) + u2 * et.e2.y,
+                (et.v0.z + u1 * et.e1.z) + u2 * et.e2.z);
+    V3 dir = cosine_dir(tri_normal(et), g);
+    float phi = d.phi0;
+    int32_t excl = et.id;
+    TraceStats st;
+    int last = -1;  // last bounce written to the row
+    for (int b = 0; b < mb; ++b) {
+        float t;
+        uint32_t kp;
+        int32_t h = closest_hit<false>(sc.bvh, link_set(dir), org, dir, sc.eps, __builtin_inff(), excl, t, kp, st);
+        if (h < 0) break;
+        V3 x = vray(org, t, dir);
+        Tri tr = load_tri(sc.bvh.tris, kp);
+        V3 nrm = tri_normal(tr);
+        uint32_t m = tr.mat;
+        int type = sc.mat_type[m];
+        if (kRecord) {
+            row[b] = 0xffu;
+            last = b;
+        }
+        if (type == PM_MAT_DIFFUSE) {
+            float rho = sc.mat_rho[m];
+            if (!(rho > 0.0f)) break;
+            if (kRecord) {
+                row[b] = (uint8_t)m;
+                adj_tab[(size_t)n * mb + b] = 0.0;
+            }
+            uint32_t slot = wave_append(&d.counters[0]);
+            if (slot < d.cap) {
+                d.store[2 * (size_t)slot] = make_float4(x.x, x.y, x.z, phi);
+                d.store[2 * (size_t)slot + 1] = make_float4(dir.x, dir.y, dir.z, __uint_as_float((n << 5) | (uint32_t)b));
+            } else {
+                atomicOr(&d.counters[1], 1u);
+            }
+            float u = rng_next(g);
+            float q = sc.mat_q[m];
+            if (!(u < q)) break;
+            phi = (phi * rho) / q;
+            V3 ns = vdot(dir, nrm) < 0.0f ? nrm : vneg(nrm);
+            dir = cosine_dir(ns, g);
+        } else if (type == PM_MAT_MIRROR) {
+            dir = reflect(dir, nrm);
+        } else {
+            dir = glass_dir(dir, nrm, sc.mat_ior[m], g);
+        }
+        org = x;
+        excl = h;
+    }
+    if (kRecord && last + 1 < mb) row[last + 1] = 0xfeu;
+}
+
+// ---------------------------------------------------------------------------
+// Hashed grid (exact): cell edge h = 2 R_max (1 + 2^-10), so the 2x2x2 cells
+// around a hit point cover its disc; cells hash (Teschner et al. 2003) into a
+// power-of-two table; photons are counting-sorted by bucket.
+// ---------------------------------------------------------------------------
+struct Grid {
+    float lo[3];
+    float inv_h;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ uint32_t cell_hash(int32_t ix, int32_t iy, int32_t iz, uint32_t mask) {
+    return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
+}
+
+__device__ __forceinline__ Grid make_grid(const SppmDev &d) {
+    double r2 = __longlong_as_double((long long)*d.r2max);
+    double h = 2.0 * sqrt(r2) * (1.0 + 1.0 / 1024.0);
+    Grid gr;
+    gr.lo[0] = d.sc.lo[0];
+    gr.lo[1] = d.sc.lo[1];
+    gr.lo[2] = d.sc.lo[2];
+    gr.inv_h = h > 0.0 ? (float)(1.0 / h) : 0.0f;
+    gr.mask = d.mask;
+    return gr;
+}
+
+__device__ __forceinline__ uint32_t photon_bucket(const Grid &gr, float x, float y, float z) {
+    int32_t ix = (int32_t)floorf((x - gr.lo[0]) * gr.inv_h);
+    int32_t iy = (int32_t)floorf((y - gr.lo[1]) * gr.inv_h);
+    int32_t iz = (int32_t)floorf((z - gr.lo[2]) * gr.inv_h);
+    return cell_hash(ix, iy, iz, gr.mask);
+}
+
+__device__ __forceinline__ uint32_t stored_photons(const SppmDev &d) { return min(d.counters[0], d.cap); }
+
+// Largest squared radius among valid hit points (positive doubles order like
+// their bit patterns).  Called by every lane of a wave (in_range false for
+// padding lanes); the wave's lanes must belong to one scene.
+__device__ __forceinline__ void rmax_elem(const SppmDev &d, const double *__restrict__ R2src, int64_t p, bool in_range) {
+    unsigned long long v = 0ull;
+    if (in_range && __float_as_int(d.hp_nrm[p].w) >= 0) v = (unsigned long long)__double_as_longlong(R2src[p]);
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicMax(d.r2max, v);
+}
+
+__device__ __forceinline__ void count_elem(const SppmDev &d, const Grid &gr, uint32_t j, uint32_t *__restrict__ cell_count) {
+    float4 a = d.store[2 * (size_t)j];
+    atomicAdd(&cell_count[d.table_off + photon_bucket(gr, a.x, a.y, a.z)], 1u);
+}
+
+__device__ __forceinline__ void scatter_elem(const SppmDev &d, const Grid &gr, uint32_t j, uint32_t *__restrict__ fill,
+                                             float4 *__restrict__ sorted) {
+    float4 a = d.store[2 * (size_t)j];
+    float4 b = d.store[2 * (size_t)j + 1];
+    uint32_t pos = atomicAdd(&fill[d.table_off + photon_bucket(gr, a.x, a.y, a.z)], 1u);
+    sorted[2 * (size_t)pos] = a;
+    sorted[2 * (size_t)pos + 1] = b;
+}
+
+// Visit every photon of the (deduplicated) buckets of the 8 cells around a
+// hit point that is inside its disc (squared distance < R^2, float32 distance
+// compared in double) and arrived from the eye's side.
+template <typename F>
+__device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const Grid &gr, float4 hx, float4 hn, double r2,
+                                                       const uint32_t *__restrict__ start,
+                                                       const float4 *__restrict__ sorted, F &&f) {
+    int32_t bx = (int32_t)floorf((hx.x - gr.lo[0]) * gr.inv_h - 0.5f);
+    int32_t by = (int32_t)floorf((hx.y - gr.lo[1]) * gr.inv_h - 0.5f);
+    int32_t bz = (int32_t)floorf((hx.z - gr.lo[2]) * gr.inv_h - 0.5f);
+    uint32_t seen[8];
+    for (int c = 0; c < 8; ++c) {
+        uint32_t hb = cell_hash(bx + (c & 1), by + ((c >> 1) & 1), bz + (c >> 2), gr.mask);
+        bool dup = false;
+        for (int e = 0; e < c; ++e) dup |= (seen[e] == hb);
+        seen[c] = hb;
+        if (dup) continue;
+        uint32_t q0 = start[d.table_off + hb], q1 = start[d.table_off + hb + 1];
+        for (uint32_t q = q0; q < q1; ++q) {
+            float4 a = sorted[2 * (size_t)q];
+            float dx = a.x - hx.x, dy = a.y - hx.y, dz = a.z - hx.z;
+            float d2 = (dx * dx + dy * dy) + dz * dz;
+            if ((double)d2 < r2) {
+                float4 b = sorted[2 * (size_t)q + 1];
+                float c2 = (b.x * hn.x + b.y * hn.y) + b.z * hn.z;
+                if (c2 < 0.0f) f(a, b);
+            }
+        }
+    }
+}
+
+// Range query of one hit point: M photons and their flux, each term rounded to
+// 2^-shift fixed point and summed as integers (order independent).
+__device__ __forceinline__ void gather_elem(const SppmDev &d, const Grid &gr, int64_t p, const uint32_t *__restrict__ start,
+                                            const float4 *__restrict__ sorted) {
+    float4 hn = d.hp_nrm[p];
+    uint32_t M = 0;
+    unsigned long long F = 0ull;
+    if (__float_as_int(hn.w) >= 0) {
+        float4 hx = d.hp_pos[p];
+        double wk = (double)hx.w;
+        const double scale = d.scale;
+        for_each_photon_in_disc(d, gr, hx, hn, d.R2[p], start, sorted, [&](const float4 &a, const float4 &) {
+            M++;
+            F += (unsigned long long)rint((wk * (double)a.w) * scale);
+        });
+    }
+    d.M[p] = M;
+    d.Phi[p] = F;
+}
+
+// Progressive update (radius reduction and flux rescaling of SPPM); hist
+// (optional) receives the radius used in this iteration.
+__device__ __forceinline__ void update_elem(const SppmDev &d, int64_t p, double *__restrict__ hist) {
+    if (hist) hist[p] = d.R2[p];
+    uint32_t Mi = d.M[p];
+    if (__float_as_int(d.hp_nrm[p].w) < 0 || Mi == 0) return;
+    double m = (double)Mi;
+    double n0 = d.N[p];
+    double nn = n0 + d.alpha * m;
+    double ratio = nn / (n0 + m);
+    d.R2[p] = d.R2[p] * ratio;
+    d.tau[p] = (d.tau[p] + (double)d.Phi[p] * d.inv_scale) * ratio;
+    d.N[p] = nn;
+}
+
+__device__ __forceinline__ float resolve_elem(const SppmDev &d, int64_t p, int32_t K) {
+    double L = d.tau[p] / ((kPiD * d.R2[p]) * (double)K) + d.D[p] / (double)K;
+    return (float)L;
+}
+
+// Block-wide exclusive scan of one value per thread (kBlock threads).
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t *lds_wave, uint32_t &total) {
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds_wave[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        uint32_t s = lds_wave[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    return before + x - v;
+}
+
+}  // namespace pmd

@@ -1,0 +1,52 @@
+// Internal state of an SPPM handle (shared by the single-scene driver and the
+// batched driver).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "runtime.h"
+#include "sppm_dev.h"
+
+struct pm_sppm {
+    pm_sppm_params prm{};
+    pm_bvh *bvh = nullptr;
+    bool own_bvh = false;
+    pmd::SppmDev dev{};  // device view passed to the kernels
+    int64_t P = 0;
+    int32_t K = 0;
+    uint32_t cap = 0;
+    uint32_t table_bits = 0;
+    float phi0 = 0.0f;
+    // device buffers
+    int32_t *mat_type = nullptr;
+    float *mat_f = nullptr;  // rho | q | Le | ior, each n_mat
+    uint32_t *emit_pos = nullptr;
+    double *emit_cdf = nullptr;
+    double *N = nullptr, *R2 = nullptr, *tau = nullptr, *D = nullptr;
+    float4 *hp_pos = nullptr, *hp_nrm = nullptr;
+    float4 *store = nullptr, *sorted = nullptr;
+    uint32_t *counters = nullptr;  // [0] photons stored, [1] overflow flag
+    unsigned long long *r2max = nullptr;
+    // bucket arrays (absent for a batch member, which uses the batch's)
+    uint32_t *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *bsum = nullptr;
+    uint32_t *M = nullptr;
+    unsigned long long *Phi = nullptr;
+    // adjoint recording / replay buffers (record_iterations > 0)
+    int32_t rec_iters = 0;
+    int32_t n_mat = 0;
+    double le_single = 0.0;  // Le of the single emitting material, 0 if not exactly one
+    double *R2_hist = nullptr;    // [rec_iters][P] radius used in each iteration
+    double *adj_tab = nullptr;    // [n_photons][max_bounces] photon sensitivities
+    uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
+    double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
+    int32_t *d_pmat = nullptr;    // [256] parameter materials
+};
+
+namespace pm {
+
+// own_grid = false: no bucket arrays (a batch member uses the batch's arrays).
+int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t st, bool own_grid, pm_sppm **out);
+void sppm_free(pm_sppm *s);
+// Back to the initial state (N = 0, R^2 = r0^2, tau = 0, D = 0, K = 0).
+int sppm_reset(pm_sppm *s, hipStream_t st);
+
+}  // namespace pm

@@ -376,3 +376,27 @@ def small_soup(n_tri: int, seed: int, scale=1.0, spread=0.3) -> Scene:
     s.verts = np.ascontiguousarray(v)
     s.tri_mat = np.zeros(n_tri, np.uint32)
     return s
+
+
+def batch_workload(n_scenes=32, seed=5, tri_range=(1000, 200000), side_range=(128, 512), photon_log2=(16, 20)):
+    """Scenes of uneven size for batched rendering: triangle counts log-uniform
+    in tri_range (procedural room + heightfield + spheres), square images with
+    sides log-uniform in side_range, photons per iteration 2^U{photon_log2}.
+
+    Returns a list of (scene, n_photons, r0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_scenes):
+        T = float(np.exp(rng.uniform(np.log(tri_range[0]), np.log(tri_range[1]))))
+        side = int(round(float(np.exp(rng.uniform(np.log(side_range[0]), np.log(side_range[1]))))))
+        Np = 1 << int(rng.integers(photon_log2[0], photon_log2[1] + 1))
+        level = 0
+        while level < 6 and 80 * 4 ** (level + 1) <= T / 2:
+            level += 1
+        cells = max(2, int(round(np.sqrt(max(T - 80 * 4 ** level - 12, 8) / 2))))
+        sc = procedural_scene(width=side, height=side, hf_cells=cells, sphere_level=level, glass_level=level,
+                              seed=seed * 1000 + i)
+        v = sc.verts.reshape(-1, 3)
+        diag = float(np.linalg.norm(v.max(0) - v.min(0)))
+        out.append((sc, Np, 0.05 * diag * 64 / side))
+    return out

@@ -201,3 +201,13 @@ def test_host_bvh_box_scene_and_soup_statistics():
     assert info["depth"] < 64 and info["sah_cost"] > 0
     # storage: 6 link sets x 16 B per node + 48 B per triangle
     assert info["device_bytes"] == 6 * 16 * info["n_nodes"] + 48 * info["n_tri"]
+
+
+def test_binding_classes_expose_the_abi():
+    for name in ("iterate", "resolve", "status", "views", "adjoint", "destroy"):
+        assert callable(getattr(api.Sppm, name, None)), name
+    for name in ("iterate", "resolve", "status", "info", "views", "destroy"):
+        assert callable(getattr(api.Batch, name, None)), name
+    for fn in ("build_bvh", "build_bvh_host", "trace_rays", "sppm_create", "render", "render_batch",
+               "sppm_render_diff"):
+        assert callable(getattr(api, fn, None)), fn
