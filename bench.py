@@ -163,7 +163,20 @@ def sppm_bench(args, torch, api, scenes):
     s.status()
     n_stored = int(s.views()["photon_count"][0].item())
     s.destroy()
-    return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored,
+    variants = {}
+    for name, kw in (("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
+                     ("regen_refill16", dict(photon_kernel=2, refill=16)),
+                     ("regen_refill32", dict(photon_kernel=2, refill=32))):
+        sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, **kw))
+        sv.iterate(1)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sv.iterate(3)
+        e1.record(st)
+        torch.cuda.synchronize()
+        variants[name] = round(e0.elapsed_time(e1) / 3, 3)
+        sv.destroy()
+    return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
                 workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
@@ -179,17 +192,19 @@ def adjoint_bench(args, torch, api, scenes):
     s = api.Sppm(sc, p)
     st = torch.cuda.current_stream()
     target = torch.zeros((720, 1280), dtype=torch.float32, device="cuda")
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    g = 2.0 * (target - target) / target.numel()     # loads the loss kernels outside the timing
     torch.cuda.synchronize()
     ev[0].record(st)
     s.iterate(K)
     img = s.resolve()
     ev[1].record(st)
     g = 2.0 * (img - target) / img.numel()
-    grad = s.adjoint(g, sc.albedo_params)
     ev[2].record(st)
+    grad = s.adjoint(g, sc.albedo_params)
+    ev[3].record(st)
     torch.cuda.synchronize()
-    t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
     s.status()
     s.destroy()
     return {"fwd_ms": round(t_fwd, 2), "adjoint_ms": round(t_adj, 2),
@@ -312,7 +327,8 @@ def main():
     if not args.no_sppm:
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
-                       "stored_photons": sp["n_stored"], "workload": sp["workload"]}
+                       "stored_photons": sp["n_stored"], "workload": sp["workload"],
+                       "iteration_ms_by_photon_kernel": sp["variants"]}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, torch, api, scenes)
     if not args.no_batch:

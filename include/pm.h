@@ -182,7 +182,15 @@ typedef struct {
                                   up to this many iterations (8 B per pixel
                                   per iteration, plus 9 B x n_photons x
                                   max_photon_bounces of replay scratch) */
+    int32_t photon_kernel;    /* PM_PHOTON_*: 0 = default (regeneration) */
+    int32_t refill;           /* regeneration: idle lanes of a wave that
+                                 trigger taking new paths (1..64; 0 = 16) */
 } pm_sppm_params;
+
+/* Photon pass scheduling (results are identical): one lane traces one whole
+ * path, or persistent lanes trace one bounce per step and switch to a new path
+ * when theirs ends (the paper's photon path regeneration, Sec. 3.3). */
+enum { PM_PHOTON_AUTO = 0, PM_PHOTON_PER_PATH = 1, PM_PHOTON_REGEN = 2 };
 
 /* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)
  * and allocates the per-pixel state (N = 0, R^2 = r0^2, tau = 0, D = 0).

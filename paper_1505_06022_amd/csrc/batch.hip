@@ -104,6 +104,7 @@ __global__ void k_batch_begin(BatchDev b) {
     if (threadIdx.x < kNumStages) b.queue[threadIdx.x] = 0u;
     for (int s = threadIdx.x; s < b.S; s += blockDim.x) {
         b.scenes[s].counters[0] = 0u;
+        b.scenes[s].counters[2] = 0u;
         *b.scenes[s].r2max = 0ull;
     }
 }

@@ -28,10 +28,14 @@ __global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint8_
     if (n < d.n_paths) photon_elem<kRecord>(d, k, n, mat_tab, adj_tab);
 }
 
-// Frame setup: clear the photon counter and the R_max accumulator.
+// Persistent photon lanes with path regeneration.
+__global__ __launch_bounds__(kBlock) void k_photon_regen(SppmDev d, uint32_t k) { photon_regen_loop(d, k, d.refill); }
+
+// Frame setup: clear the photon and path counters and the R_max accumulator.
 __global__ void k_begin(SppmDev d) {
     if (threadIdx.x == 0) {
         d.counters[0] = 0u;
+        d.counters[2] = 0u;
         *d.r2max = 0ull;
     }
 }
@@ -171,10 +175,14 @@ __global__ void k_fill_f64(double *p, int64_t n) {
     if (i < n) p[i] = 0.0;
 }
 
-__global__ void k_collect_grad(const double *__restrict__ grad_mat, const int32_t *__restrict__ pmat, int32_t n_par,
+struct ParamMats {
+    uint8_t m[kMaxAdjMat];
+};
+
+__global__ void k_collect_grad(const double *__restrict__ grad_mat, ParamMats pm, int32_t n_par,
                                const double *__restrict__ le_sum, double inv_Le, double *__restrict__ out) {
     int i = threadIdx.x;
-    if (i < n_par) out[i] = grad_mat[pmat[i]];
+    if (i < n_par) out[i] = grad_mat[pm.m[i]];
     if (i == n_par) out[i] = *le_sum * inv_Le;
 }
 
@@ -201,8 +209,7 @@ void sppm_free(pm_sppm *s) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
-                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
-                    s->d_pmat};
+                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (s->own_bvh && s->bvh) {
@@ -243,6 +250,8 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->store_factor < 1 || p->n_photons * p->store_factor > (int64_t(1) << 30))
         return set_error("store_factor must be >= 1 and the store below 2^30 photons"), PM_ERR_ARG;
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
+    if (p->photon_kernel < 0 || p->photon_kernel > 2 || p->refill < 0 || p->refill > 64)
+        return set_error("photon_kernel must be 0..2 and refill 0..64"), PM_ERR_ARG;
     if (p->record_iterations < 0 || p->record_iterations > 100000)
         return set_error("record_iterations must be in [0, 100000]"), PM_ERR_ARG;
     if (p->record_iterations > 0 && d->n_mat > kMaxAdjMat)
@@ -330,13 +339,13 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     PM_HIPF(hipMalloc(&s->M, sizeof(uint32_t) * s->P));
     PM_HIPF(hipMalloc(&s->Phi, sizeof(unsigned long long) * s->P));
     s->n_mat = nm;
+    s->rho_host.assign(d->mat_rho, d->mat_rho + nm);
     s->rec_iters = p->record_iterations;
     if (s->rec_iters > 0) {
         PM_HIPF(hipMalloc(&s->R2_hist, sizeof(double) * (size_t)s->rec_iters * s->P));
         PM_HIPF(hipMalloc(&s->adj_tab, sizeof(double) * (size_t)p->n_photons * p->max_photon_bounces));
         PM_HIPF(hipMalloc(&s->mat_tab, (size_t)p->n_photons * p->max_photon_bounces));
         PM_HIPF(hipMalloc(&s->grad_mat, sizeof(double) * (nm + 1)));
-        PM_HIPF(hipMalloc(&s->d_pmat, sizeof(int32_t) * kMaxAdjMat));
     }
     {
         int n_emit_mat = 0;
@@ -408,6 +417,15 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.P = s->P;
     dv.mask = T - 1u;
     dv.table_off = 0;
+    dv.photon_kernel = p->photon_kernel == PM_PHOTON_PER_PATH ? PM_PHOTON_PER_PATH : PM_PHOTON_REGEN;
+    dv.refill = p->refill > 0 ? (uint32_t)p->refill : 16u;
+    {
+        int dev = 0, cus = 0, per_cu = 0;
+        PM_HIPF(hipGetDevice(&dev));
+        PM_HIPF(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_regen, kBlock, 0));
+        s->regen_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+    }
     dv.hp_pos = s->hp_pos;
     dv.hp_nrm = s->hp_nrm;
     dv.N = s->N;
@@ -457,8 +475,11 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
         hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, k, 1);
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
-        hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
-                           (double *)nullptr);
+        if (d.photon_kernel == PM_PHOTON_REGEN)
+            hipLaunchKernelGGL(k_photon_regen, dim3(s->regen_grid), dim3(kBlock), 0, st, d, k);
+        else
+            hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
+                               (double *)nullptr);
         hipLaunchKernelGGL(k_rmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, (const double *)s->R2);
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
         launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
@@ -498,11 +519,9 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
     if (s->K > s->rec_iters)
         return set_error("the forward iterations were not recorded: set record_iterations >= K"), PM_ERR_STATE;
     if (n_par >= kMaxAdjMat) return set_error("too many parameters"), PM_ERR_ARG;
-    std::vector<float> rho(s->n_mat);
-    PM_HIP(hipMemcpy(rho.data(), s->mat_f, sizeof(float) * s->n_mat, hipMemcpyDeviceToHost));
     for (int32_t i = 0; i < n_par; ++i) {
         if (pmat[i] < 0 || pmat[i] >= s->n_mat) return set_error("parameter material out of range"), PM_ERR_ARG;
-        if (!(rho[pmat[i]] > 0.0f)) return set_error("albedo parameters must have rho > 0"), PM_ERR_ARG;
+        if (!(s->rho_host[pmat[i]] > 0.0f)) return set_error("albedo parameters must have rho > 0"), PM_ERR_ARG;
     }
     const uint32_t T = 1u << s->table_bits;
     const uint32_t np = (uint32_t)s->prm.n_photons;
@@ -510,7 +529,8 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
     const uint32_t ph_blocks = std::min<uint32_t>(blocks_for(s->cap), 256u * 64u);
     const double K = (double)s->K;
     const SppmDev &d = s->dev;
-    PM_HIP(hipMemcpyAsync(s->d_pmat, pmat, sizeof(int32_t) * std::max(1, n_par), hipMemcpyHostToDevice, st));
+    ParamMats pms;
+    for (int32_t i = 0; i < n_par; ++i) pms.m[i] = (uint8_t)pmat[i];
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(s->n_mat + 1)), dim3(kBlock), 0, st, s->grad_mat,
                        (int64_t)s->n_mat + 1);
     for (int32_t k = 0; k < s->K; ++k) {
@@ -532,7 +552,7 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
         PM_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_le_grad, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, K, g, s->grad_mat + s->n_mat);
-    hipLaunchKernelGGL(k_collect_grad, dim3(1), dim3(kMaxAdjMat), 0, st, s->grad_mat, s->d_pmat, n_par,
+    hipLaunchKernelGGL(k_collect_grad, dim3(1), dim3(kMaxAdjMat), 0, st, s->grad_mat, pms, n_par,
                        s->grad_mat + s->n_mat, s->le_single > 0.0 ? 1.0 / s->le_single : 0.0, grad);
     PM_HIP(hipGetLastError());
     return PM_OK;

@@ -37,10 +37,12 @@ struct SppmDev {
     double alpha, scale, inv_scale;
     int64_t P;
     uint32_t mask, table_off;
+    int32_t photon_kernel;    // PM_PHOTON_* (resolved: per path or regenerating)
+    uint32_t refill;          // regeneration: idle lanes that trigger a refill
     float4 *hp_pos, *hp_nrm;  // (x, W*rho/pi), (n toward the eye, material bits | -1)
     double *N, *R2, *tau, *D;
     float4 *store;            // [cap][2]: (x, phi), (w, path << 5 | bounce)
-    uint32_t *counters;       // [0] photons stored, [1] overflow flag
+    uint32_t *counters;       // [0] photons stored, [1] overflow flag, [2] next path (regeneration)
     unsigned long long *r2max;
     uint32_t *M;
     unsigned long long *Phi;
@@ -119,23 +121,29 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter) {
 // ---------------------------------------------------------------------------
 // Photon path n (Sec. 2, Sec. 3.3): emitter by power, point by folding,
 // cosine direction, then bounces until a miss, an absorbing surface, Russian
-// roulette or the cap; a photon is stored at every diffuse hit.
-// kRecord (adjoint replay): row n of mat_tab gets, per bounce, the material of
-// a stored photon (0xff: none at that bounce; 0xfe: the path ended), and the
-// matching entries of adj_tab are cleared for the adjoint gather.
+// roulette or the cap; a photon is stored at every diffuse hit.  The path is
+// split into emission and single bounces so that a lane can switch to a new
+// path as soon as its path ends (regeneration).
 // ---------------------------------------------------------------------------
-template <bool kRecord>
-__device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32_t n, uint8_t *__restrict__ mat_tab,
-                                            double *__restrict__ adj_tab) {
+struct PhotonPath {
+    Rng g;
+    V3 org, dir;
+    float phi;
+    int32_t excl;
+    uint32_t n;
+    int32_t b;     // next bounce index
+    int32_t last;  // last bounce written to the adjoint row (recording only)
+};
+
+// Returns false when the scene has no emitter (the path is empty).
+__device__ __forceinline__ bool photon_emit(const SppmDev &d, uint32_t k, uint32_t n, PhotonPath &P) {
     const SceneDev &sc = d.sc;
-    const int32_t mb = d.max_bounces;
-    uint8_t *row = kRecord ? mat_tab + (size_t)n * mb : nullptr;
-    if (sc.n_emit == 0) {
-        if (kRecord) row[0] = 0xfeu;
-        return;
-    }
-    Rng g = rng_seed(d.seed, kKindPhoton, k, (uint64_t)n);
-    float u0 = rng_next(g);
+    P.n = n;
+    P.b = 0;
+    P.last = -1;
+    if (sc.n_emit == 0) return false;
+    P.g = rng_seed(d.seed, kKindPhoton, k, (uint64_t)n);
+    float u0 = rng_next(P.g);
     double target = (double)u0 * sc.power;
     // first emitter whose cumulative power exceeds the target
     int32_t lo = 0, hi = sc.n_emit - 1;
@@ -145,61 +153,115 @@ __device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32
         else lo = mid + 1;
     }
     Tri et = load_tri(sc.bvh.tris, sc.emit_pos[lo]);
-    float u1 = rng_next(g), u2 = rng_next(g);
+    float u1 = rng_next(P.g), u2 = rng_next(P.g);
     if (u1 + u2 > 1.0f) {
         u1 = 1.0f - u1;
         u2 = 1.0f - u2;
     }
-    V3 org = v3((et.v0.x + u1 * et.e1.x) + u2 * et.e2.x, (et.v0.y + u1 * et.e1.y) + u2 * et.e2.y,
-                (et.v0.z + u1 * et.e1.z) + u2 * et.e2.z);
-    V3 dir = cosine_dir(tri_normal(et), g);
-    float phi = d.phi0;
-    int32_t excl = et.id;
+    P.org = v3((et.v0.x + u1 * et.e1.x) + u2 * et.e2.x, (et.v0.y + u1 * et.e1.y) + u2 * et.e2.y,
+               (et.v0.z + u1 * et.e1.z) + u2 * et.e2.z);
+    P.dir = cosine_dir(tri_normal(et), P.g);
+    P.phi = d.phi0;
+    P.excl = et.id;
+    return true;
+}
+
+// One bounce of a live path; returns true while the path continues.
+// kRecord (adjoint replay): row n of mat_tab gets, per bounce, the material of
+// a stored photon (0xff: none at that bounce), and the matching entries of
+// adj_tab are cleared for the adjoint gather; photon_finish marks the end.
+template <bool kRecord>
+__device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, uint8_t *__restrict__ mat_tab,
+                                              double *__restrict__ adj_tab) {
+    const SceneDev &sc = d.sc;
+    const int32_t mb = d.max_bounces;
+    const int b = P.b;
+    float t;
+    uint32_t kp;
     TraceStats st;
-    int last = -1;  // last bounce written to the row
-    for (int b = 0; b < mb; ++b) {
-        float t;
-        uint32_t kp;
-        int32_t h = closest_hit<false>(sc.bvh, link_set(dir), org, dir, sc.eps, __builtin_inff(), excl, t, kp, st);
-        if (h < 0) break;
-        V3 x = vray(org, t, dir);
-        Tri tr = load_tri(sc.bvh.tris, kp);
-        V3 nrm = tri_normal(tr);
-        uint32_t m = tr.mat;
-        int type = sc.mat_type[m];
-        if (kRecord) {
-            row[b] = 0xffu;
-            last = b;
-        }
-        if (type == PM_MAT_DIFFUSE) {
-            float rho = sc.mat_rho[m];
-            if (!(rho > 0.0f)) break;
-            if (kRecord) {
-                row[b] = (uint8_t)m;
-                adj_tab[(size_t)n * mb + b] = 0.0;
-            }
-            uint32_t slot = wave_append(&d.counters[0]);
-            if (slot < d.cap) {
-                d.store[2 * (size_t)slot] = make_float4(x.x, x.y, x.z, phi);
-                d.store[2 * (size_t)slot + 1] = make_float4(dir.x, dir.y, dir.z, __uint_as_float((n << 5) | (uint32_t)b));
-            } else {
-                atomicOr(&d.counters[1], 1u);
-            }
-            float u = rng_next(g);
-            float q = sc.mat_q[m];
-            if (!(u < q)) break;
-            phi = (phi * rho) / q;
-            V3 ns = vdot(dir, nrm) < 0.0f ? nrm : vneg(nrm);
-            dir = cosine_dir(ns, g);
-        } else if (type == PM_MAT_MIRROR) {
-            dir = reflect(dir, nrm);
-        } else {
-            dir = glass_dir(dir, nrm, sc.mat_ior[m], g);
-        }
-        org = x;
-        excl = h;
+    int32_t h = closest_hit<false>(sc.bvh, link_set(P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp, st);
+    if (h < 0) return false;
+    V3 x = vray(P.org, t, P.dir);
+    Tri tr = load_tri(sc.bvh.tris, kp);
+    V3 nrm = tri_normal(tr);
+    uint32_t m = tr.mat;
+    int type = sc.mat_type[m];
+    uint8_t *row = kRecord ? mat_tab + (size_t)P.n * mb : nullptr;
+    if (kRecord) {
+        row[b] = 0xffu;
+        P.last = b;
     }
-    if (kRecord && last + 1 < mb) row[last + 1] = 0xfeu;
+    if (type == PM_MAT_DIFFUSE) {
+        float rho = sc.mat_rho[m];
+        if (!(rho > 0.0f)) return false;
+        if (kRecord) {
+            row[b] = (uint8_t)m;
+            adj_tab[(size_t)P.n * mb + b] = 0.0;
+        }
+        uint32_t slot = wave_append(&d.counters[0]);
+        if (slot < d.cap) {
+            d.store[2 * (size_t)slot] = make_float4(x.x, x.y, x.z, P.phi);
+            d.store[2 * (size_t)slot + 1] = make_float4(P.dir.x, P.dir.y, P.dir.z, __uint_as_float((P.n << 5) | (uint32_t)b));
+        } else {
+            atomicOr(&d.counters[1], 1u);
+        }
+        float u = rng_next(P.g);
+        float q = sc.mat_q[m];
+        if (!(u < q)) return false;
+        P.phi = (P.phi * rho) / q;
+        V3 ns = vdot(P.dir, nrm) < 0.0f ? nrm : vneg(nrm);
+        P.dir = cosine_dir(ns, P.g);
+    } else if (type == PM_MAT_MIRROR) {
+        P.dir = reflect(P.dir, nrm);
+    } else {
+        P.dir = glass_dir(P.dir, nrm, sc.mat_ior[m], P.g);
+    }
+    P.org = x;
+    P.excl = h;
+    P.b = b + 1;
+    return P.b < mb;
+}
+
+template <bool kRecord>
+__device__ __forceinline__ void photon_finish(const SppmDev &d, const PhotonPath &P, uint8_t *__restrict__ mat_tab) {
+    if (kRecord && P.last + 1 < d.max_bounces) mat_tab[(size_t)P.n * d.max_bounces + P.last + 1] = 0xfeu;
+}
+
+// Photon path n traced to its end by one lane.
+template <bool kRecord>
+__device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32_t n, uint8_t *__restrict__ mat_tab,
+                                            double *__restrict__ adj_tab) {
+    PhotonPath P;
+    if (photon_emit(d, k, n, P))
+        while (photon_bounce<kRecord>(d, P, mat_tab, adj_tab)) {
+        }
+    photon_finish<kRecord>(d, P, mat_tab);
+}
+
+// Photon paths with regeneration (Sec. 3.3): persistent lanes trace one bounce
+// per step; a lane whose path ended takes the next path index from the
+// counter d.counters[2] once at least `refill` lanes of its wave are idle (or
+// all are).  Every step advances each live path by one bounce and paths are
+// bounded by max_bounces, so every wave exits once the counter passes n_paths.
+// Called by every lane of a wave; the wave's lanes must share one scene.
+__device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, uint32_t refill) {
+    PhotonPath P;
+    bool live = false, exhausted = false;
+    for (;;) {
+        bool idle = !live && !exhausted;
+        uint64_t idle_mask = __ballot(idle);
+        uint64_t live_mask = __ballot(live);
+        if (idle_mask != 0ull && (live_mask == 0ull || (uint32_t)__popcll(idle_mask) >= refill)) {
+            uint32_t n = wave_fetch_add(&d.counters[2], idle_mask, idle);
+            if (idle) {
+                if (n < d.n_paths) live = photon_emit(d, k, n, P);
+                else exhausted = true;
+            }
+            live_mask = __ballot(live);
+        }
+        if (live_mask == 0ull && __ballot(!exhausted) == 0ull) break;
+        if (live) live = photon_bounce<false>(d, P, nullptr, nullptr);
+    }
 }
 
 // ---------------------------------------------------------------------------

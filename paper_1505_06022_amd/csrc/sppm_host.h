@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "runtime.h"
 #include "sppm_dev.h"
 
@@ -15,6 +17,7 @@ struct pm_sppm {
     int32_t K = 0;
     uint32_t cap = 0;
     uint32_t table_bits = 0;
+    uint32_t regen_grid = 1;  // workgroups of the regenerating photon kernel
     float phi0 = 0.0f;
     // device buffers
     int32_t *mat_type = nullptr;
@@ -33,12 +36,12 @@ struct pm_sppm {
     // adjoint recording / replay buffers (record_iterations > 0)
     int32_t rec_iters = 0;
     int32_t n_mat = 0;
+    std::vector<float> rho_host;  // albedos (validation of adjoint parameters)
     double le_single = 0.0;  // Le of the single emitting material, 0 if not exactly one
     double *R2_hist = nullptr;    // [rec_iters][P] radius used in each iteration
     double *adj_tab = nullptr;    // [n_photons][max_bounces] photon sensitivities
     uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
     double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
-    int32_t *d_pmat = nullptr;    // [256] parameter materials
 };
 
 namespace pm {

@@ -65,9 +65,9 @@ def _check_photons(g, ph):
     assert np.array_equal(s[:, 4:7], d["w"])
 
 
-def _run_parity(torch, oracle_lib, sc, Np, K, r0, seed, alpha=0.7, stage_iters=1):
+def _run_parity(torch, oracle_lib, sc, Np, K, r0, seed, alpha=0.7, stage_iters=1, **kw):
     osc = oracle_lib.OracleScene(sc)
-    params = api.sppm_params(Np, alpha=alpha, r0=r0, seed=seed)
+    params = api.sppm_params(Np, alpha=alpha, r0=r0, seed=seed, **kw)
     s = api.Sppm(sc, params)
     P = osc.P
     N, R2, tau, D = np.zeros(P), np.full(P, r0 * r0), np.zeros(P), np.zeros(P)
@@ -117,6 +117,15 @@ def test_specular_scene_parity(torch_cuda, oracle_lib):
     sc = scenes.procedural_scene(width=97, height=61, hf_cells=20, sphere_level=2, glass_level=3, seed=3)
     diag = float(np.linalg.norm(sc.verts.reshape(-1, 3).max(0) - sc.verts.reshape(-1, 3).min(0)))
     _run_parity(torch_cuda, oracle_lib, sc, 1 << 15, 3, 0.05 * diag * 64 / 97, seed=3)
+
+
+@pytest.mark.parametrize("photon_kernel,refill", [(1, 0), (2, 1), (2, 8), (2, 64)])
+def test_photon_kernels_parity(torch_cuda, oracle_lib, photon_kernel, refill):
+    """One path per lane and regenerating lanes give the same photons and images."""
+    _log(f"case: photon kernel {photon_kernel} refill {refill}")
+    sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
+    _run_parity(torch_cuda, oracle_lib, sc, 3 * (1 << 12) + 5, 2, 0.02, seed=8, stage_iters=2,
+                photon_kernel=photon_kernel, refill=refill)
 
 
 def test_degenerate_cases(torch_cuda, oracle_lib):
