@@ -81,6 +81,9 @@ def traversal_bench(args, torch, api, scenes):
     rc = torch.from_numpy(coh).to(dev)
     ri = torch.from_numpy(inc).to(dev)
     batches = [rc, ri]
+    # camera rays are traced in pixel order; the incoherent batch is first
+    # bucketed by (link set, origin cell) -- an option of the trace call
+    trace_kw = [dict(), dict(reorder=1)]
     outs = [(torch.empty(len(r), dtype=torch.int32, device=dev), torch.empty(len(r), dtype=torch.float32, device=dev))
             for r in batches]
     n_rays = sum(len(r) for r in batches)
@@ -98,15 +101,15 @@ def traversal_bench(args, torch, api, scenes):
 
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
-        for r, (h, t) in zip(batches, outs):
-            api.trace_rays(bvh, r, h, t)
+        for r, (h, t), kw in zip(batches, outs, trace_kw):
+            api.trace_rays(bvh, r, h, t, **kw)
     torch.cuda.synchronize()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))] for _ in range(args.steps)]
     t0 = time.perf_counter()
     for s in range(args.steps):
-        for b, (r, (h, t)) in enumerate(zip(batches, outs)):
+        for b, (r, (h, t), kw) in enumerate(zip(batches, outs, trace_kw)):
             ev[s][2 * b].record(stream)
-            api.trace_rays(bvh, r, h, t)
+            api.trace_rays(bvh, r, h, t, **kw)
             ev[s][2 * b + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -115,7 +118,11 @@ def traversal_bench(args, torch, api, scenes):
     step_ms = wall * 1e3 / args.steps
     # the other traversal kernels, for comparison (not part of the timed steps)
     variants = {}
-    for name, kw in () if args.no_variants else (("per_ray", dict(kernel=1)), ("persistent_refill8", dict(kernel=2, refill=8)),
+    for name, kw in () if args.no_variants else (("per_ray", dict(kernel=1)),
+                                                 ("paired", dict(kernel=3)),
+                                                 ("paired_reorder1", dict(kernel=3, reorder=1)),
+                                                 ("per_ray_reorder1", dict(kernel=1, reorder=1)),
+                                                 ("per_ray_reorder2", dict(kernel=1, reorder=2)), ("persistent_refill8", dict(kernel=2, refill=8)),
                      ("persistent_refill16", dict(kernel=2, refill=16)),
                      ("persistent_refill32", dict(kernel=2, refill=32))):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
@@ -131,6 +138,30 @@ def traversal_bench(args, torch, api, scenes):
         ms /= 3
         variants[name] = {"coherent_mrays_s": round(len(rc) / ms[0] / 1e3, 1),
                           "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1)}
+    # SAH node-visit cost (relative to a triangle test): tree size vs traversal rate
+    sah = {}
+    if not args.no_variants:
+        for tc in (2.0, 4.0):
+            bv = api.build_bvh(sc.verts, sc.tri_mat, trav_cost=tc)
+            inf = bv.info()
+            res = {"n_nodes": inf["n_nodes"], "device_mb": round(inf["device_bytes"] / 1e6, 1)}
+            for name, kw in (("per_ray", dict(kernel=1)), ("paired", dict(kernel=3)),
+                             ("paired_reorder1", dict(kernel=3, reorder=1))):
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
+                ms = np.zeros(len(batches))
+                for rep in range(4):
+                    for b, (r, (h, t)) in enumerate(zip(batches, outs)):
+                        e[2 * b].record(stream)
+                        api.trace_rays(bv, r, h, t, **kw)
+                        e[2 * b + 1].record(stream)
+                    torch.cuda.synchronize()
+                    if rep:
+                        ms += [e[2 * b].elapsed_time(e[2 * b + 1]) for b in range(len(batches))]
+                ms /= 3
+                res[name] = [round(len(rc) / ms[0] / 1e3, 1), round(len(ri) / ms[1] / 1e3, 1)]
+            sah[f"trav_cost_{tc:g}"] = res
+            bv.destroy()
+        variants["sah_trav_cost"] = sah
     avg_launch_ms = kern_ms.mean()
     per_launch_bytes = alg_bytes / len(batches)
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
@@ -311,7 +342,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "traversal: 2^20 random triangles (lognormal(-5,0.5) edges), SAH 32 bins leaf<=4, "
                                "1920x1080 coherent + 2^21 incoherent rays",
-                   "n_rays": tb["n_rays"], "n_tri": 1 << 20, "parallelism": "none"},
+                   "n_rays": tb["n_rays"], "n_tri": 1 << 20, "parallelism": "none",
+                   "trace_options": ["coherent: per-ray kernel, pixel order",
+                                     "incoherent: per-ray kernel after bucketing by (link set, 16^3 origin cell)"]},
         "coherent_mrays_s": round(tb["coherent_mrays"], 2),
         "incoherent_mrays_s": round(tb["incoherent_mrays"], 2),
         "kernel_mrays_s": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6, 2),

@@ -71,6 +71,8 @@ typedef struct {
     int32_t bins;      /* SAH bins per axis, 2..256 (default 32) */
     int32_t max_leaf;  /* triangles per leaf, 1..7 (default 4) */
     int32_t n_threads; /* host build threads, 0 = all */
+    float trav_cost;   /* SAH cost of a node visit relative to a triangle
+                          test (0 = default 1; range (0, 64]) */
 } pm_bvh_opts;
 
 typedef struct {
@@ -128,9 +130,10 @@ PM_API int pm_bvh_get_info(const pm_bvh *bvh, pm_bvh_info *info);
  * Errors: PM_ERR_ARG for n < 0, n >= 2^31 or NULL pointers with n > 0. */
 PM_API int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t, void *stream);
 
-/* Traversal kernels: one ray per lane for the whole walk, or persistent
- * wavefronts whose finished lanes take new rays from a work counter. */
-enum { PM_TRACE_AUTO = 0, PM_TRACE_PER_RAY = 1, PM_TRACE_PERSISTENT = 2 };
+/* Traversal kernels: one ray per lane for the whole walk; persistent
+ * wavefronts whose finished lanes take new rays from a work counter; or one
+ * ray per lane testing nodes i and i+1 from one memory round trip. */
+enum { PM_TRACE_AUTO = 0, PM_TRACE_PER_RAY = 1, PM_TRACE_PERSISTENT = 2, PM_TRACE_PAIRED = 3 };
 
 typedef struct {
     uint32_t size;      /* sizeof(pm_trace_opts) */
@@ -140,6 +143,13 @@ typedef struct {
     int32_t kernel;     /* PM_TRACE_* */
     int32_t refill;     /* persistent kernel: idle lanes that trigger a refill
                            (1..64; 0 = default 16) */
+    int32_t reorder;    /* 1: first bucket the rays by (link set, origin cell of
+                           a 16^3 grid over the scene, Morton order) and trace
+                           them in that order; 2: the same with a 32^3 grid and
+                           the signs of the two minor direction components
+                           (for incoherent batches; results are unchanged and
+                           written to each ray's own slot).  Uses a
+                           library-owned scratch of 4 B per ray. */
 } pm_trace_opts;
 
 /* pm_trace_rays with options (ablation of the link-set choice; per-ray

@@ -32,7 +32,8 @@ class PMError(RuntimeError):
 
 
 class BvhOpts(C.Structure):
-    _fields_ = [("size", C.c_uint32), ("bins", C.c_int32), ("max_leaf", C.c_int32), ("n_threads", C.c_int32)]
+    _fields_ = [("size", C.c_uint32), ("bins", C.c_int32), ("max_leaf", C.c_int32), ("n_threads", C.c_int32),
+                ("trav_cost", C.c_float)]
 
 
 class BvhInfo(C.Structure):
@@ -44,7 +45,7 @@ class BvhInfo(C.Structure):
 
 class TraceOpts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("link_set", C.c_int32), ("counters", C.c_void_p), ("kernel", C.c_int32),
-                ("refill", C.c_int32)]
+                ("refill", C.c_int32), ("reorder", C.c_int32)]
 
 
 TRACE_AUTO, TRACE_PER_RAY, TRACE_PERSISTENT = 0, 1, 2
@@ -146,9 +147,10 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _opts(bins, max_leaf, n_threads):
+def _opts(bins, max_leaf, n_threads, trav_cost=0.0):
     o = BvhOpts()
     o.size, o.bins, o.max_leaf, o.n_threads = C.sizeof(BvhOpts), bins, max_leaf, n_threads
+    o.trav_cost = trav_cost
     return o
 
 
@@ -195,21 +197,22 @@ class Bvh:
 
 
 def build_bvh(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0,
-              stream=None) -> Bvh:
+              trav_cost=0.0, stream=None) -> Bvh:
     v = np.ascontiguousarray(verts, np.float32)
     m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
     out = C.c_void_p()
-    o = _opts(bins, max_leaf, n_threads)
+    o = _opts(bins, max_leaf, n_threads, trav_cost)
     _check(lib().pm_build_bvh(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), _stream(stream),
                               C.byref(out)))
     return Bvh(out.value, v.shape[0])
 
 
-def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0):
+def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0,
+                   trav_cost=0.0):
     """Host-only build: returns (nodes uint32 [6, n_nodes, 4], tris uint32 [T, 12], info dict)."""
     v = np.ascontiguousarray(verts, np.float32)
     m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
-    o = _opts(bins, max_leaf, n_threads)
+    o = _opts(bins, max_leaf, n_threads, trav_cost)
     nn = C.c_int64()
     L = lib()
     _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
@@ -224,7 +227,7 @@ def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32
 
 
 def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=None, kernel: int = 0, refill: int = 0,
-               stream=None):
+               reorder: int = 0, stream=None):
     """Closest hit of each ray.  rays: float32 cuda tensor [n, 8]; returns (hit int32 [n], t float32 [n])."""
     import torch
     assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
@@ -233,11 +236,12 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
         hit = torch.empty(n, dtype=torch.int32, device=rays.device)
     if t is None:
         t = torch.empty(n, dtype=torch.float32, device=rays.device)
-    if link_set == -1 and counters is None and kernel == 0 and refill == 0:
+    if link_set == -1 and counters is None and kernel == 0 and refill == 0 and not reorder:
         _check(lib().pm_trace_rays(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), _stream(stream)))
     else:
         o = TraceOpts()
         o.size, o.link_set, o.kernel, o.refill = C.sizeof(TraceOpts), link_set, kernel, refill
+        o.reorder = int(reorder)   # 0 none, 1 coarse, 2 fine
         o.counters = None if counters is None else counters.data_ptr()
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t

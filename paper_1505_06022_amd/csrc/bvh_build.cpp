@@ -53,6 +53,7 @@ struct Builder {
     const float *V;
     int64_t n;
     int bins, max_leaf;
+    double trav_cost;
     std::vector<Box> tb;
     std::vector<float> cen;
     std::vector<int32_t> idx;
@@ -119,7 +120,7 @@ struct Builder {
             }
         }
         double parea = nb.area();
-        double split_cost = best_axis >= 0 ? 1.0 + (parea > 0 ? best_cost / parea : 0.0) : INFINITY;
+        double split_cost = best_axis >= 0 ? trav_cost + (parea > 0 ? best_cost / parea : 0.0) : INFINITY;
         if (count <= max_leaf && (double)count <= split_cost) return make_leaf();
 
         int32_t nl;
@@ -181,8 +182,9 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
         err = "n_tri must be in [1, 2^28)";
         return false;
     }
-    if (opt.bins < 2 || opt.bins > 256 || opt.max_leaf < 1 || opt.max_leaf > 7) {
-        err = "bins must be in [2,256] and max_leaf in [1,7]";
+    if (opt.bins < 2 || opt.bins > 256 || opt.max_leaf < 1 || opt.max_leaf > 7 || !(opt.trav_cost > 0.0) ||
+        opt.trav_cost > 64.0) {
+        err = "bins must be in [2,256], max_leaf in [1,7] and trav_cost in (0,64]";
         return false;
     }
     for (int64_t i = 0; i < 9 * n_tri; ++i)
@@ -195,6 +197,7 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     b.n = n_tri;
     b.bins = opt.bins;
     b.max_leaf = opt.max_leaf;
+    b.trav_cost = opt.trav_cost;
     unsigned hw = std::max(1u, std::thread::hardware_concurrency());
     int nth = opt.n_threads > 0 ? opt.n_threads : (int)std::min(hw, 16u);
     b.par_depth = 0;
@@ -228,7 +231,7 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
         if (t.left >= 0) {
             dep[t.left] = dep[i] + 1;
             dep[t.right] = dep[i] + 1;
-            sah += rel;
+            sah += rel * opt.trav_cost;
         } else {
             leaves++;
             sah += rel * t.count;

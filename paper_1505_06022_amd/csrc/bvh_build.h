@@ -10,6 +10,7 @@ struct BuildOptions {
     int bins = 32;
     int max_leaf = 4;
     int n_threads = 0;
+    double trav_cost = 1.0;  // SAH: node visit cost relative to a triangle test
 };
 
 // Device layout (words are 32-bit):

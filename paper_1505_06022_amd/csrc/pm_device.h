@@ -245,6 +245,55 @@ struct Walker {
         i = (hit || leaf) ? i + 1 : q.w;
     }
 
+    // Slab test of a quantised node box against [tmin, tbest].
+    __device__ __forceinline__ bool box_hit(const uint4 &q) const {
+        float tx0 = fmaf((float)(q.x & 0xffffu), sx, bx), tx1 = fmaf((float)(q.y >> 16), sx, bx);
+        float ty0 = fmaf((float)(q.x >> 16), sy, by), ty1 = fmaf((float)(q.z & 0xffffu), sy, by);
+        float tz0 = fmaf((float)(q.y & 0xffffu), sz, bz), tz1 = fmaf((float)(q.z >> 16), sz, bz);
+        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
+        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tbest));
+        return tn <= tf;
+    }
+
+    template <bool kStats>
+    __device__ __forceinline__ void leaf_tris(const float4 *__restrict__ tris, uint32_t w, TraceStats &st) {
+        uint32_t first = (w >> 3) & 0x0fffffffu, cnt = w & 7u;
+        for (uint32_t k = 0; k < cnt; ++k) {
+            Tri tr = load_tri(tris, first + k);
+            if (kStats) st.tris++;
+            if (tr.id == exclude) continue;
+            float t;
+            if (mt_hit(o, d, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
+                tbest = t;
+                best = tr.id;
+                best_k = first + k;
+            }
+        }
+    }
+
+    // Up to two node visits per memory round trip: nodes i and i + 1 are
+    // loaded together; when the walk continues at i + 1 (an inner-node hit or
+    // any leaf) that node is tested without waiting for another load.
+    template <bool kStats>
+    __device__ __forceinline__ void step2(const float4 *__restrict__ tris, TraceStats &st) {
+        uint4 q0 = nodes[i];
+        uint4 q1 = nodes[i + 1 < n ? i + 1 : i];
+        if (kStats) st.boxes++;
+        bool leaf = (q0.w >> 31) != 0u, hit = box_hit(q0);
+        if (hit && leaf) leaf_tris<kStats>(tris, q0.w, st);
+        if (!(hit || leaf)) {
+            i = q0.w;
+            return;
+        }
+        i = i + 1;
+        if (i >= n) return;
+        if (kStats) st.boxes++;
+        leaf = (q1.w >> 31) != 0u;
+        hit = box_hit(q1);
+        if (hit && leaf) leaf_tris<kStats>(tris, q1.w, st);
+        i = (hit || leaf) ? i + 1 : q1.w;
+    }
+
     __device__ __forceinline__ float t_hit() const { return best >= 0 ? tbest : __builtin_inff(); }
 };
 

@@ -35,6 +35,9 @@ struct pm_bvh {
     uint4 *d_nodes = nullptr;   // [6][n_nodes] 16-byte nodes
     float4 *d_tris = nullptr;   // [n_tri][3]
     uint32_t *d_next = nullptr; // work counter of the persistent traversal kernel
+    uint32_t *d_perm = nullptr; // ray order of the reordering traversal (perm_cap entries)
+    uint64_t perm_cap = 0;
+    uint32_t *d_order = nullptr; // bucket counts / starts / cursors of the ray reordering
     int device = 0;
     std::vector<int32_t> pos_of;  // original triangle index -> position in d_tris
 };
@@ -54,6 +57,6 @@ void free_bvh(pm_bvh *b);
 
 // Launch the closest-hit kernel.  link_set < 0 selects by direction.
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, hipStream_t s);
+                 uint32_t *counters, int kernel, int refill, int reorder, hipStream_t s);
 
 }  // namespace pm

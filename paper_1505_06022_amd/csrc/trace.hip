@@ -3,6 +3,7 @@
 
 #include "pm_device.h"
 #include "runtime.h"
+#include "sppm_scan.h"
 
 namespace {
 
@@ -26,6 +27,29 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(pmd::Bvh bvh, const float
     int32_t h = pmd::closest_hit<kStats>(bvh, set, o, d, r0.w, r1.w, -1, t, kpos, st);
     hit[i] = h;
     tout[i] = t;
+    if (kStats) {
+        counters[2 * i] = st.boxes;
+        counters[2 * i + 1] = st.tris;
+    }
+}
+
+// One ray per lane, two node visits per memory round trip where possible.
+template <bool kStats>
+__global__ __launch_bounds__(kTraceBlock) void k_trace2(pmd::Bvh bvh, const float4 *__restrict__ rays, int64_t n,
+                                                        int32_t *__restrict__ hit, float *__restrict__ tout,
+                                                        int32_t force_set, uint32_t *__restrict__ counters) {
+    uint32_t blk = pmd::xcd_block(blockIdx.x, gridDim.x);
+    int64_t i = (int64_t)blk * kTraceBlock + threadIdx.x;
+    if (i >= n) return;
+    float4 r0 = rays[2 * i], r1 = rays[2 * i + 1];
+    pmd::V3 o = pmd::v3(r0.x, r0.y, r0.z), d = pmd::v3(r1.x, r1.y, r1.z);
+    int set = force_set >= 0 ? force_set : pmd::link_set(d);
+    pmd::TraceStats st{0u, 0u};
+    pmd::Walker w;
+    w.init(bvh, set, o, d, r0.w, r1.w, -1);
+    while (!w.done()) w.step2<kStats>(bvh.tris, st);
+    hit[i] = w.best;
+    tout[i] = w.t_hit();
     if (kStats) {
         counters[2 * i] = st.boxes;
         counters[2 * i + 1] = st.tris;
@@ -89,6 +113,92 @@ __global__ void k_reset_counter(uint32_t *next) {
     if (threadIdx.x == 0) *next = 0u;
 }
 
+// Ray reordering: bucket = (link set, [signs of the two minor direction
+// components,] Morton code of the origin cell in a grid over the scene box),
+// so that the rays of a wave share a direction set and start near each other.
+// Counting sort of ray indices (count, scan, scatter); a wave whose rays all
+// fall in one bucket uses one atomic and keeps its lanes in order.
+constexpr uint32_t kOrderBucketsCoarse = 6 * 4096;        // 16^3 cells
+constexpr uint32_t kOrderBucketsFine = 6 * 4 * 32768;      // minor signs x 32^3 cells
+
+__device__ __forceinline__ uint32_t spread5(uint32_t v) {  // 5 bits -> every third bit
+    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4) | ((v & 8u) << 6) | ((v & 16u) << 8);
+}
+
+struct OrderBox {
+    float lo[3], scale[3];  // cell = (o - lo) * scale, scale = cells / extent
+    uint32_t cells;         // per axis: 16 (coarse) or 32 (fine)
+    int32_t fine;
+};
+
+__device__ __forceinline__ uint32_t ray_bucket(const float4 *__restrict__ rays, uint32_t i, const OrderBox &ob,
+                                               int32_t force_set) {
+    float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+    int set = force_set >= 0 ? force_set : pmd::link_set(pmd::v3(r1.x, r1.y, r1.z));
+    uint32_t c[3];
+    float o[3] = {r0.x, r0.y, r0.z};
+    const float cmax = (float)(ob.cells - 1);
+    for (int a = 0; a < 3; ++a) {
+        float f = (o[a] - ob.lo[a]) * ob.scale[a];
+        c[a] = f >= cmax ? ob.cells - 1 : (f > 0.0f ? (uint32_t)f : 0u);  // NaN -> 0
+    }
+    uint32_t morton = spread5(c[0]) | (spread5(c[1]) << 1) | (spread5(c[2]) << 2);
+    if (!ob.fine) return (uint32_t)set * 4096u + morton;
+    // signs of the two components other than the major axis
+    int axis = set >> 1;
+    float d[3] = {r1.x, r1.y, r1.z};
+    uint32_t sg = (d[(axis + 1) % 3] < 0.0f ? 1u : 0u) | (d[(axis + 2) % 3] < 0.0f ? 2u : 0u);
+    return ((uint32_t)set * 4u + sg) * 32768u + morton;
+}
+
+// Wave-aggregated increment when every active lane has the same key.
+__device__ __forceinline__ uint32_t bucket_add(uint32_t *counters, uint32_t key) {
+    uint32_t k0 = __shfl(key, __ffsll((unsigned long long)__ballot(1)) - 1);
+    if (__ballot(key != k0) == 0ull) return pmd::wave_fetch_add(&counters[key], __ballot(1), true);
+    return atomicAdd(&counters[key], 1u);
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_ray_count(const float4 *__restrict__ rays, uint32_t n, OrderBox ob,
+                                                           int32_t force_set, uint32_t *__restrict__ counts) {
+    uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
+    if (i < n) bucket_add(counts, ray_bucket(rays, i, ob, force_set));
+}
+
+__global__ __launch_bounds__(kTraceBlock) void k_ray_scatter(const float4 *__restrict__ rays, uint32_t n, OrderBox ob,
+                                                             int32_t force_set, uint32_t *__restrict__ fill,
+                                                             uint32_t *__restrict__ perm) {
+    uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
+    if (i < n) perm[bucket_add(fill, ray_bucket(rays, i, ob, force_set))] = i;
+}
+
+// One ray per lane, rays taken in the order of perm; results go to each ray's
+// own slot.
+template <bool kStats, bool kPaired>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const float4 *__restrict__ rays,
+                                                            const uint32_t *__restrict__ perm, uint32_t n,
+                                                            int32_t *__restrict__ hit, float *__restrict__ tout,
+                                                            int32_t force_set, uint32_t *__restrict__ counters) {
+    uint32_t j = pmd::xcd_block(blockIdx.x, gridDim.x) * kTraceBlock + threadIdx.x;
+    if (j >= n) return;
+    uint32_t i = perm[j];
+    float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
+    pmd::V3 o = pmd::v3(r0.x, r0.y, r0.z), d = pmd::v3(r1.x, r1.y, r1.z);
+    int set = force_set >= 0 ? force_set : pmd::link_set(d);
+    pmd::TraceStats st{0u, 0u};
+    pmd::Walker w;
+    w.init(bvh, set, o, d, r0.w, r1.w, -1);
+    while (!w.done()) {
+        if (kPaired) w.step2<kStats>(bvh.tris, st);
+        else w.step<kStats>(bvh.tris, st);
+    }
+    hit[i] = w.best;
+    tout[i] = w.t_hit();
+    if (kStats) {
+        counters[2 * (size_t)i] = st.boxes;
+        counters[2 * (size_t)i + 1] = st.tris;
+    }
+}
+
 }  // namespace
 
 namespace pm {
@@ -137,6 +247,11 @@ void free_bvh(pm_bvh *b) {
     if (b->d_nodes) (void)hipFree(b->d_nodes);
     if (b->d_tris) (void)hipFree(b->d_tris);
     if (b->d_next) (void)hipFree(b->d_next);
+    if (b->d_perm) (void)hipFree(b->d_perm);
+    if (b->d_order) (void)hipFree(b->d_order);
+    b->d_perm = nullptr;
+    b->d_order = nullptr;
+    b->perm_cap = 0;
     b->d_nodes = nullptr;
     b->d_tris = nullptr;
     b->d_next = nullptr;
@@ -159,10 +274,54 @@ static int persistent_grid(hipStream_t s, int device, uint32_t &grid) {
     return PM_OK;
 }
 
+static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *rays, int64_t n, int32_t *hit,
+                                  float *t, int link_set, uint32_t *counters, int kernel, int reorder,
+                                  hipStream_t s) {
+    if ((uint64_t)n > b->perm_cap) {
+        if (b->d_perm) {
+            PM_HIP(hipStreamSynchronize(s));
+            PM_HIP(hipFree(b->d_perm));
+            b->d_perm = nullptr;
+        }
+        PM_HIP(hipMalloc(&b->d_perm, sizeof(uint32_t) * (size_t)n));
+        b->perm_cap = (uint64_t)n;
+    }
+    const uint32_t nbk = reorder == 2 ? kOrderBucketsFine : kOrderBucketsCoarse;
+    if (!b->d_order)
+        PM_HIP(hipMalloc(&b->d_order, sizeof(uint32_t) * (3 * kOrderBucketsFine + 1 + kOrderBucketsFine / 4096 + 1)));
+    uint32_t *counts = b->d_order, *start = counts + nbk, *fill = start + nbk + 1;
+    uint32_t *bsum = fill + nbk;
+    OrderBox ob;
+    ob.cells = reorder == 2 ? 32u : 16u;
+    ob.fine = reorder == 2;
+    for (int a = 0; a < 3; ++a) {
+        float ext = b->hi[a] - b->lo[a];
+        ob.lo[a] = b->lo[a];
+        ob.scale[a] = ext > 0.0f ? (float)ob.cells / ext : 0.0f;
+    }
+    const uint32_t nn = (uint32_t)n, blocks = (uint32_t)((n + kTraceBlock - 1) / kTraceBlock);
+    hipLaunchKernelGGL(k_fill_u32, dim3((nbk + 255) / 256), dim3(256), 0, s, counts, nbk, 0u);
+    hipLaunchKernelGGL(k_ray_count, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
+                       counts);
+    launch_bucket_scan(counts, start, fill, bsum, nbk, s);
+    hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
+                       fill, b->d_perm);
+    const bool paired = kernel == PM_TRACE_PAIRED;
+    auto kern = counters ? (paired ? k_trace_perm<true, true> : k_trace_perm<true, false>)
+                         : (paired ? k_trace_perm<false, true> : k_trace_perm<false, false>);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kTraceBlock), 0, s, bvh, (const float4 *)rays,
+                       (const uint32_t *)b->d_perm, nn, hit, t, link_set, counters);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, hipStream_t s) {
+                 uint32_t *counters, int kernel, int refill, int reorder, hipStream_t s) {
     if (n == 0) return PM_OK;
     pmd::Bvh bvh = make_device_bvh(b);
+    if (reorder)
+        return launch_trace_reordered(const_cast<pm_bvh *>(b), bvh, rays, n, hit, t, link_set, counters, kernel,
+                                      reorder, s);
     if (kernel == 0) kernel = PM_TRACE_PER_RAY;
     if (kernel == PM_TRACE_PERSISTENT) {
         if (n >= (int64_t(1) << 31)) {
@@ -189,10 +348,18 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
         return PM_ERR_ARG;
     }
     dim3 grid((uint32_t)nblk), block(kTraceBlock);
-    if (counters)
+    if (kernel == PM_TRACE_PAIRED) {
+        if (counters)
+            hipLaunchKernelGGL(k_trace2<true>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set,
+                               counters);
+        else
+            hipLaunchKernelGGL(k_trace2<false>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set,
+                               counters);
+    } else if (counters) {
         hipLaunchKernelGGL(k_trace<true>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set, counters);
-    else
+    } else {
         hipLaunchKernelGGL(k_trace<false>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set, counters);
+    }
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

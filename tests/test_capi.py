@@ -38,7 +38,7 @@ def test_host_validation_errors_without_gpu():
     bad[0, 1, 2] = np.nan
     assert L.pm_build_bvh_host(bad.ctypes.data, None, 1, None, C.byref(nn), None, None, None) == api.PM_ERR_ARG
     assert b"non-finite" in L.pm_last_error()
-    o = api.BvhOpts(C.sizeof(api.BvhOpts), 32, 9, 0)
+    o = api.BvhOpts(C.sizeof(api.BvhOpts), 32, 9, 0, 0.0)
     assert L.pm_build_bvh_host(v.ctypes.data, None, 1, C.byref(o), C.byref(nn), None, None, None) == api.PM_ERR_ARG
     assert L.pm_trace_rays(None, None, 0, None, None, None) == api.PM_ERR_ARG
     # scene/param validation happens before any device work
@@ -199,6 +199,10 @@ def test_host_bvh_box_scene_and_soup_statistics():
     _check_structure(sc.verts, nodes, tris, 2, info)
     # SAH tree: cheaper than the worst case of one leaf per 2 triangles in a chain
     assert info["depth"] < 64 and info["sah_cost"] > 0
+    # a costlier node visit gives fewer nodes and fuller leaves
+    n2, t2, info2 = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8, trav_cost=4.0)
+    _check_structure(sc.verts, n2, t2, 2, info2)
+    assert info2["n_nodes"] < info["n_nodes"]
     # storage: 6 link sets x 16 B per node + 48 B per triangle
     assert info["device_bytes"] == 6 * 16 * info["n_nodes"] + 48 * info["n_tri"]
 

@@ -86,17 +86,18 @@ def test_every_link_set_and_stats_mode_agree(torch_cuda, oracle_lib):
     assert np.all(c[:, 0] >= 1) and np.all(c[:, 1] >= (h >= 0))
 
 
-@pytest.mark.parametrize("kernel,refill", [(1, 0), (2, 1), (2, 16), (2, 64)])
-def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill):
-    _log(f"case: traversal kernel={kernel} refill={refill}")
+@pytest.mark.parametrize("kernel,refill,reorder", [(1, 0, False), (2, 1, False), (2, 16, False), (2, 64, False),
+                                                   (1, 0, 1), (1, 0, 2), (3, 0, 0)])
+def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder):
+    _log(f"case: traversal kernel={kernel} refill={refill} reorder={reorder}")
     sc = scenes.small_soup(5000, 11, spread=0.02)
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     rays = np.concatenate([scenes.random_rays(7001, 11), scenes.pinhole_rays(sc.camera)])
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
-    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill)
+    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, reorder=reorder)
     _compare(h, t, h_ref, t_ref)
     cnt = torch_cuda.zeros((len(rays), 2), dtype=torch_cuda.int32, device="cuda")
-    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, counters=cnt)
+    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, counters=cnt, reorder=reorder)
     _compare(h, t, h_ref, t_ref)
 
 
@@ -111,6 +112,11 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
     h, t = _gpu_trace(torch_cuda, bvh, rays)
     h1, t1 = _gpu_trace(torch_cuda, bvh, rays, kernel=1)     # one ray per lane: identical
     assert np.array_equal(h, h1) and np.array_equal(t, t1)
+    h3, t3 = _gpu_trace(torch_cuda, bvh, rays, kernel=3)     # paired node visits: identical
+    assert np.array_equal(h, h3) and np.array_equal(t, t3)
+    for level in (1, 2):                                      # reordered: identical
+        h2, t2 = _gpu_trace(torch_cuda, bvh, rays, reorder=level)
+        assert np.array_equal(h, h2) and np.array_equal(t, t2)
     rng = np.random.default_rng(123)
     pick = np.concatenate([rng.choice(len(coh), 4096, replace=False),
                            len(coh) + rng.choice(len(inc), 4096, replace=False)])
