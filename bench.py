@@ -4,12 +4,15 @@ Default workload (the traversal-only configuration): 2^20 random triangles
 (centroids uniform in the unit cube, lognormal(-5, 0.5) vertex offsets),
 SAH-binned BVH (32 bins, <= 4 triangles per leaf), 1920x1080 coherent pinhole
 rays plus 2^21 incoherent rays.  One step = closest-hit traversal of all
-4,170,752 rays (two launches of the traversal kernel, inputs resident in HBM).
-The JSON line reports Mrays/s, the traversal kernel's algorithmic-bytes
-roofline, the CPU oracle timed on the host, and an SPPM photon-pass
-measurement on the 250k-triangle procedural scene.
+4,170,752 rays: two trace calls, inputs resident in HBM.  The camera batch is
+traced in pixel order (--coherent), the incoherent batch after bucketing by
+(link set, origin cell) with postponed leaf tests (--incoherent); every
+option listed in KERNEL_VARIANTS gives identical results and is also timed.
+The JSON line reports Mrays/s, the traversal's algorithmic-bytes roofline,
+the CPU oracle timed on the host, the SPPM iteration on the 250k-triangle
+procedural scene, the adjoint-to-forward time ratio and the batched renderer.
 
-python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-sppm]
+python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-sppm] [--no-adjoint] [--no-batch]
 """
 from __future__ import annotations
 
@@ -25,6 +28,31 @@ HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRACE_SOURCES = ["paper_1505_06022_amd/csrc/pm_device.h", "paper_1505_06022_amd/csrc/trace.hip",
                  "paper_1505_06022_amd/csrc/bvh_build.cpp"]
+
+
+# Traversal options compared by the bench (names usable with --coherent/--incoherent)
+KERNEL_VARIANTS = (
+    ("per_ray", dict(kernel=1)), ("per_ray_reorder1", dict(kernel=1, reorder=1)),
+    ("per_ray_reorder2", dict(kernel=1, reorder=2)), ("paired", dict(kernel=3)),
+    ("paired_reorder1", dict(kernel=3, reorder=1)), ("persistent_refill16", dict(kernel=2, refill=16)),
+    ("postponed_late0", dict(kernel=4, refill=0)), ("postponed_late4", dict(kernel=4, refill=4)),
+    ("postponed_late16", dict(kernel=4, refill=16)), ("postponed_late0_reorder1", dict(kernel=4, reorder=1)),
+    ("postponed_late4_reorder1", dict(kernel=4, refill=4, reorder=1)),
+    ("postponed_late16_reorder1", dict(kernel=4, refill=16, reorder=1)),
+    ("per_ray_block64", dict(kernel=1, block=64)), ("per_ray_block128", dict(kernel=1, block=128)),
+    ("per_ray_reorder1_block64", dict(kernel=1, reorder=1, block=64)),
+    ("per_ray_reorder1_block128", dict(kernel=1, reorder=1, block=128)),
+    ("postponed_late16_block64", dict(kernel=4, refill=16, block=64)),
+    ("postponed_late16_reorder1_block64", dict(kernel=4, refill=16, reorder=1, block=64)),
+    ("paired_reorder1_block64", dict(kernel=3, reorder=1, block=64)),
+    ("two_rays", dict(kernel=5)), ("two_rays_block64", dict(kernel=5, block=64)),
+    ("two_rays_block128", dict(kernel=5, block=128)), ("two_rays_reorder1", dict(kernel=5, reorder=1)),
+    ("two_rays_reorder1_block64", dict(kernel=5, reorder=1, block=64)),
+    ("two_rays_reorder1_block128", dict(kernel=5, reorder=1, block=128)),
+    ("two_rays_reorder2_block64", dict(kernel=5, reorder=2, block=64)),
+    ("persistent_reorder1_refill4", dict(kernel=2, refill=4, reorder=1)),
+    ("persistent_reorder1_refill16", dict(kernel=2, refill=16, reorder=1)),
+    ("persistent_reorder1_refill32", dict(kernel=2, refill=32, reorder=1)))
 
 
 def measured_traffic():
@@ -60,6 +88,11 @@ def _parse():
     ap.add_argument("--batch-iters", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the comparison of traversal kernels")
+    names = [k for k, _ in KERNEL_VARIANTS]
+    ap.add_argument("--coherent", default="per_ray_block64", choices=names,
+                    help="traversal options of the camera batch")
+    ap.add_argument("--incoherent", default="postponed_late16_reorder1_block64", choices=names,
+                    help="traversal options of the incoherent batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -83,7 +116,8 @@ def traversal_bench(args, torch, api, scenes):
     batches = [rc, ri]
     # camera rays are traced in pixel order; the incoherent batch is first
     # bucketed by (link set, origin cell) -- an option of the trace call
-    trace_kw = [dict(), dict(reorder=1)]
+    table = dict(KERNEL_VARIANTS)
+    trace_kw = [table[args.coherent], table[args.incoherent]]
     outs = [(torch.empty(len(r), dtype=torch.int32, device=dev), torch.empty(len(r), dtype=torch.float32, device=dev))
             for r in batches]
     n_rays = sum(len(r) for r in batches)
@@ -118,13 +152,7 @@ def traversal_bench(args, torch, api, scenes):
     step_ms = wall * 1e3 / args.steps
     # the other traversal kernels, for comparison (not part of the timed steps)
     variants = {}
-    for name, kw in () if args.no_variants else (("per_ray", dict(kernel=1)),
-                                                 ("paired", dict(kernel=3)),
-                                                 ("paired_reorder1", dict(kernel=3, reorder=1)),
-                                                 ("per_ray_reorder1", dict(kernel=1, reorder=1)),
-                                                 ("per_ray_reorder2", dict(kernel=1, reorder=2)), ("persistent_refill8", dict(kernel=2, refill=8)),
-                     ("persistent_refill16", dict(kernel=2, refill=16)),
-                     ("persistent_refill32", dict(kernel=2, refill=32))):
+    for name, kw in () if args.no_variants else KERNEL_VARIANTS:
         e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
         ms = np.zeros(len(batches))
         for rep in range(4):
@@ -343,8 +371,8 @@ def main():
         "config": {"workload": "traversal: 2^20 random triangles (lognormal(-5,0.5) edges), SAH 32 bins leaf<=4, "
                                "1920x1080 coherent + 2^21 incoherent rays",
                    "n_rays": tb["n_rays"], "n_tri": 1 << 20, "parallelism": "none",
-                   "trace_options": ["coherent: per-ray kernel, pixel order",
-                                     "incoherent: per-ray kernel after bucketing by (link set, 16^3 origin cell)"]},
+                   "trace_options": {"coherent": [args.coherent, dict(KERNEL_VARIANTS)[args.coherent]],
+                                     "incoherent": [args.incoherent, dict(KERNEL_VARIANTS)[args.incoherent]]}},
         "coherent_mrays_s": round(tb["coherent_mrays"], 2),
         "incoherent_mrays_s": round(tb["incoherent_mrays"], 2),
         "kernel_mrays_s": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6, 2),
@@ -354,8 +382,11 @@ def main():
                             for vn, vt, n in tb["per_batch"]],
         "roofline": {"bound": "hbm", "achieved": round(tb["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(tb["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_trace", "bytes_per_launch": tb["per_launch_bytes"],
-                     "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4)},
+                     "kernel": "trace call: k_trace (coherent batch); k_ray_count + scan + k_ray_scatter + "
+                               "k_trace_perm (incoherent batch)",
+                     "bytes_per_launch": tb["per_launch_bytes"],
+                     "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4),
+                     "launch_ms_by_batch": [round(float(x), 4) for x in tb["kern_ms"].mean(0)]},
     }
     if not args.no_sppm:
         sp = sppm_bench(args, torch, api, scenes)

@@ -131,9 +131,21 @@ PM_API int pm_bvh_get_info(const pm_bvh *bvh, pm_bvh_info *info);
 PM_API int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t, void *stream);
 
 /* Traversal kernels: one ray per lane for the whole walk; persistent
- * wavefronts whose finished lanes take new rays from a work counter; or one
- * ray per lane testing nodes i and i+1 from one memory round trip. */
-enum { PM_TRACE_AUTO = 0, PM_TRACE_PER_RAY = 1, PM_TRACE_PERSISTENT = 2, PM_TRACE_PAIRED = 3 };
+ * wavefronts whose finished lanes take new rays from a work counter; one
+ * ray per lane testing nodes i and i+1 from one memory round trip; one ray
+ * per lane with leaf tests postponed until the wavefront's lanes hold leaf
+ * hits together (box visits and triangle tests then run in separate phases
+ * instead of sharing each iteration); or two consecutive rays per lane walked
+ * in lockstep (two node loads in flight per lane).  All return the same
+ * result. */
+enum {
+    PM_TRACE_AUTO = 0,
+    PM_TRACE_PER_RAY = 1,
+    PM_TRACE_PERSISTENT = 2,
+    PM_TRACE_PAIRED = 3,
+    PM_TRACE_POSTPONED = 4,
+    PM_TRACE_TWO_RAYS = 5
+};
 
 typedef struct {
     uint32_t size;      /* sizeof(pm_trace_opts) */
@@ -142,7 +154,10 @@ typedef struct {
     uint32_t *counters; /* optional device [n][2]: AABB tests, triangle tests */
     int32_t kernel;     /* PM_TRACE_* */
     int32_t refill;     /* persistent kernel: idle lanes that trigger a refill
-                           (1..64; 0 = default 16) */
+                           (1..64; 0 = default 16).  Postponed kernel: lanes
+                           of a wavefront still searching for a leaf hit at
+                           which the held leaves are tested (0..63; 0 = only
+                           once no lane is searching) */
     int32_t reorder;    /* 1: first bucket the rays by (link set, origin cell of
                            a 16^3 grid over the scene, Morton order) and trace
                            them in that order; 2: the same with a 32^3 grid and
@@ -150,6 +165,8 @@ typedef struct {
                            (for incoherent batches; results are unchanged and
                            written to each ray's own slot).  Uses a
                            library-owned scratch of 4 B per ray. */
+    int32_t block;      /* threads per workgroup of every kernel but the
+                           persistent one: 64, 128 or 256 (0 = default) */
 } pm_trace_opts;
 
 /* pm_trace_rays with options (ablation of the link-set choice; per-ray

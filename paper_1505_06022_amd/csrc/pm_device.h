@@ -219,29 +219,16 @@ struct Walker {
     // Next node: i + 1 after an inner-node hit or any leaf, else the skip link.
     template <bool kStats>
     __device__ __forceinline__ void step(const float4 *__restrict__ tris, TraceStats &st) {
-        uint4 q = nodes[i];
-        float tx0 = fmaf((float)(q.x & 0xffffu), sx, bx), tx1 = fmaf((float)(q.y >> 16), sx, bx);
-        float ty0 = fmaf((float)(q.x >> 16), sy, by), ty1 = fmaf((float)(q.z & 0xffffu), sy, by);
-        float tz0 = fmaf((float)(q.y & 0xffffu), sz, bz), tz1 = fmaf((float)(q.z >> 16), sz, bz);
-        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tbest));
+        visit<kStats>(nodes[i], tris, st);
+    }
+
+    // The visit of node i once its record q has been loaded.
+    template <bool kStats>
+    __device__ __forceinline__ void visit(const uint4 &q, const float4 *__restrict__ tris, TraceStats &st) {
         const bool leaf = (q.w >> 31) != 0u;
-        const bool hit = tn <= tf;
+        const bool hit = box_hit(q);
         if (kStats) st.boxes++;
-        if (hit && leaf) {
-            uint32_t first = (q.w >> 3) & 0x0fffffffu, cnt = q.w & 7u;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                Tri tr = load_tri(tris, first + k);
-                if (kStats) st.tris++;
-                if (tr.id == exclude) continue;
-                float t;
-                if (mt_hit(o, d, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
-                    tbest = t;
-                    best = tr.id;
-                    best_k = first + k;
-                }
-            }
-        }
+        if (hit && leaf) leaf_tris<kStats>(tris, q.w, st);
         i = (hit || leaf) ? i + 1 : q.w;
     }
 
@@ -294,8 +281,66 @@ struct Walker {
         i = (hit || leaf) ? i + 1 : q1.w;
     }
 
+    // The whole walk with postponed leaf tests.  The wave visits boxes until
+    // at most `late` of its lanes are still looking for a leaf hit (and at
+    // least one lane holds one); then every lane that holds a leaf tests its
+    // triangles, all lanes together.  A lane that holds a leaf keeps visiting
+    // boxes while others search and halts in front of its next leaf hit, which
+    // it visits again after the tests.  Each box iteration advances every
+    // searching lane, so the walk ends.  The closest hit under the lower-index
+    // tie rule does not depend on the order of the visits: the result is the
+    // one of step().
+    template <bool kStats>
+    __device__ __forceinline__ void walk_postponed(const float4 *__restrict__ tris, uint32_t late, TraceStats &st) {
+        uint32_t held = 0u;  // link word of a leaf hit not yet tested, or 0
+        bool halted = false;
+        for (;;) {
+            for (;;) {
+                const uint64_t searching = __ballot(i < n && held == 0u);
+                if (searching == 0ull) break;
+                if ((uint32_t)__popcll(searching) <= late && __ballot(held != 0u) != 0ull) break;
+                if (i < n && !halted) {
+                    uint4 q = nodes[i];
+                    if (kStats) st.boxes++;
+                    const bool leaf = (q.w >> 31) != 0u, hit = box_hit(q);
+                    if (hit && leaf) {
+                        if (held == 0u) {
+                            held = q.w;
+                            ++i;
+                        } else {
+                            halted = true;
+                        }
+                    } else {
+                        i = (hit || leaf) ? i + 1 : q.w;
+                    }
+                }
+            }
+            if (__ballot(held != 0u) == 0ull) break;  // no lane searching and none holding: all done
+            if (held != 0u) leaf_tris<kStats>(tris, held, st);
+            held = 0u;
+            halted = false;
+        }
+    }
+
     __device__ __forceinline__ float t_hit() const { return best >= 0 ? tbest : __builtin_inff(); }
 };
+
+// Two rays per lane walked in lockstep: both node records are requested
+// before either box is tested, so each lane keeps two loads in flight.  A
+// walker that has finished re-reads node 0 of its link set (an in-bounds,
+// cached address) and is left unchanged until the other one finishes.
+template <bool kStats>
+__device__ __forceinline__ void walk_two(Walker &a, Walker &b, const float4 *__restrict__ tris, TraceStats &sa,
+                                         TraceStats &sb) {
+    for (;;) {
+        const bool da = a.done(), db = b.done();
+        if (da && db) break;
+        const uint4 qa = a.nodes[da ? 0u : a.i];
+        const uint4 qb = b.nodes[db ? 0u : b.i];
+        if (!da) a.visit<kStats>(qa, tris, sa);
+        if (!db) b.visit<kStats>(qb, tris, sb);
+    }
+}
 
 // Returns the original index of the closest triangle (-1: none); t_out gets
 // its distance (+inf on a miss) and k_out its position in the triangle array.

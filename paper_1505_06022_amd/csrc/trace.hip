@@ -8,52 +8,94 @@
 namespace {
 
 constexpr int kTraceBlock = 256;
+constexpr int kDefaultWalkBlock = 256;  // workgroup of the one-ray-per-lane kernels
 constexpr uint32_t kNoRay = 0xffffffffu;
 
-// One ray per lane.  rays: [n][2] float4 = (o.xyz, tmin), (d.xyz, tmax).
-template <bool kStats>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(pmd::Bvh bvh, const float4 *__restrict__ rays, int64_t n,
-                                                       int32_t *__restrict__ hit, float *__restrict__ tout,
-                                                       int32_t force_set, uint32_t *__restrict__ counters) {
-    uint32_t blk = pmd::xcd_block(blockIdx.x, gridDim.x);
-    int64_t i = (int64_t)blk * kTraceBlock + threadIdx.x;
-    if (i >= n) return;
-    float4 r0 = rays[2 * i], r1 = rays[2 * i + 1];
-    pmd::V3 o = pmd::v3(r0.x, r0.y, r0.z), d = pmd::v3(r1.x, r1.y, r1.z);
-    int set = force_set >= 0 ? force_set : pmd::link_set(d);
-    pmd::TraceStats st{0u, 0u};
-    float t;
-    uint32_t kpos;
-    int32_t h = pmd::closest_hit<kStats>(bvh, set, o, d, r0.w, r1.w, -1, t, kpos, st);
-    hit[i] = h;
-    tout[i] = t;
-    if (kStats) {
-        counters[2 * i] = st.boxes;
-        counters[2 * i + 1] = st.tris;
+// Walk orders: one ray per lane, one node per visit with the leaf's
+// triangles tested at once (kWalkStep); nodes i and i + 1 from one memory
+// round trip (kWalkPaired); leaf tests postponed until the wave's lanes hold
+// leaves together (kWalkPostponed); or two rays per lane in lockstep
+// (kWalkTwo).  All give the same closest hit.
+enum { kWalkStep = 0, kWalkPaired = 1, kWalkPostponed = 2, kWalkTwo = 3 };
+
+template <int kWalk, bool kStats>
+__device__ __forceinline__ void walk(pmd::Walker &w, const float4 *__restrict__ tris, uint32_t late,
+                                     pmd::TraceStats &st) {
+    if (kWalk == kWalkPostponed) {
+        w.walk_postponed<kStats>(tris, late, st);
+    } else {
+        while (!w.done()) {
+            if (kWalk == kWalkPaired) w.step2<kStats>(tris, st);
+            else w.step<kStats>(tris, st);
+        }
     }
 }
 
-// One ray per lane, two node visits per memory round trip where possible.
-template <bool kStats>
-__global__ __launch_bounds__(kTraceBlock) void k_trace2(pmd::Bvh bvh, const float4 *__restrict__ rays, int64_t n,
-                                                        int32_t *__restrict__ hit, float *__restrict__ tout,
-                                                        int32_t force_set, uint32_t *__restrict__ counters) {
-    uint32_t blk = pmd::xcd_block(blockIdx.x, gridDim.x);
-    int64_t i = (int64_t)blk * kTraceBlock + threadIdx.x;
-    if (i >= n) return;
-    float4 r0 = rays[2 * i], r1 = rays[2 * i + 1];
+// rays: [n][2] float4 = (o.xyz, tmin), (d.xyz, tmax).
+__device__ __forceinline__ void start_walk(pmd::Walker &w, const pmd::Bvh &bvh, const float4 *__restrict__ rays,
+                                           size_t r, int32_t force_set) {
+    float4 r0 = rays[2 * r], r1 = rays[2 * r + 1];
     pmd::V3 o = pmd::v3(r0.x, r0.y, r0.z), d = pmd::v3(r1.x, r1.y, r1.z);
     int set = force_set >= 0 ? force_set : pmd::link_set(d);
-    pmd::TraceStats st{0u, 0u};
-    pmd::Walker w;
     w.init(bvh, set, o, d, r0.w, r1.w, -1);
-    while (!w.done()) w.step2<kStats>(bvh.tris, st);
-    hit[i] = w.best;
-    tout[i] = w.t_hit();
+}
+
+template <bool kStats>
+__device__ __forceinline__ void finish_walk(const pmd::Walker &w, const pmd::TraceStats &st, size_t r,
+                                            int32_t *__restrict__ hit, float *__restrict__ tout,
+                                            uint32_t *__restrict__ counters) {
+    hit[r] = w.best;
+    tout[r] = w.t_hit();
     if (kStats) {
-        counters[2 * i] = st.boxes;
-        counters[2 * i + 1] = st.tris;
+        counters[2 * r] = st.boxes;
+        counters[2 * r + 1] = st.tris;
     }
+}
+
+// The rays of slot j: ray j (kPerm false) or perm[j]; two consecutive slots
+// per lane for kWalkTwo.  Results go to each ray's own index.
+template <bool kStats, int kWalk, bool kPerm>
+__device__ __forceinline__ void trace_slot(const pmd::Bvh &bvh, const float4 *__restrict__ rays,
+                                           const uint32_t *__restrict__ perm, uint64_t lane, uint64_t n,
+                                           int32_t *__restrict__ hit, float *__restrict__ tout, int32_t force_set,
+                                           uint32_t *__restrict__ counters, uint32_t late) {
+    if (kWalk == kWalkTwo) {
+        const uint64_t ja = 2 * lane, jb = ja + 1;
+        if (ja >= n) return;
+        const size_t ra = kPerm ? perm[ja] : ja;
+        const bool has_b = jb < n;
+        const size_t rb = has_b ? (kPerm ? perm[jb] : jb) : 0;
+        pmd::Walker a, b;
+        pmd::TraceStats sa{0u, 0u}, sb{0u, 0u};
+        start_walk(a, bvh, rays, ra, force_set);
+        if (has_b) {
+            start_walk(b, bvh, rays, rb, force_set);
+        } else {  // no second ray: a walker that is done from the start
+            b = a;
+            b.i = b.n = 0u;
+        }
+        pmd::walk_two<kStats>(a, b, bvh.tris, sa, sb);
+        finish_walk<kStats>(a, sa, ra, hit, tout, counters);
+        if (has_b) finish_walk<kStats>(b, sb, rb, hit, tout, counters);
+    } else {
+        if (lane >= n) return;
+        const size_t r = kPerm ? perm[lane] : lane;
+        pmd::Walker w;
+        pmd::TraceStats st{0u, 0u};
+        start_walk(w, bvh, rays, r, force_set);
+        walk<kWalk, kStats>(w, bvh.tris, late, st);
+        finish_walk<kStats>(w, st, r, hit, tout, counters);
+    }
+}
+
+// Rays in input order.
+template <bool kStats, int kWalk>
+__global__ __launch_bounds__(kTraceBlock) void k_trace(pmd::Bvh bvh, const float4 *__restrict__ rays, int64_t n,
+                                                       int32_t *__restrict__ hit, float *__restrict__ tout,
+                                                       int32_t force_set, uint32_t *__restrict__ counters,
+                                                       uint32_t late) {
+    const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    trace_slot<kStats, kWalk, false>(bvh, rays, nullptr, lane, (uint64_t)n, hit, tout, force_set, counters, late);
 }
 
 // Persistent wavefronts with ray replacement (the scheduling idea of the
@@ -63,12 +105,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace2(pmd::Bvh bvh, const floa
 // wave takes that many new ray indices from a global counter with one atomic.
 // Every iteration advances each active ray to a strictly larger preorder
 // index, so every wave exits once the counter passes n.
+// With perm, the k-th ray taken is perm[k].
 template <bool kStats>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_persistent(pmd::Bvh bvh, const float4 *__restrict__ rays,
                                                                   uint32_t n, int32_t *__restrict__ hit,
                                                                   float *__restrict__ tout, int32_t force_set,
                                                                   uint32_t *__restrict__ counters,
-                                                                  uint32_t *__restrict__ next, uint32_t refill) {
+                                                                  uint32_t *__restrict__ next, uint32_t refill,
+                                                                  const uint32_t *__restrict__ perm) {
     pmd::Walker w;
     pmd::TraceStats st{0u, 0u};
     uint32_t r = kNoRay;
@@ -92,6 +136,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_persistent(pmd::Bvh bvh, 
             uint32_t rr = pmd::wave_fetch_add(next, idle_mask, idle);
             if (idle) {
                 if (rr < n) {
+                    if (perm) rr = perm[rr];
                     float4 r0 = rays[2 * (size_t)rr], r1 = rays[2 * (size_t)rr + 1];
                     pmd::V3 o = pmd::v3(r0.x, r0.y, r0.z), d = pmd::v3(r1.x, r1.y, r1.z);
                     int set = force_set >= 0 ? force_set : pmd::link_set(d);
@@ -171,32 +216,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_ray_scatter(const float4 *__res
     if (i < n) perm[bucket_add(fill, ray_bucket(rays, i, ob, force_set))] = i;
 }
 
-// One ray per lane, rays taken in the order of perm; results go to each ray's
-// own slot.
-template <bool kStats, bool kPaired>
+// Rays taken in the order of perm.
+template <bool kStats, int kWalk>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const float4 *__restrict__ rays,
                                                             const uint32_t *__restrict__ perm, uint32_t n,
                                                             int32_t *__restrict__ hit, float *__restrict__ tout,
-                                                            int32_t force_set, uint32_t *__restrict__ counters) {
-    uint32_t j = pmd::xcd_block(blockIdx.x, gridDim.x) * kTraceBlock + threadIdx.x;
-    if (j >= n) return;
-    uint32_t i = perm[j];
-    float4 r0 = rays[2 * (size_t)i], r1 = rays[2 * (size_t)i + 1];
-    pmd::V3 o = pmd::v3(r0.x, r0.y, r0.z), d = pmd::v3(r1.x, r1.y, r1.z);
-    int set = force_set >= 0 ? force_set : pmd::link_set(d);
-    pmd::TraceStats st{0u, 0u};
-    pmd::Walker w;
-    w.init(bvh, set, o, d, r0.w, r1.w, -1);
-    while (!w.done()) {
-        if (kPaired) w.step2<kStats>(bvh.tris, st);
-        else w.step<kStats>(bvh.tris, st);
-    }
-    hit[i] = w.best;
-    tout[i] = w.t_hit();
-    if (kStats) {
-        counters[2 * (size_t)i] = st.boxes;
-        counters[2 * (size_t)i + 1] = st.tris;
-    }
+                                                            int32_t force_set, uint32_t *__restrict__ counters,
+                                                            uint32_t late) {
+    const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    trace_slot<kStats, kWalk, true>(bvh, rays, perm, lane, n, hit, tout, force_set, counters, late);
 }
 
 }  // namespace
@@ -274,9 +302,38 @@ static int persistent_grid(hipStream_t s, int device, uint32_t &grid) {
     return PM_OK;
 }
 
+static int walk_of(int kernel) {
+    switch (kernel) {
+    case PM_TRACE_PAIRED: return kWalkPaired;
+    case PM_TRACE_POSTPONED: return kWalkPostponed;
+    case PM_TRACE_TWO_RAYS: return kWalkTwo;
+    default: return kWalkStep;
+    }
+}
+
+template <class K>
+static K pick_walk(int wk, K step, K paired, K postponed, K two) {
+    return wk == kWalkPaired ? paired : wk == kWalkPostponed ? postponed : wk == kWalkTwo ? two : step;
+}
+
+static int launch_persistent(const pm_bvh *b, const pmd::Bvh &bvh, const float *rays, uint32_t n, int32_t *hit,
+                             float *t, int link_set, uint32_t *counters, int refill, const uint32_t *perm,
+                             hipStream_t s) {
+    uint32_t grid = 0;
+    int rc = persistent_grid(s, b->device, grid);
+    if (rc) return rc;
+    uint32_t rf = refill > 0 ? (uint32_t)refill : 16u;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->d_next);
+    auto kern = counters ? k_trace_persistent<true> : k_trace_persistent<false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kTraceBlock), 0, s, bvh, (const float4 *)rays, n, hit, t, link_set,
+                       counters, b->d_next, rf, perm);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
 static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *rays, int64_t n, int32_t *hit,
-                                  float *t, int link_set, uint32_t *counters, int kernel, int reorder,
-                                  hipStream_t s) {
+                                  float *t, int link_set, uint32_t *counters, int kernel, uint32_t late,
+                                  int reorder, uint32_t block, hipStream_t s) {
     if ((uint64_t)n > b->perm_cap) {
         if (b->d_perm) {
             PM_HIP(hipStreamSynchronize(s));
@@ -306,60 +363,55 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
     launch_bucket_scan(counts, start, fill, bsum, nbk, s);
     hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
                        fill, b->d_perm);
-    const bool paired = kernel == PM_TRACE_PAIRED;
-    auto kern = counters ? (paired ? k_trace_perm<true, true> : k_trace_perm<true, false>)
-                         : (paired ? k_trace_perm<false, true> : k_trace_perm<false, false>);
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kTraceBlock), 0, s, bvh, (const float4 *)rays,
-                       (const uint32_t *)b->d_perm, nn, hit, t, link_set, counters);
+    if (kernel == PM_TRACE_PERSISTENT)
+        return launch_persistent(b, bvh, rays, nn, hit, t, link_set, counters, (int)late, b->d_perm, s);
+    using Kern = void (*)(pmd::Bvh, const float4 *, const uint32_t *, uint32_t, int32_t *, float *, int32_t,
+                          uint32_t *, uint32_t);
+    const int wk = walk_of(kernel);
+    Kern kern = counters ? pick_walk<Kern>(wk, k_trace_perm<true, kWalkStep>, k_trace_perm<true, kWalkPaired>,
+                                           k_trace_perm<true, kWalkPostponed>, k_trace_perm<true, kWalkTwo>)
+                         : pick_walk<Kern>(wk, k_trace_perm<false, kWalkStep>, k_trace_perm<false, kWalkPaired>,
+                                           k_trace_perm<false, kWalkPostponed>, k_trace_perm<false, kWalkTwo>);
+    const uint32_t lanes = wk == kWalkTwo ? (nn + 1) / 2 : nn;
+    hipLaunchKernelGGL(kern, dim3((lanes + block - 1) / block), dim3(block), 0, s, bvh, (const float4 *)rays,
+                       (const uint32_t *)b->d_perm, nn, hit, t, link_set, counters, late);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }
 
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, int reorder, hipStream_t s) {
+                 uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s) {
+    if (block == 0) block = kDefaultWalkBlock;
     if (n == 0) return PM_OK;
     pmd::Bvh bvh = make_device_bvh(b);
+    // the postponed walk reads its threshold from the refill option (and the
+    // persistent one its refill count)
+    const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT ? (uint32_t)refill : 0u;
     if (reorder)
         return launch_trace_reordered(const_cast<pm_bvh *>(b), bvh, rays, n, hit, t, link_set, counters, kernel,
-                                      reorder, s);
+                                      late, reorder, (uint32_t)block, s);
     if (kernel == 0) kernel = PM_TRACE_PER_RAY;
     if (kernel == PM_TRACE_PERSISTENT) {
         if (n >= (int64_t(1) << 31)) {
             set_error("too many rays for one launch");
             return PM_ERR_ARG;
         }
-        uint32_t grid = 0;
-        int rc = persistent_grid(s, b->device, grid);
-        if (rc) return rc;
-        uint32_t rf = refill > 0 ? (uint32_t)refill : 16u;
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->d_next);
-        if (counters)
-            hipLaunchKernelGGL(k_trace_persistent<true>, dim3(grid), dim3(kTraceBlock), 0, s, bvh,
-                               (const float4 *)rays, (uint32_t)n, hit, t, link_set, counters, b->d_next, rf);
-        else
-            hipLaunchKernelGGL(k_trace_persistent<false>, dim3(grid), dim3(kTraceBlock), 0, s, bvh,
-                               (const float4 *)rays, (uint32_t)n, hit, t, link_set, counters, b->d_next, rf);
-        PM_HIP(hipGetLastError());
-        return PM_OK;
+        return launch_persistent(b, bvh, rays, (uint32_t)n, hit, t, link_set, counters, refill, nullptr, s);
     }
-    int64_t nblk = (n + kTraceBlock - 1) / kTraceBlock;
+    const int wk = walk_of(kernel);
+    const int64_t lanes = wk == kWalkTwo ? (n + 1) / 2 : n;
+    int64_t nblk = (lanes + block - 1) / block;
     if (nblk > 0x7fffffff) {
         set_error("too many rays for one launch");
         return PM_ERR_ARG;
     }
-    dim3 grid((uint32_t)nblk), block(kTraceBlock);
-    if (kernel == PM_TRACE_PAIRED) {
-        if (counters)
-            hipLaunchKernelGGL(k_trace2<true>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set,
-                               counters);
-        else
-            hipLaunchKernelGGL(k_trace2<false>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set,
-                               counters);
-    } else if (counters) {
-        hipLaunchKernelGGL(k_trace<true>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set, counters);
-    } else {
-        hipLaunchKernelGGL(k_trace<false>, grid, block, 0, s, bvh, (const float4 *)rays, n, hit, t, link_set, counters);
-    }
+    using Kern = void (*)(pmd::Bvh, const float4 *, int64_t, int32_t *, float *, int32_t, uint32_t *, uint32_t);
+    Kern kern = counters ? pick_walk<Kern>(wk, k_trace<true, kWalkStep>, k_trace<true, kWalkPaired>,
+                                           k_trace<true, kWalkPostponed>, k_trace<true, kWalkTwo>)
+                         : pick_walk<Kern>(wk, k_trace<false, kWalkStep>, k_trace<false, kWalkPaired>,
+                                           k_trace<false, kWalkPostponed>, k_trace<false, kWalkTwo>);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)nblk), dim3(block), 0, s, bvh, (const float4 *)rays, n, hit, t,
+                       link_set, counters, late);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

@@ -189,6 +189,80 @@ def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, s
                 assert np.float32(t) == t_ref[r]
 
 
+def _py_wave_postponed(nodes, tris, info, rays, s, late):
+    """Lockstep model of one wavefront running the postponed-leaf walk: box
+    visits until at most `late` lanes still search (and one lane holds a leaf),
+    then every held leaf is tested; a holding lane halts at its next leaf hit."""
+    lo, hi, leaf, first, cnt, skip = _decode(nodes[s], info)
+    tf = _f(tris)
+    L, n = len(rays), nodes.shape[1]
+    o = rays[:, 0:3].astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = 1.0 / rays[:, 4:7].astype(np.float64)
+    tmin = rays[:, 3].astype(np.float64)
+    tb = rays[:, 7].astype(np.float64).copy()
+    best = np.full(L, -1)
+    i = np.zeros(L, np.int64)
+    held = np.full(L, -1)
+    halted = np.zeros(L, bool)
+    visits = 0
+
+    def box_hit(r, k):
+        t0, t1 = (lo[k] - o[r]) * inv[r], (hi[k] - o[r]) * inv[r]
+        with np.errstate(invalid="ignore"):
+            tn = np.nanmax(np.concatenate([np.minimum(t0, t1), [tmin[r]]]))
+            tf_ = np.nanmin(np.concatenate([np.maximum(t0, t1), [tb[r]]]))
+        return tn <= tf_ * (1 + 1e-6) + 1e-12
+
+    while True:
+        while True:
+            searching = (i < n) & (held < 0)
+            if not searching.any():
+                break
+            if searching.sum() <= late and (held >= 0).any():
+                break
+            visits += 1
+            assert visits < 64 * n, "box loop does not end"
+            for r in range(L):
+                if i[r] >= n or halted[r]:
+                    continue
+                k = i[r]
+                hit = box_hit(r, k)
+                if hit and leaf[k]:
+                    if held[r] < 0:
+                        held[r], i[r] = k, k + 1
+                    else:
+                        halted[r] = True
+                else:
+                    i[r] = k + 1 if (hit or leaf[k]) else skip[k]
+        if not (held >= 0).any():
+            break
+        for r in np.nonzero(held >= 0)[0]:
+            k = held[r]
+            for j in range(first[k], first[k] + cnt[k]):
+                t = _mt32(rays[r], tf[j])
+                idx = int(tris[j, 9])
+                if t is not None and t > tmin[r] and (t < tb[r] or (t == tb[r] and best[r] >= 0 and idx < best[r])):
+                    tb[r], best[r] = t, idx
+        held[:] = -1
+        halted[:] = False
+    return best, tb
+
+
+@pytest.mark.parametrize("late", [0, 5, 63])
+def test_postponed_leaf_walk_model_matches_brute_force(oracle_lib, late):
+    """The wave schedule of the postponed traversal kernel, modelled on the
+    CPU: it ends, and every lane's closest hit equals brute force."""
+    sc = scenes.small_soup(300, 4, spread=0.4 / np.cbrt(300))
+    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
+    rays = scenes.random_rays(64, 4)
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+    for s in (0, 3):
+        h, t = _py_wave_postponed(nodes, tris, info, rays, s, late)
+        assert np.array_equal(h, h_ref)
+        assert np.array_equal(np.float32(t[h >= 0]), t_ref[h >= 0])
+
+
 def test_host_bvh_box_scene_and_soup_statistics():
     sc = scenes.box_scene()
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)

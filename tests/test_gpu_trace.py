@@ -86,18 +86,22 @@ def test_every_link_set_and_stats_mode_agree(torch_cuda, oracle_lib):
     assert np.all(c[:, 0] >= 1) and np.all(c[:, 1] >= (h >= 0))
 
 
-@pytest.mark.parametrize("kernel,refill,reorder", [(1, 0, False), (2, 1, False), (2, 16, False), (2, 64, False),
-                                                   (1, 0, 1), (1, 0, 2), (3, 0, 0)])
-def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder):
-    _log(f"case: traversal kernel={kernel} refill={refill} reorder={reorder}")
+@pytest.mark.parametrize("kernel,refill,reorder,block", [
+    (1, 0, False, 0), (2, 1, False, 0), (2, 16, False, 0), (2, 64, False, 0), (1, 0, 1, 0), (1, 0, 2, 0),
+    (3, 0, 0, 0), (4, 0, 0, 0), (4, 7, 0, 0), (4, 63, 0, 0), (4, 0, 1, 0), (4, 16, 2, 0), (3, 0, 1, 0),
+    (1, 0, 0, 64), (1, 0, 1, 128), (4, 16, 1, 64), (3, 0, 0, 128), (5, 0, 0, 0), (5, 0, 1, 64),
+    (5, 0, 2, 128), (2, 16, 1, 0), (2, 1, 2, 0)])
+def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder, block):
+    _log(f"case: traversal kernel={kernel} refill={refill} reorder={reorder} block={block}")
     sc = scenes.small_soup(5000, 11, spread=0.02)
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     rays = np.concatenate([scenes.random_rays(7001, 11), scenes.pinhole_rays(sc.camera)])
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
-    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, reorder=reorder)
+    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, reorder=reorder, block=block)
     _compare(h, t, h_ref, t_ref)
     cnt = torch_cuda.zeros((len(rays), 2), dtype=torch_cuda.int32, device="cuda")
-    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, counters=cnt, reorder=reorder)
+    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, counters=cnt, reorder=reorder,
+                      block=block)
     _compare(h, t, h_ref, t_ref)
 
 
@@ -114,8 +118,17 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
     assert np.array_equal(h, h1) and np.array_equal(t, t1)
     h3, t3 = _gpu_trace(torch_cuda, bvh, rays, kernel=3)     # paired node visits: identical
     assert np.array_equal(h, h3) and np.array_equal(t, t3)
+    for late in (0, 8):                                       # postponed leaf tests: identical
+        h4, t4 = _gpu_trace(torch_cuda, bvh, rays, kernel=4, refill=late)
+        assert np.array_equal(h, h4) and np.array_equal(t, t4)
+    h5, t5 = _gpu_trace(torch_cuda, bvh, rays, kernel=5)     # two rays per lane: identical
+    assert np.array_equal(h, h5) and np.array_equal(t, t5)
+    h5, t5 = _gpu_trace(torch_cuda, bvh, rays[:-1], kernel=5, reorder=1, block=64)   # odd count
+    assert np.array_equal(h[:-1], h5) and np.array_equal(t[:-1], t5)
     for level in (1, 2):                                      # reordered: identical
         h2, t2 = _gpu_trace(torch_cuda, bvh, rays, reorder=level)
+        assert np.array_equal(h, h2) and np.array_equal(t, t2)
+        h2, t2 = _gpu_trace(torch_cuda, bvh, rays, reorder=level, kernel=4)
         assert np.array_equal(h, h2) and np.array_equal(t, t2)
     rng = np.random.default_rng(123)
     pick = np.concatenate([rng.choice(len(coh), 4096, replace=False),
@@ -127,3 +140,17 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
     h2, t2 = osc.trace(rays[pick2])
     _compare(h[pick2], t[pick2], h2, t2)
     assert (h[:len(coh)] >= 0).mean() > 0.3    # the 16:9 view extends past the cube
+
+
+def test_trace_option_errors(torch_cuda):
+    """Invalid options are rejected by the host before any launch."""
+    _log("case: trace option validation")
+    sc = scenes.small_soup(64, 1)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    r = torch_cuda.from_numpy(scenes.random_rays(100, 1)).cuda()
+    for kw in (dict(block=100), dict(block=512), dict(kernel=6), dict(kernel=4, refill=64), dict(reorder=3),
+               dict(link_set=6)):
+        with pytest.raises(api.PMError) as e:
+            api.trace_rays(bvh, r, **kw)
+        assert e.value.code == api.PM_ERR_ARG, kw
+    bvh.destroy()
