@@ -166,6 +166,25 @@ def traversal_bench(args, torch, api, scenes):
         ms /= 3
         variants[name] = {"coherent_mrays_s": round(len(rc) / ms[0] / 1e3, 1),
                           "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1)}
+    # the paper's TBVH comparison: every ray walks one link set (a single threaded BVH),
+    # with the timed kernel options
+    tbvh = {}
+    if not args.no_variants:
+        for ls in range(6):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
+            ms = np.zeros(len(batches))
+            for rep in range(4):
+                for b, (r, (h, t), kw) in enumerate(zip(batches, outs, trace_kw)):
+                    e[2 * b].record(stream)
+                    api.trace_rays(bvh, r, h, t, link_set=ls, **kw)
+                    e[2 * b + 1].record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    ms += [e[2 * b].elapsed_time(e[2 * b + 1]) for b in range(len(batches))]
+            ms /= 3
+            tbvh[f"link_set_{ls}"] = {"coherent_mrays_s": round(len(rc) / ms[0] / 1e3, 1),
+                                      "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1),
+                                      "mrays_s": round((len(rc) + len(ri)) / ms.sum() / 1e3, 1)}
     # SAH node-visit cost (relative to a triangle test): tree size vs traversal rate
     sah = {}
     if not args.no_variants:
@@ -196,7 +215,7 @@ def traversal_bench(args, torch, api, scenes):
     hit_frac = float((outs[0][0] >= 0).float().mean().item())
     return dict(
         n_rays=n_rays, step_ms=step_ms, kern_ms=kern_ms, info=info, per_batch=per_batch,
-        achieved=achieved, per_launch_bytes=per_launch_bytes, hit_frac=hit_frac, variants=variants,
+        achieved=achieved, per_launch_bytes=per_launch_bytes, hit_frac=hit_frac, variants=variants, tbvh=tbvh,
         coherent_mrays=len(rc) / (kern_ms[:, 0].mean() * 1e-3) / 1e6,
         incoherent_mrays=len(ri) / (kern_ms[:, 1].mean() * 1e-3) / 1e6,
         scene=sc, rays=(coh, inc),
@@ -209,7 +228,8 @@ def sppm_bench(args, torch, api, scenes):
     diag = float(np.linalg.norm(v.max(0) - v.min(0)))
     Np = 1 << 20
     p = api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3)
-    s = api.Sppm(sc, p)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    s = api.Sppm(sc, p, bvh=bvh)
     s.iterate(2)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
@@ -222,21 +242,24 @@ def sppm_bench(args, torch, api, scenes):
     s.status()
     n_stored = int(s.views()["photon_count"][0].item())
     s.destroy()
-    variants = {}
-    for name, kw in (("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
-                     ("regen_refill16", dict(photon_kernel=2, refill=16)),
-                     ("regen_refill32", dict(photon_kernel=2, refill=32))):
-        sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, **kw))
+    variants, tbvh = {}, {}
+    runs = [("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
+            ("regen_refill16", dict(photon_kernel=2, refill=16)), ("regen_refill32", dict(photon_kernel=2, refill=32))]
+    # the paper's TBVH comparison: every ray walks one link set (a single threaded BVH)
+    runs += [(f"single_link_set_{k}", dict(single_link_set=k + 1)) for k in range(6)]
+    for name, kw in runs:
+        sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, **kw), bvh=bvh)
         sv.iterate(1)
         torch.cuda.synchronize()
         e0.record(st)
         sv.iterate(3)
         e1.record(st)
         torch.cuda.synchronize()
-        variants[name] = round(e0.elapsed_time(e1) / 3, 3)
+        (tbvh if name.startswith("single") else variants)[name] = round(e0.elapsed_time(e1) / 3, 3)
         sv.destroy()
+    bvh.destroy()
     return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
-                workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
+                tbvh=tbvh, workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
 def adjoint_bench(args, torch, api, scenes):
@@ -332,10 +355,29 @@ def cpu_baseline(tb, scenes):
     t0 = time.perf_counter()
     osc.trace(bf, brute_force=True, nthreads=nth)
     dt_bf = time.perf_counter() - t0
+    # the oracle's SPPM: the full box configuration, and one reduced iteration of the procedural scene
+    sppm = {}
+    box = oracle.OracleScene(scenes.box_scene(64, 64))
+    t0 = time.perf_counter()
+    oracle.sppm_run(box, 1, 1 << 14, 2, r0=0.05 * np.sqrt(3.0), nthreads=nth)
+    dt_box = (time.perf_counter() - t0) / 2
+    sppm["box_64x64_2^14_photons"] = {"s_per_iteration": round(dt_box, 4),
+                                      "photons_per_s": round((1 << 14) / dt_box, 1)}
+    sc = scenes.procedural_scene()
+    v = sc.verts.reshape(-1, 3)
+    diag = float(np.linalg.norm(v.max(0) - v.min(0)))
+    proc = oracle.OracleScene(sc, use_bvh=True)
+    t0 = time.perf_counter()
+    oracle.sppm_run(proc, 3, 1 << 20, 2, r0=0.05 * diag * 64 / 1280, nthreads=nth)
+    dt_proc = (time.perf_counter() - t0) / 2
+    sppm["procedural_1280x720_2^20_photons"] = {"s_per_iteration": round(dt_proc, 3),
+                                                "photons_per_s": round((1 << 20) / dt_proc, 1),
+                                                "note": "2 of the configuration's 64 iterations"}
     return {"value": len(sample) / dt / 1e6, "unit": "Mrays/s", "cores": nth, "kind": "oracle",
             "sample": (f"oracle median-split BVH over the same 2^20-triangle soup, 2^18 coherent + 2^18 "
                        f"incoherent rays sampled from the workload (build {t_build:.2f} s not counted); "
-                       f"brute force over all triangles: {len(bf) / dt_bf:.1f} rays/s on 512 of them")}
+                       f"brute force over all triangles: {len(bf) / dt_bf:.1f} rays/s on 512 of them"),
+            "sppm": sppm}
 
 
 def main():
@@ -378,6 +420,10 @@ def main():
         "kernel_mrays_s": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6, 2),
         "bvh": {k: tb["info"][k] for k in ("n_nodes", "n_leaves", "depth", "sah_cost", "device_bytes", "build_ms")},
         "kernel_variants": tb["variants"],
+        "tbvh_ablation": ({"single_link_set": tb["tbvh"],
+                           "mtbvh_over_mean_tbvh": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6 /
+                                                         float(np.mean([v["mrays_s"] for v in tb["tbvh"].values()])), 3)}
+                          if tb["tbvh"] else None),
         "traversal_stats": [{"rays": int(n), "boxes_per_ray": round(vn / n, 2), "tris_per_ray": round(vt / n, 2)}
                             for vn, vt, n in tb["per_batch"]],
         "roofline": {"bound": "hbm", "achieved": round(tb["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -392,7 +438,10 @@ def main():
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
                        "stored_photons": sp["n_stored"], "workload": sp["workload"],
-                       "iteration_ms_by_photon_kernel": sp["variants"]}
+                       "iteration_ms_by_photon_kernel": sp["variants"],
+                       "tbvh_ablation": {"iteration_ms_single_link_set": sp["tbvh"],
+                                         "mean_ratio_tbvh_over_mtbvh": round(
+                                             float(np.mean(list(sp["tbvh"].values()))) / sp["iteration_ms"], 3)}}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, torch, api, scenes)
     if not args.no_batch:

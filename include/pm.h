@@ -212,6 +212,11 @@ typedef struct {
     int32_t photon_kernel;    /* PM_PHOTON_*: 0 = default (regeneration) */
     int32_t refill;           /* regeneration: idle lanes of a wave that
                                  trigger taking new paths (1..64; 0 = 16) */
+    int32_t single_link_set;  /* 0: each ray walks the link set of its
+                                 direction (MTBVH, Sec. 3.1); s + 1 (1..6):
+                                 every ray walks link set s, i.e. a single
+                                 threaded BVH (the paper's TBVH comparison).
+                                 Results are identical; only speed differs. */
 } pm_sppm_params;
 
 /* Photon pass scheduling (results are identical): one lane traces one whole
@@ -236,6 +241,29 @@ PM_API int pm_sppm_resolve(pm_sppm *s, float *image, void *stream);
 
 /* Synchronise `stream` and report sticky device errors (PM_ERR_OVERFLOW). */
 PM_API int pm_sppm_status(pm_sppm *s, void *stream);
+
+/* Checkpoint of an SPPM handle: the per-pixel state (N, R^2, tau, D as
+ * float64), the iteration count K, the sticky overflow flag and, for a
+ * handle that records iterations for the adjoint, the radii of the recorded
+ * iterations.  Every random stream is keyed by (seed, kind, iteration,
+ * index) (Sec. 3.2 with counter-keyed seeding), so a handle loaded from a
+ * checkpoint taken after K iterations continues exactly as the saved run
+ * would have: further iterations, images and gradients are bit-identical.
+ *   buf   host memory owned by the caller; NULL queries the size
+ *   size  in: capacity of buf in bytes; out: bytes written (or required)
+ * Synchronises `stream`.  Errors: PM_ERR_ARG (NULL handle or size pointer;
+ * buf smaller than required, with the required size in *size),
+ * PM_ERR_STATE (a member of a batch). */
+PM_API int pm_sppm_save(pm_sppm *s, void *buf, uint64_t *size, void *stream);
+
+/* Restore a checkpoint into a handle created with the same scene and
+ * parameters (checked through a fingerprint of the scene description and the
+ * pixel count, photon count, seed, alpha, r0, fixed-point shift, path-length
+ * caps and recorded-iteration count).  On any mismatch, or a truncated or
+ * foreign buffer, returns PM_ERR_ARG and leaves the handle unchanged.  The
+ * photon store and hashed grid are rebuilt by the next iteration.
+ * Synchronises `stream`. */
+PM_API int pm_sppm_load(pm_sppm *s, const void *buf, uint64_t size, void *stream);
 
 /* create -> K x iterate -> resolve -> status -> destroy. */
 PM_API int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream);

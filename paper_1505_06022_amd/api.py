@@ -21,7 +21,7 @@ PM_OK, PM_ERR_ARG, PM_ERR_HIP, PM_ERR_OVERFLOW, PM_ERR_STATE, PM_ERR_NOMEM = 0, 
 EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host", "pm_bvh_destroy",
            "pm_bvh_get_info", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
-           "pm_sppm_adjoint", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
+           "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
            "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch"]
 
 
@@ -64,7 +64,7 @@ class SppmParams(C.Structure):
     _fields_ = [("size", C.c_uint32), ("n_photons", C.c_int64), ("alpha", C.c_double), ("r0", C.c_double),
                 ("seed", C.c_uint64), ("max_eye_depth", C.c_int32), ("max_photon_bounces", C.c_int32),
                 ("fixed_shift", C.c_int32), ("store_factor", C.c_int32), ("record_iterations", C.c_int32),
-                ("photon_kernel", C.c_int32), ("refill", C.c_int32)]
+                ("photon_kernel", C.c_int32), ("refill", C.c_int32), ("single_link_set", C.c_int32)]
 
 
 PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN = 0, 1, 2
@@ -117,6 +117,8 @@ def lib() -> C.CDLL:
         L.pm_render.argtypes = [P, P, I32, P, P]
         L.pm_sppm_get_views.argtypes = [P, P]
         L.pm_sppm_adjoint.argtypes = [P, P, P, I32, P, P]
+        L.pm_sppm_save.argtypes = [P, P, P, P]
+        L.pm_sppm_load.argtypes = [P, P, C.c_uint64, P]
         L.pm_batch_create.argtypes = [P, P, I32, P, P, P]
         L.pm_batch_destroy.argtypes = [P]
         L.pm_batch_iterate.argtypes = [P, I32, P]
@@ -252,7 +254,8 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
 # SPPM
 # ---------------------------------------------------------------------------
 def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, max_photon_bounces=32,
-                fixed_shift=40, store_factor=8, record_iterations=0, photon_kernel=0, refill=0) -> SppmParams:
+                fixed_shift=40, store_factor=8, record_iterations=0, photon_kernel=0, refill=0,
+                single_link_set=0) -> SppmParams:
     p = SppmParams()
     p.size = C.sizeof(SppmParams)
     p.n_photons, p.alpha, p.r0, p.seed = n_photons, alpha, float(r0), seed
@@ -260,6 +263,7 @@ def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, ma
     p.fixed_shift, p.store_factor = fixed_shift, store_factor
     p.record_iterations = record_iterations
     p.photon_kernel, p.refill = photon_kernel, refill
+    p.single_link_set = single_link_set
     return p
 
 
@@ -347,6 +351,18 @@ class Sppm:
         _check(lib().pm_sppm_get_views(self.h, C.byref(v)))
         return _views_dict(v)
 
+    def save(self, stream=None) -> bytes:
+        """Checkpoint of the per-pixel state, iteration count and recorded radii."""
+        n = C.c_uint64(0)
+        _check(lib().pm_sppm_save(self.h, None, C.byref(n), _stream(stream)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().pm_sppm_save(self.h, buf, C.byref(n), _stream(stream)))
+        return buf.raw[:n.value]
+
+    def load(self, checkpoint: bytes, stream=None):
+        """Continue from a checkpoint taken from a handle with the same scene and parameters."""
+        buf = C.create_string_buffer(bytes(checkpoint), len(checkpoint))
+        _check(lib().pm_sppm_load(self.h, buf, len(checkpoint), _stream(stream)))
 
     def adjoint(self, dloss_dimage, param_mats, grad=None, stream=None):
         """dLoss/drho for each material in param_mats, then dLoss/dLe (float64 cuda tensor)."""

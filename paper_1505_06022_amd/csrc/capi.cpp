@@ -203,6 +203,14 @@ int pm_sppm_adjoint(pm_sppm *s, const float *dloss_dimage, const int32_t *param_
     PM_GUARD({ return pm::sppm_adjoint(s, dloss_dimage, param_mats, n_par, grad, (hipStream_t)stream); })
 }
 
+int pm_sppm_save(pm_sppm *s, void *buf, uint64_t *size, void *stream) {
+    PM_GUARD({ return pm::sppm_save(s, buf, size, (hipStream_t)stream); })
+}
+
+int pm_sppm_load(pm_sppm *s, const void *buf, uint64_t size, void *stream) {
+    PM_GUARD({ return pm::sppm_load(s, buf, size, (hipStream_t)stream); })
+}
+
 int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream) {
     PM_GUARD({
         if (K < 1 || !image) return pm::set_error("K must be >= 1 and image non-NULL"), PM_ERR_ARG;

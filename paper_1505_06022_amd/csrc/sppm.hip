@@ -252,6 +252,8 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
     if (p->photon_kernel < 0 || p->photon_kernel > 2 || p->refill < 0 || p->refill > 64)
         return set_error("photon_kernel must be 0..2 and refill 0..64"), PM_ERR_ARG;
+    if (p->single_link_set < 0 || p->single_link_set > 6)
+        return set_error("single_link_set must be 0 (by direction) or 1..6"), PM_ERR_ARG;
     if (p->record_iterations < 0 || p->record_iterations > 100000)
         return set_error("record_iterations must be in [0, 100000]"), PM_ERR_ARG;
     if (p->record_iterations > 0 && d->n_mat > kMaxAdjMat)
@@ -289,6 +291,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     }
     const pm_bvh *b = s->bvh;
     s->P = (int64_t)d->width * d->height;
+    s->scene_hash = scene_fingerprint(d);
     // emitters in original triangle order, by power = area * Le
     std::vector<uint32_t> epos;
     std::vector<double> ecdf;
@@ -419,6 +422,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.table_off = 0;
     dv.photon_kernel = p->photon_kernel == PM_PHOTON_PER_PATH ? PM_PHOTON_PER_PATH : PM_PHOTON_REGEN;
     dv.refill = p->refill > 0 ? (uint32_t)p->refill : 16u;
+    dv.force_set = p->single_link_set - 1;
     {
         int dev = 0, cus = 0, per_cu = 0;
         PM_HIPF(hipGetDevice(&dev));
@@ -555,6 +559,138 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
     hipLaunchKernelGGL(k_collect_grad, dim3(1), dim3(kMaxAdjMat), 0, st, s->grad_mat, pms, n_par,
                        s->grad_mat + s->n_mat, s->le_single > 0.0 ? 1.0 / s->le_single : 0.0, grad);
     PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
+namespace {
+
+struct HashWords {  // FNV-1a over 32-bit words
+    uint64_t h = 0xcbf29ce484222325ull;
+    void add(const void *p, size_t bytes) {
+        const uint8_t *b = (const uint8_t *)p;
+        for (size_t i = 0; i + 4 <= bytes; i += 4) {
+            uint32_t w;
+            memcpy(&w, b + i, 4);
+            h = (h ^ w) * 0x100000001b3ull;
+        }
+        for (size_t i = bytes & ~(size_t)3; i < bytes; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+    }
+};
+
+// Checkpoint layout: this header, then N, R2, tau, D (f64 [P] each), then
+// n_hist recorded radii (f64 [n_hist][P]).
+struct CheckpointHeader {
+    char magic[8];  // "PMSPPMCK"
+    uint32_t version, header_bytes;
+    int64_t n_pixels, n_photons;
+    uint64_t seed, scene_hash;
+    double alpha, r0;
+    int32_t fixed_shift, max_eye_depth, max_photon_bounces, record_iterations;
+    int32_t iterations, n_hist;
+    uint32_t overflow, reserved;
+};
+constexpr uint32_t kCheckpointVersion = 1;
+
+uint64_t checkpoint_bytes(const pm_sppm *s, int32_t n_hist) {
+    return sizeof(CheckpointHeader) + (uint64_t)(4 + n_hist) * (uint64_t)s->P * sizeof(double);
+}
+
+}  // namespace
+
+uint64_t scene_fingerprint(const pm_scene_desc *d) {
+    HashWords h;
+    h.add(&d->n_tri, sizeof(d->n_tri));
+    h.add(d->tri_verts, sizeof(float) * 9 * (size_t)d->n_tri);
+    h.add(d->tri_mat, sizeof(uint32_t) * (size_t)d->n_tri);
+    h.add(&d->n_mat, sizeof(d->n_mat));
+    h.add(d->mat_type, sizeof(int32_t) * (size_t)d->n_mat);
+    h.add(d->mat_rho, sizeof(float) * (size_t)d->n_mat);
+    h.add(d->mat_q, sizeof(float) * (size_t)d->n_mat);
+    h.add(d->mat_Le, sizeof(float) * (size_t)d->n_mat);
+    h.add(d->mat_ior, sizeof(float) * (size_t)d->n_mat);
+    h.add(d->cam_pos, sizeof(d->cam_pos));
+    h.add(d->cam_look, sizeof(d->cam_look));
+    h.add(d->cam_up, sizeof(d->cam_up));
+    h.add(&d->tan_half_fov, sizeof(d->tan_half_fov));
+    h.add(&d->width, sizeof(d->width));
+    h.add(&d->height, sizeof(d->height));
+    return h.h;
+}
+
+int sppm_save(pm_sppm *s, void *buf, uint64_t *size, hipStream_t st) {
+    if (!s || !size) return set_error("NULL handle or size pointer"), PM_ERR_ARG;
+    if (!s->cell_count) return set_error("handle belongs to a batch"), PM_ERR_STATE;
+    const int32_t n_hist = std::min(s->K, s->rec_iters);
+    const uint64_t need = checkpoint_bytes(s, n_hist);
+    if (!buf) {
+        *size = need;
+        return PM_OK;
+    }
+    if (*size < need) {
+        *size = need;
+        return set_error("checkpoint buffer too small (the required size is returned in *size)"), PM_ERR_ARG;
+    }
+    uint32_t c[4];
+    PM_HIP(hipMemcpyAsync(c, s->counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    CheckpointHeader h{};
+    memcpy(h.magic, "PMSPPMCK", 8);
+    h.version = kCheckpointVersion;
+    h.header_bytes = sizeof(CheckpointHeader);
+    h.n_pixels = s->P;
+    h.n_photons = s->prm.n_photons;
+    h.seed = s->prm.seed;
+    h.scene_hash = s->scene_hash;
+    h.alpha = s->prm.alpha;
+    h.r0 = s->prm.r0;
+    h.fixed_shift = s->prm.fixed_shift;
+    h.max_eye_depth = s->prm.max_eye_depth;
+    h.max_photon_bounces = s->prm.max_photon_bounces;
+    h.record_iterations = s->rec_iters;
+    h.iterations = s->K;
+    h.n_hist = n_hist;
+    uint8_t *out = (uint8_t *)buf;
+    const size_t pb = sizeof(double) * (size_t)s->P;
+    const double *arrays[4] = {s->N, s->R2, s->tau, s->D};
+    for (int a = 0; a < 4; ++a)
+        PM_HIP(hipMemcpyAsync(out + sizeof(h) + a * pb, arrays[a], pb, hipMemcpyDeviceToHost, st));
+    if (n_hist > 0)
+        PM_HIP(hipMemcpyAsync(out + sizeof(h) + 4 * pb, s->R2_hist, pb * (size_t)n_hist, hipMemcpyDeviceToHost, st));
+    PM_HIP(hipStreamSynchronize(st));
+    h.overflow = c[1];
+    memcpy(out, &h, sizeof(h));
+    *size = need;
+    return PM_OK;
+}
+
+int sppm_load(pm_sppm *s, const void *buf, uint64_t size, hipStream_t st) {
+    if (!s || !buf) return set_error("NULL handle or buffer"), PM_ERR_ARG;
+    if (!s->cell_count) return set_error("handle belongs to a batch"), PM_ERR_STATE;
+    CheckpointHeader h;
+    if (size < sizeof(h)) return set_error("checkpoint too short"), PM_ERR_ARG;
+    memcpy(&h, buf, sizeof(h));
+    if (memcmp(h.magic, "PMSPPMCK", 8) != 0 || h.version != kCheckpointVersion || h.header_bytes != sizeof(h))
+        return set_error("not a checkpoint of this format version"), PM_ERR_ARG;
+    if (h.n_pixels != s->P || h.n_photons != s->prm.n_photons || h.seed != s->prm.seed ||
+        h.scene_hash != s->scene_hash || h.alpha != s->prm.alpha || h.r0 != s->prm.r0 ||
+        h.fixed_shift != s->prm.fixed_shift || h.max_eye_depth != s->prm.max_eye_depth ||
+        h.max_photon_bounces != s->prm.max_photon_bounces || h.record_iterations != s->rec_iters)
+        return set_error("checkpoint was taken from a handle with another scene or parameters"), PM_ERR_ARG;
+    if (h.iterations < 0 || h.n_hist != std::min(h.iterations, s->rec_iters) ||
+        size < checkpoint_bytes(s, h.n_hist))
+        return set_error("checkpoint is truncated or inconsistent"), PM_ERR_ARG;
+    const uint8_t *in = (const uint8_t *)buf;
+    const size_t pb = sizeof(double) * (size_t)s->P;
+    double *arrays[4] = {s->N, s->R2, s->tau, s->D};
+    for (int a = 0; a < 4; ++a)
+        PM_HIP(hipMemcpyAsync(arrays[a], in + sizeof(h) + a * pb, pb, hipMemcpyHostToDevice, st));
+    if (h.n_hist > 0)
+        PM_HIP(hipMemcpyAsync(s->R2_hist, in + sizeof(h) + 4 * pb, pb * (size_t)h.n_hist, hipMemcpyHostToDevice, st));
+    if (h.overflow) {
+        const uint32_t one = 1u;
+        PM_HIP(hipMemcpyAsync(s->counters + 1, &one, sizeof(one), hipMemcpyHostToDevice, st));
+    }
+    PM_HIP(hipStreamSynchronize(st));
+    s->K = h.iterations;
     return PM_OK;
 }
 

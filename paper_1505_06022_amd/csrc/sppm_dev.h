@@ -39,6 +39,7 @@ struct SppmDev {
     uint32_t mask, table_off;
     int32_t photon_kernel;    // PM_PHOTON_* (resolved: per path or regenerating)
     uint32_t refill;          // regeneration: idle lanes that trigger a refill
+    int32_t force_set;        // -1: link set by ray direction; 0..5: that set for every ray
     float4 *hp_pos, *hp_nrm;  // (x, W*rho/pi), (n toward the eye, material bits | -1)
     double *N, *R2, *tau, *D;
     float4 *store;            // [cap][2]: (x, phi), (w, path << 5 | bounce)
@@ -47,6 +48,11 @@ struct SppmDev {
     uint32_t *M;
     unsigned long long *Phi;
 };
+
+// Link set of a ray: by its direction (MTBVH), or one set for every ray.
+__device__ __forceinline__ int ray_set(const SppmDev &d, V3 dir) {
+    return d.force_set >= 0 ? d.force_set : link_set(dir);
+}
 
 // ---------------------------------------------------------------------------
 // Eye pass: a jittered pinhole ray followed through mirror and glass to the
@@ -74,7 +80,7 @@ __device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p
     for (int depth = 0; depth < d.max_depth; ++depth) {
         float t;
         uint32_t kp;
-        int32_t h = closest_hit<false>(sc.bvh, link_set(dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st);
+        int32_t h = closest_hit<false>(sc.bvh, ray_set(d, dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st);
         if (h < 0) break;
         V3 x = vray(org, t, dir);
         Tri tr = load_tri(sc.bvh.tris, kp);
@@ -179,7 +185,7 @@ __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, u
     float t;
     uint32_t kp;
     TraceStats st;
-    int32_t h = closest_hit<false>(sc.bvh, link_set(P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp, st);
+    int32_t h = closest_hit<false>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp, st);
     if (h < 0) return false;
     V3 x = vray(P.org, t, P.dir);
     Tri tr = load_tri(sc.bvh.tris, kp);

@@ -42,6 +42,7 @@ struct pm_sppm {
     double *adj_tab = nullptr;    // [n_photons][max_bounces] photon sensitivities
     uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
     double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
+    uint64_t scene_hash = 0;      // fingerprint of the scene description (checkpoint matching)
 };
 
 namespace pm {
@@ -51,5 +52,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
 void sppm_free(pm_sppm *s);
 // Back to the initial state (N = 0, R^2 = r0^2, tau = 0, D = 0, K = 0).
 int sppm_reset(pm_sppm *s, hipStream_t st);
+// 64-bit fingerprint of everything in a scene description that the render reads.
+uint64_t scene_fingerprint(const pm_scene_desc *d);
 
 }  // namespace pm

@@ -47,6 +47,9 @@ def test_host_validation_errors_without_gpu():
     p = api.sppm_params(0)
     out = C.c_void_p()
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+    p = api.sppm_params(1024, single_link_set=7)
+    assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+    assert b"single_link_set" in L.pm_last_error()
     p = api.sppm_params(1024, alpha=1.5)
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
     assert b"alpha" in L.pm_last_error()
@@ -56,6 +59,9 @@ def test_host_validation_errors_without_gpu():
     assert L.pm_render(C.byref(args.desc), C.byref(p), 1, C.c_void_p(1), None) == api.PM_ERR_ARG
     assert L.pm_sppm_iterate(None, 1, None) == api.PM_ERR_ARG
     assert L.pm_sppm_resolve(None, None, None) == api.PM_ERR_ARG
+    n = C.c_uint64(0)
+    assert L.pm_sppm_save(None, None, C.byref(n), None) == api.PM_ERR_ARG
+    assert L.pm_sppm_load(None, None, 0, None) == api.PM_ERR_ARG
 
 
 def _f(words):

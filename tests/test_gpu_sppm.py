@@ -128,6 +128,16 @@ def test_photon_kernels_parity(torch_cuda, oracle_lib, photon_kernel, refill):
                 photon_kernel=photon_kernel, refill=refill)
 
 
+@pytest.mark.parametrize("single_link_set", [1, 4, 6])
+def test_single_link_set_parity(torch_cuda, oracle_lib, single_link_set):
+    """Every ray walking one link set (a single threaded BVH) changes nothing
+    but speed: stage-by-stage parity with the oracle still holds."""
+    _log(f"case: single link set {single_link_set - 1}")
+    sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
+    _run_parity(torch_cuda, oracle_lib, sc, 1 << 12, 2, 0.02, seed=9, stage_iters=2,
+                single_link_set=single_link_set)
+
+
 def test_degenerate_cases(torch_cuda, oracle_lib):
     _log("case: single photon, no emitter, tiny image")
     sc = scenes.box_scene(5, 3)
@@ -167,3 +177,49 @@ def test_full_size_procedural_iteration(torch_cuda, oracle_lib):
     r0 = 0.05 * diag * 64 / 1280
     Np, seed = 1 << 20, 3
     _run_parity(torch_cuda, oracle_lib, sc, Np, 1, r0, seed=seed)
+
+
+def test_checkpoint_resume_is_bit_identical(torch_cuda):
+    """K iterations straight equal k iterations, a checkpoint, a fresh handle
+    loaded from it and K - k more (counter-keyed streams make resume exact);
+    a checkpoint is refused by a handle with other parameters."""
+    _log("case: checkpoint and resume, reduced procedural scene")
+    sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
+    prm = api.sppm_params(1 << 13, r0=0.02, seed=21, record_iterations=4)
+    a = api.Sppm(sc, prm)
+    a.iterate(4)
+    ref = a.resolve().cpu().numpy()
+    ref_state = {k: v.cpu().numpy() for k, v in a.views().items() if k in ("N", "R2", "tau", "D")}
+    g = torch_cuda.ones((sc.camera.height, sc.camera.width), device="cuda")
+    ref_grad = a.adjoint(g, sc.albedo_params).cpu().numpy()
+    a.destroy()
+
+    b = api.Sppm(sc, prm)
+    b.iterate(2)
+    ck = b.save()
+    b.destroy()
+    c = api.Sppm(sc, prm)
+    c.load(ck)
+    assert c.views()["iterations"] == 2
+    c.iterate(2)
+    img = c.resolve().cpu().numpy()
+    assert np.array_equal(img, ref)
+    v = c.views()
+    for k in ("N", "R2", "tau", "D"):
+        assert np.array_equal(v[k].cpu().numpy(), ref_state[k]), k
+    # the adjoint sums with float64 atomics, whose rounding depends on their order
+    np.testing.assert_allclose(c.adjoint(g, sc.albedo_params).cpu().numpy(), ref_grad, rtol=1e-10, atol=0)
+    c.destroy()
+
+    # another seed, a truncated buffer and a foreign buffer are all refused
+    d = api.Sppm(sc, api.sppm_params(1 << 13, r0=0.02, seed=22, record_iterations=4))
+    for bad in (ck, ck[:100], b"x" * len(ck)):
+        with pytest.raises(api.PMError) as e:
+            d.load(bad)
+        assert e.value.code == api.PM_ERR_ARG
+    d.destroy()
+    e2 = api.Sppm(sc, prm)
+    with pytest.raises(api.PMError):
+        e2.load(ck[:len(ck) - 8])
+    assert e2.views()["iterations"] == 0
+    e2.destroy()
