@@ -383,8 +383,9 @@ def cpu_baseline(tb, scenes):
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rays and photon index ranges would be sharded per GPU; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (rays, and the photon "
+              "index range of an iteration, would be sharded per GPU with one integer all-reduce of the "
+              "per-pixel counts and fluxes).", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1505_06022_amd import api, scenes

@@ -7,8 +7,8 @@ the same seeded input arrays (from ``paper_1505_06022_amd.scenes``, which
 holds no renderer arithmetic) and computes everything itself in plain C
 (``pm_oracle.c``), loaded here with ctypes.
 
-Parity status of each function is listed in the design doc; every function here is
-pinned by a ``-m "not gpu"`` test against something other than itself.
+Every function here is pinned by a ``-m "not gpu"`` test against something
+other than itself.
 """
 from __future__ import annotations
 
@@ -115,6 +115,8 @@ def _declare(L):
     L.orc_photon_pass.restype = C.c_int64
     L.orc_gather.argtypes = [C.POINTER(HitPoints), C.c_int64, C.POINTER(Photons), C.c_int64, P, C.c_int, C.c_int,
                              C.c_int, P, P, P]
+    L.orc_gather_stochastic.argtypes = [C.POINTER(HitPoints), C.c_int64, C.POINTER(Photons), C.c_int64, P, C.c_int,
+                                        P, C.c_int64, C.c_uint64, C.c_uint32, P, P, P]
     L.orc_update.argtypes = [C.c_int64, P, P, P, C.c_double, C.c_int, P, P, P]
     L.orc_resolve.argtypes = [C.c_int64, P, P, P, C.c_int32, P]
     L.orc_sppm_run.argtypes = [P, C.POINTER(RunOpts), C.POINTER(SppmParams), C.c_int32, C.c_int32, C.POINTER(State)]
@@ -308,6 +310,28 @@ def gather(hp: HitPointBuf, ph: PhotonBuf, R2: np.ndarray, shift=40, method=1, n
     lib().orc_gather(C.byref(hp.c), P, C.byref(ph.c), ph.n, _p(R2), shift, method,
                      nthreads or default_threads(), _p(M), _p(Phi), None if phid is None else _p(phid))
     return (M, Phi, phid) if want_double else (M, Phi)
+
+
+def scene_lo(scene) -> np.ndarray:
+    """Per-axis minimum over the scene's vertices (origin of the hashing grid)."""
+    return np.ascontiguousarray(np.asarray(scene.verts, np.float32).reshape(-1, 3).min(0), np.float32)
+
+
+def gather_stochastic(hp: HitPointBuf, ph: PhotonBuf, R2: np.ndarray, lo, n_photons: int, seed: int, k: int,
+                      shift=40, want_counts=False):
+    """Stochastic spatial hashing estimate of (M, Phi) for every hit point (Sec. 3.4)."""
+    P = len(hp.valid)
+    R2 = np.ascontiguousarray(R2, np.float64)
+    lo = np.ascontiguousarray(lo, np.float32)
+    M = np.zeros(P, np.uint32)
+    Phi = np.zeros(P, np.uint64)
+    bits = 12
+    while bits < 24 and (1 << bits) < 4 * n_photons:
+        bits += 1
+    counts = np.zeros(1 << bits, np.uint32) if want_counts else None
+    lib().orc_gather_stochastic(C.byref(hp.c), P, C.byref(ph.c), ph.n, _p(R2), shift, _p(lo), n_photons, seed, k,
+                                _p(M), _p(Phi), None if counts is None else _p(counts))
+    return (M, Phi, counts) if want_counts else (M, Phi)
 
 
 def update(valid, M, Phi, alpha, N, R2, tau, shift=40):

@@ -18,6 +18,9 @@
  *     to the first non-specular hit, photon tracing with Russian roulette,
  *     exact range query (brute force or a plain uniform grid), progressive
  *     radius / flux update, and the final radiance estimate;
+ *   - the stochastic spatial hashing estimate of the range query (Sec. 3.4):
+ *     one surviving photon per hash entry by a z-buffer test on independent
+ *     random depths, counted as many times as the entry received photons;
  *   - forward-mode derivatives of the rendered image with respect to the
  *     diffuse albedos and the emitted radiance.
  *
@@ -100,7 +103,7 @@ static void par_for(int64_t n, int nthreads, int64_t chunk, orc_range_fn fn, voi
 static const uint32_t RNG_A[4] = {3423u, 2646u, 1707u, 1999u};
 static const uint32_t RNG_M[4] = {4194287u, 4194277u, 4194191u, 4194167u};
 
-enum { KIND_EYE = 1, KIND_PHOTON = 2 };
+enum { KIND_EYE = 1, KIND_PHOTON = 2, KIND_DEPTH = 3 };
 
 static inline void rng_step(uint32_t s[4]) {
     for (int j = 0; j < 4; ++j) s[j] = (uint32_t)(((uint64_t)RNG_A[j] * s[j]) % RNG_M[j]);
@@ -1111,6 +1114,113 @@ ORC_EXPORT void orc_gather(const orc_hitpoints *hp, int64_t n_hp, const orc_phot
     gather_run(&c, method, nthreads);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Stochastic spatial hashing (Sec. 3.4): instead of listing every photon of */
+/* a hash entry, only one photon per entry survives, and a hit point counts  */
+/* that survivor once for every photon the entry received.  The survivor is */
+/* decided by a z-buffer test on a random depth drawn independently for     */
+/* each photon, so which photon survives does not depend on any property of */
+/* its path (nor on the order of the writes).                                */
+/*                                                                            */
+/* Grid and table (the same for every method that hashes):                   */
+/*   lo     per-axis minimum over the scene's vertices                       */
+/*   h      2 sqrt(max R^2 over valid hit points) (1 + 2^-10), in double;    */
+/*          inv_h = (float)(1/h) (0 when h = 0)                              */
+/*   cell   floor((x - lo) * inv_h) per axis, in float32                     */
+/*   entry  Teschner et al.'s hash of the cell mod 2^bits, bits the smallest */
+/*          value in [12, 24] with 2^bits >= 4 n_photons                     */
+/* A hit point's disc lies within the 2x2x2 cells whose lowest corner is    */
+/* floor((x - lo) * inv_h - 0.5); each distinct entry of those is visited   */
+/* once.  Depth of photon (path, bounce) in iteration k: the float bits of  */
+/* the first output of stream (seed, DEPTH, k, path * 32 + bounce); the      */
+/* smallest (depth, path * 32 + bounce) survives.                            */
+/* ------------------------------------------------------------------------ */
+static inline uint32_t teschner(int32_t ix, int32_t iy, int32_t iz, uint32_t mask) {
+    uint32_t a = (uint32_t)ix * 73856093u, b = (uint32_t)iy * 19349663u, c = (uint32_t)iz * 83492791u;
+    return (a ^ b ^ c) & mask;
+}
+
+static inline int32_t grid_coord(float x, float lo, float inv_h, float shift) {
+    float f = (x - lo) * inv_h - shift;
+    return (int32_t)floorf(f);
+}
+
+static uint32_t table_bits_for(int64_t n_photons) {
+    uint32_t bits = 12;
+    while (bits < 24 && ((int64_t)1 << bits) < 4 * n_photons) bits++;
+    return bits;
+}
+
+ORC_EXPORT void orc_gather_stochastic(const orc_hitpoints *hp, int64_t n_hp, const orc_photons *ph, int64_t n_ph,
+                                      const double *R2, int shift, const float *lo, int64_t n_photons_emitted,
+                                      uint64_t seed, uint32_t k, uint32_t *M, uint64_t *Phi, uint32_t *n_entry_out) {
+    double r2max = 0.0;
+    for (int64_t p = 0; p < n_hp; ++p)
+        if (hp->valid[p] && R2[p] > r2max) r2max = R2[p];
+    double h = 2.0 * sqrt(r2max) * (1.0 + 1.0 / 1024.0);
+    float inv_h = h > 0.0 ? (float)(1.0 / h) : 0.0f;
+    uint32_t bits = table_bits_for(n_photons_emitted);
+    uint32_t T = 1u << bits, mask = T - 1u;
+    uint32_t *count = (uint32_t *)calloc(T, sizeof(uint32_t));
+    uint64_t *best = (uint64_t *)malloc(sizeof(uint64_t) * T);
+    int64_t *who = (int64_t *)malloc(sizeof(int64_t) * T);
+    for (uint32_t e = 0; e < T; ++e) { best[e] = UINT64_MAX; who[e] = -1; }
+    for (int64_t j = 0; j < n_ph; ++j) {
+        const float *x = ph->x + 3 * j;
+        uint32_t e = teschner(grid_coord(x[0], lo[0], inv_h, 0.0f), grid_coord(x[1], lo[1], inv_h, 0.0f),
+                              grid_coord(x[2], lo[2], inv_h, 0.0f), mask);
+        uint32_t id = ph->path[j] * 32u + ph->bounce[j];
+        uint32_t st[4];
+        rng_seed(seed, KIND_DEPTH, k, (uint64_t)id, st);
+        float depth = rng_next(st);
+        uint32_t dbits;
+        memcpy(&dbits, &depth, 4);
+        uint64_t key = ((uint64_t)dbits << 32) | (uint64_t)id;
+        count[e]++;
+        if (key < best[e]) { best[e] = key; who[e] = j; }
+    }
+    for (int64_t p = 0; p < n_hp; ++p) {
+        uint32_t m = 0;
+        uint64_t f = 0;
+        if (hp->valid[p]) {
+            const float *x = hp->x + 3 * p;
+            int32_t b0 = grid_coord(x[0], lo[0], inv_h, 0.5f), b1 = grid_coord(x[1], lo[1], inv_h, 0.5f),
+                    b2 = grid_coord(x[2], lo[2], inv_h, 0.5f);
+            uint32_t visited[8];
+            int nv = 0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        uint32_t e = teschner(b0 + dx, b1 + dy, b2 + dz, mask);
+                        int seen = 0;
+                        for (int v = 0; v < nv; ++v) seen |= (visited[v] == e);
+                        if (seen) continue;
+                        visited[nv++] = e;
+                        if (count[e] == 0) continue;
+                        int64_t j = who[e];
+                        if (accept(x, hp->n + 3 * p, ph->x + 3 * j, ph->w + 3 * j, R2[p])) {
+                            m += count[e];
+                            f += (uint64_t)count[e] * fx_term(hp->wk[p], ph->phi[j], shift);
+                        }
+                    }
+        }
+        M[p] = m;
+        Phi[p] = f;
+    }
+    if (n_entry_out) memcpy(n_entry_out, count, sizeof(uint32_t) * T);
+    free(count);
+    free(best);
+    free(who);
+}
+
+static void scene_lo(const orc_scene *s, float lo[3]) {
+    for (int a = 0; a < 3; ++a) lo[a] = INFINITY;
+    for (int64_t i = 0; i < 9 * s->d.n_tri; ++i) {
+        float v = s->d.verts[i];
+        if (v < lo[i % 3]) lo[i % 3] = v;
+    }
+}
+
 /* Progressive update of one pixel (radius reduction of stochastic
  * progressive photon mapping): with M new photons and fixed-point flux Phi,
  *   N' = N + alpha*M,  R2' = R2 * (N + alpha*M)/(N + M),
@@ -1147,7 +1257,7 @@ typedef struct {
     double alpha;
     double r0;
     int32_t shift;
-    int32_t gather_method; /* 0 brute force, 1 grid */
+    int32_t gather_method; /* 0 brute force, 1 grid, 2 stochastic spatial hashing */
     int64_t photon_cap;
 } orc_sppm_params;
 
@@ -1208,7 +1318,13 @@ ORC_EXPORT int orc_sppm_run(const orc_scene *s, const orc_run_opts *op, const or
         if (n < 0) { rc = -1; break; }
         if (st->n_stored) st->n_stored[it] = n;
         if (st->R2_hist) memcpy(st->R2_hist + (size_t)it * P, st->R2, sizeof(double) * (size_t)P);
-        orc_gather(&hp, P, &ph, n, st->R2, pp->shift, pp->gather_method, op->nthreads, M, Phi, NULL);
+        if (pp->gather_method == 2) {
+            float lo[3];
+            scene_lo(s, lo);
+            orc_gather_stochastic(&hp, P, &ph, n, st->R2, pp->shift, lo, pp->n_photons, op->seed, k, M, Phi, NULL);
+        } else {
+            orc_gather(&hp, P, &ph, n, st->R2, pp->shift, pp->gather_method, op->nthreads, M, Phi, NULL);
+        }
         if (st->M_hist) memcpy(st->M_hist + (size_t)it * P, M, sizeof(uint32_t) * (size_t)P);
         orc_update(P, hp.valid, M, Phi, pp->alpha, pp->shift, st->N, st->R2, st->tau);
         for (int64_t p = 0; p < P; ++p) st->D[p] += hp.d_add[p];

@@ -8,9 +8,9 @@ oracle consume exactly these arrays.
 
 The paper's own scenes (the metal Cornell box used by its released code, the
 teaser scenes with a scanned model, the scenes behind its ray-casting plot)
-are not available; the generators below are synthetic stand-ins with the
-structure described in the design doc (room-with-boxes, random triangle soup,
-procedural heightfield + spheres inside a room).
+are not available; the generators below are synthetic stand-ins of the same
+kinds of structure (room-with-boxes, random triangle soup, procedural
+heightfield + spheres inside a room).
 
 Conventions
 -----------
