@@ -257,9 +257,29 @@ def sppm_bench(args, torch, api, scenes):
         torch.cuda.synchronize()
         (tbvh if name.startswith("single") else variants)[name] = round(e0.elapsed_time(e1) / 3, 3)
         sv.destroy()
+    # stochastic spatial hashing (Sec. 3.4) against the exact gather: time per
+    # iteration, and RMSE after 8 iterations against a 64-iteration exact render
+    r0 = 0.05 * diag * 64 / 1280
+    ref = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=r0, seed=101), bvh=bvh)
+    ref.iterate(64)
+    ref_img = ref.resolve().double()
+    ref.destroy()
+    sh = {}
+    for name, mode in (("exact", 0), ("stochastic", 1)):
+        sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=r0, seed=3, gather_mode=mode), bvh=bvh)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sv.iterate(8)
+        e1.record(st)
+        torch.cuda.synchronize()
+        img = sv.resolve().double()
+        rmse = float(((img - ref_img) ** 2).mean().sqrt() / ref_img.mean())
+        sh[name] = {"iteration_ms": round(e0.elapsed_time(e1) / 8, 3), "relative_rmse_after_8": round(rmse, 4)}
+        sv.destroy()
     bvh.destroy()
     return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
-                tbvh=tbvh, workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
+                tbvh=tbvh, stochastic_hashing=sh,
+                workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
 def adjoint_bench(args, torch, api, scenes):
@@ -440,6 +460,7 @@ def main():
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
                        "stored_photons": sp["n_stored"], "workload": sp["workload"],
                        "iteration_ms_by_photon_kernel": sp["variants"],
+                       "gather_exact_vs_stochastic_hashing": sp["stochastic_hashing"],
                        "tbvh_ablation": {"iteration_ms_single_link_set": sp["tbvh"],
                                          "mean_ratio_tbvh_over_mtbvh": round(
                                              float(np.mean(list(sp["tbvh"].values()))) / sp["iteration_ms"], 3)}}

@@ -217,7 +217,20 @@ typedef struct {
                                  every ray walks link set s, i.e. a single
                                  threaded BVH (the paper's TBVH comparison).
                                  Results are identical; only speed differs. */
+    int32_t gather_mode;      /* PM_GATHER_*: the range query's estimator */
 } pm_sppm_params;
+
+/* Range query.  EXACT: every photon inside a hit point's disc, found through
+ * a hashed grid with cell edge 2 R_max (1 + 2^-10) and 2^bits entries,
+ * bits = clamp(ceil(log2(4 n_photons)), 12, 24).  STOCHASTIC: the paper's
+ * stochastic spatial hashing (Sec. 3.4) on the same grid and table: each
+ * entry keeps one photon, the one of smallest (random depth, path * 32 +
+ * bounce), with the depth drawn for each photon from its own counter-keyed
+ * stream, and a hit point counts that photon, when inside its disc, once per
+ * photon the entry received.  The estimate is unbiased for the exact query
+ * and independent of thread order; it needs no sort.  Not supported with
+ * record_iterations > 0 (the adjoint) or in a batch. */
+enum { PM_GATHER_EXACT = 0, PM_GATHER_STOCHASTIC = 1 };
 
 /* Photon pass scheduling (results are identical): one lane traces one whole
  * path, or persistent lanes trace one bounce per step and switch to a new path
@@ -259,7 +272,7 @@ PM_API int pm_sppm_save(pm_sppm *s, void *buf, uint64_t *size, void *stream);
 /* Restore a checkpoint into a handle created with the same scene and
  * parameters (checked through a fingerprint of the scene description and the
  * pixel count, photon count, seed, alpha, r0, fixed-point shift, path-length
- * caps and recorded-iteration count).  On any mismatch, or a truncated or
+ * caps, recorded-iteration count and gather mode).  On any mismatch, or a truncated or
  * foreign buffer, returns PM_ERR_ARG and leaves the handle unchanged.  The
  * photon store and hashed grid are rebuilt by the next iteration.
  * Synchronises `stream`. */

@@ -424,6 +424,8 @@ int batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const 
     for (int32_t i = 0; i < n; ++i) {
         int rc = sppm_validate(descs[i], params[i]);
         if (rc) return set_error("scene " + std::to_string(i) + ": " + last_error()), rc;
+        if (params[i]->gather_mode != PM_GATHER_EXACT)
+            return set_error("scene " + std::to_string(i) + ": a batch uses the exact gather"), PM_ERR_ARG;
     }
     pm_batch *b = new pm_batch();
     auto fail = [&](int code) {

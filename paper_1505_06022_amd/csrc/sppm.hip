@@ -66,6 +66,33 @@ __global__ __launch_bounds__(kBlock) void k_gather(SppmDev d, const uint32_t *__
     gather_elem(d, gr, p, start, sorted);
 }
 
+// Stochastic spatial hashing: clear the keys, insert every stored photon
+// (count and smallest key per entry), record each entry's survivor, gather.
+__global__ __launch_bounds__(kBlock) void k_sh_clear(SppmDev d, uint32_t T) {
+    for (uint32_t e = blockIdx.x * kBlock + threadIdx.x; e < T; e += gridDim.x * kBlock)
+        d.sh_key[d.table_off + e] = ~0ull;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sh_insert(SppmDev d, uint32_t k, uint32_t *__restrict__ count) {
+    uint32_t n_ph = stored_photons(d);
+    Grid gr = make_grid(d);
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < n_ph; j += gridDim.x * kBlock)
+        sh_insert_elem(d, gr, k, j, count);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sh_pick(SppmDev d, uint32_t k) {
+    uint32_t n_ph = stored_photons(d);
+    Grid gr = make_grid(d);
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < n_ph; j += gridDim.x * kBlock) sh_pick_elem(d, gr, k, j);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sh_gather(SppmDev d, const uint32_t *__restrict__ count) {
+    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (p >= d.P) return;
+    Grid gr = make_grid(d);
+    sh_gather_elem(d, gr, p, count);
+}
+
 __global__ __launch_bounds__(kBlock) void k_update(SppmDev d, double *__restrict__ hist) {
     int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p < d.P) update_elem(d, p, hist);
@@ -209,7 +236,8 @@ void sppm_free(pm_sppm *s) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
-                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat};
+                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
+                    s->sh_key, s->sh_surv};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (s->own_bvh && s->bvh) {
@@ -252,6 +280,10 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
     if (p->photon_kernel < 0 || p->photon_kernel > 2 || p->refill < 0 || p->refill > 64)
         return set_error("photon_kernel must be 0..2 and refill 0..64"), PM_ERR_ARG;
+    if (p->gather_mode != PM_GATHER_EXACT && p->gather_mode != PM_GATHER_STOCHASTIC)
+        return set_error("gather_mode must be PM_GATHER_EXACT or PM_GATHER_STOCHASTIC"), PM_ERR_ARG;
+    if (p->gather_mode == PM_GATHER_STOCHASTIC && p->record_iterations > 0)
+        return set_error("the adjoint needs the exact gather (gather_mode 0)"), PM_ERR_ARG;
     if (p->single_link_set < 0 || p->single_link_set > 6)
         return set_error("single_link_set must be 0 (by direction) or 1..6"), PM_ERR_ARG;
     if (p->record_iterations < 0 || p->record_iterations > 100000)
@@ -333,11 +365,16 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     PM_HIPF(hipMalloc(&s->counters, sizeof(uint32_t) * 4));
     PM_HIPF(hipMalloc(&s->r2max, sizeof(unsigned long long)));
     if (own_grid) {
-        PM_HIPF(hipMalloc(&s->sorted, sizeof(float4) * 2 * (size_t)cap64));
         PM_HIPF(hipMalloc(&s->cell_count, sizeof(uint32_t) * T));
-        PM_HIPF(hipMalloc(&s->cell_start, sizeof(uint32_t) * (T + 1)));
-        PM_HIPF(hipMalloc(&s->cell_fill, sizeof(uint32_t) * T));
-        PM_HIPF(hipMalloc(&s->bsum, sizeof(uint32_t) * (nb + 1)));
+        if (p->gather_mode == PM_GATHER_STOCHASTIC) {
+            PM_HIPF(hipMalloc(&s->sh_key, sizeof(unsigned long long) * T));
+            PM_HIPF(hipMalloc(&s->sh_surv, sizeof(uint32_t) * T));
+        } else {
+            PM_HIPF(hipMalloc(&s->sorted, sizeof(float4) * 2 * (size_t)cap64));
+            PM_HIPF(hipMalloc(&s->cell_start, sizeof(uint32_t) * (T + 1)));
+            PM_HIPF(hipMalloc(&s->cell_fill, sizeof(uint32_t) * T));
+            PM_HIPF(hipMalloc(&s->bsum, sizeof(uint32_t) * (nb + 1)));
+        }
     }
     PM_HIPF(hipMalloc(&s->M, sizeof(uint32_t) * s->P));
     PM_HIPF(hipMalloc(&s->Phi, sizeof(unsigned long long) * s->P));
@@ -423,6 +460,9 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.photon_kernel = p->photon_kernel == PM_PHOTON_PER_PATH ? PM_PHOTON_PER_PATH : PM_PHOTON_REGEN;
     dv.refill = p->refill > 0 ? (uint32_t)p->refill : 16u;
     dv.force_set = p->single_link_set - 1;
+    dv.gather_mode = p->gather_mode;
+    dv.sh_key = s->sh_key;
+    dv.sh_surv = s->sh_surv;
     {
         int dev = 0, cus = 0, per_cu = 0;
         PM_HIPF(hipGetDevice(&dev));
@@ -485,11 +525,19 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
             hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
                                (double *)nullptr);
         hipLaunchKernelGGL(k_rmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, (const double *)s->R2);
-        hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
-        launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
-        hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_fill, s->sorted);
-        hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, (const uint32_t *)s->cell_start,
-                           (const float4 *)s->sorted);
+        if (d.gather_mode == PM_GATHER_STOCHASTIC) {
+            hipLaunchKernelGGL(k_sh_clear, dim3(std::min<uint32_t>(blocks_for(T), 4096u)), dim3(kBlock), 0, st, d, T);
+            hipLaunchKernelGGL(k_sh_insert, dim3(ph_blocks), dim3(kBlock), 0, st, d, k, s->cell_count);
+            hipLaunchKernelGGL(k_sh_pick, dim3(ph_blocks), dim3(kBlock), 0, st, d, k);
+            hipLaunchKernelGGL(k_sh_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d,
+                               (const uint32_t *)s->cell_count);
+        } else {
+            hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
+            launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
+            hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_fill, s->sorted);
+            hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d,
+                               (const uint32_t *)s->cell_start, (const float4 *)s->sorted);
+        }
         double *hist = (int32_t)k < s->rec_iters ? s->R2_hist + (size_t)k * s->P : nullptr;
         hipLaunchKernelGGL(k_update, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, hist);
         PM_HIP(hipGetLastError());
@@ -587,7 +635,8 @@ struct CheckpointHeader {
     double alpha, r0;
     int32_t fixed_shift, max_eye_depth, max_photon_bounces, record_iterations;
     int32_t iterations, n_hist;
-    uint32_t overflow, reserved;
+    uint32_t overflow;
+    int32_t gather_mode;
 };
 constexpr uint32_t kCheckpointVersion = 1;
 
@@ -648,6 +697,7 @@ int sppm_save(pm_sppm *s, void *buf, uint64_t *size, hipStream_t st) {
     h.record_iterations = s->rec_iters;
     h.iterations = s->K;
     h.n_hist = n_hist;
+    h.gather_mode = s->prm.gather_mode;
     uint8_t *out = (uint8_t *)buf;
     const size_t pb = sizeof(double) * (size_t)s->P;
     const double *arrays[4] = {s->N, s->R2, s->tau, s->D};
@@ -673,7 +723,8 @@ int sppm_load(pm_sppm *s, const void *buf, uint64_t size, hipStream_t st) {
     if (h.n_pixels != s->P || h.n_photons != s->prm.n_photons || h.seed != s->prm.seed ||
         h.scene_hash != s->scene_hash || h.alpha != s->prm.alpha || h.r0 != s->prm.r0 ||
         h.fixed_shift != s->prm.fixed_shift || h.max_eye_depth != s->prm.max_eye_depth ||
-        h.max_photon_bounces != s->prm.max_photon_bounces || h.record_iterations != s->rec_iters)
+        h.max_photon_bounces != s->prm.max_photon_bounces || h.record_iterations != s->rec_iters ||
+        h.gather_mode != s->prm.gather_mode)
         return set_error("checkpoint was taken from a handle with another scene or parameters"), PM_ERR_ARG;
     if (h.iterations < 0 || h.n_hist != std::min(h.iterations, s->rec_iters) ||
         size < checkpoint_bytes(s, h.n_hist))

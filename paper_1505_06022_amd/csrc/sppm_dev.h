@@ -40,6 +40,9 @@ struct SppmDev {
     int32_t photon_kernel;    // PM_PHOTON_* (resolved: per path or regenerating)
     uint32_t refill;          // regeneration: idle lanes that trigger a refill
     int32_t force_set;        // -1: link set by ray direction; 0..5: that set for every ray
+    int32_t gather_mode;      // PM_GATHER_EXACT or PM_GATHER_STOCHASTIC
+    unsigned long long *sh_key;  // stochastic hashing: smallest (depth, photon id) per entry
+    uint32_t *sh_surv;           // stochastic hashing: store index of each entry's survivor
     float4 *hp_pos, *hp_nrm;  // (x, W*rho/pi), (n toward the eye, material bits | -1)
     double *N, *R2, *tau, *D;
     float4 *store;            // [cap][2]: (x, phi), (w, path << 5 | bounce)
@@ -362,6 +365,76 @@ __device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const 
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Stochastic spatial hashing (Sec. 3.4): every photon is hashed to the entry
+// of its cell (the same grid and table as above); the entry keeps one photon,
+// the smallest (random depth, photon id) -- a z-buffer test with a depth drawn
+// per photon from stream (seed, DEPTH, k, path * 32 + bounce), independent of
+// the path's properties -- and counts the photons it received.  A hit point
+// counts each surviving photon inside its disc once per photon of its entry.
+// The smallest key wins whatever the order of the atomics, so the estimate is
+// deterministic.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kKindDepth = 3u;
+
+__device__ __forceinline__ unsigned long long photon_key(const SppmDev &d, uint32_t k, uint32_t id) {
+    Rng g = rng_seed(d.seed, kKindDepth, k, (uint64_t)id);
+    float depth = rng_next(g);
+    return ((unsigned long long)__float_as_uint(depth) << 32) | (unsigned long long)id;
+}
+
+__device__ __forceinline__ void sh_insert_elem(const SppmDev &d, const Grid &gr, uint32_t k, uint32_t j,
+                                               uint32_t *__restrict__ count) {
+    float4 a = d.store[2 * (size_t)j];
+    uint32_t id = __float_as_uint(d.store[2 * (size_t)j + 1].w);
+    uint32_t e = d.table_off + photon_bucket(gr, a.x, a.y, a.z);
+    atomicAdd(&count[e], 1u);
+    atomicMin(&d.sh_key[e], photon_key(d, k, id));
+}
+
+__device__ __forceinline__ void sh_pick_elem(const SppmDev &d, const Grid &gr, uint32_t k, uint32_t j) {
+    float4 a = d.store[2 * (size_t)j];
+    uint32_t id = __float_as_uint(d.store[2 * (size_t)j + 1].w);
+    uint32_t e = d.table_off + photon_bucket(gr, a.x, a.y, a.z);
+    if (d.sh_key[e] == photon_key(d, k, id)) d.sh_surv[e] = j;
+}
+
+__device__ __forceinline__ void sh_gather_elem(const SppmDev &d, const Grid &gr, int64_t p,
+                                               const uint32_t *__restrict__ count) {
+    float4 hn = d.hp_nrm[p];
+    uint32_t M = 0;
+    unsigned long long F = 0ull;
+    if (__float_as_int(hn.w) >= 0) {
+        float4 hx = d.hp_pos[p];
+        const double wk = (double)hx.w, r2 = d.R2[p];
+        int32_t bx = (int32_t)floorf((hx.x - gr.lo[0]) * gr.inv_h - 0.5f);
+        int32_t by = (int32_t)floorf((hx.y - gr.lo[1]) * gr.inv_h - 0.5f);
+        int32_t bz = (int32_t)floorf((hx.z - gr.lo[2]) * gr.inv_h - 0.5f);
+        uint32_t seen[8];
+        for (int c = 0; c < 8; ++c) {
+            uint32_t hb = cell_hash(bx + (c & 1), by + ((c >> 1) & 1), bz + (c >> 2), gr.mask);
+            bool dup = false;
+            for (int e = 0; e < c; ++e) dup |= (seen[e] == hb);
+            seen[c] = hb;
+            if (dup) continue;
+            const uint32_t n = count[d.table_off + hb];
+            if (n == 0) continue;
+            const uint32_t j = d.sh_surv[d.table_off + hb];
+            float4 a = d.store[2 * (size_t)j];
+            float dx = a.x - hx.x, dy = a.y - hx.y, dz = a.z - hx.z;
+            float d2 = (dx * dx + dy * dy) + dz * dz;
+            if (!((double)d2 < r2)) continue;
+            float4 b = d.store[2 * (size_t)j + 1];
+            float c2 = (b.x * hn.x + b.y * hn.y) + b.z * hn.z;
+            if (!(c2 < 0.0f)) continue;
+            M += n;
+            F += (unsigned long long)n * (unsigned long long)rint((wk * (double)a.w) * d.scale);
+        }
+    }
+    d.M[p] = M;
+    d.Phi[p] = F;
 }
 
 // Range query of one hit point: M photons and their flux, each term rounded to

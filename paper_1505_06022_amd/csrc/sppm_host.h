@@ -43,6 +43,8 @@ struct pm_sppm {
     uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
     double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
     uint64_t scene_hash = 0;      // fingerprint of the scene description (checkpoint matching)
+    unsigned long long *sh_key = nullptr;  // stochastic hashing (gather_mode 1): [T] keys
+    uint32_t *sh_surv = nullptr;           // and [T] survivors
 };
 
 namespace pm {

@@ -50,6 +50,11 @@ def test_host_validation_errors_without_gpu():
     p = api.sppm_params(1024, single_link_set=7)
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
     assert b"single_link_set" in L.pm_last_error()
+    p = api.sppm_params(1024, gather_mode=2)
+    assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+    p = api.sppm_params(1024, gather_mode=1, record_iterations=2)
+    assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+    assert b"adjoint" in L.pm_last_error()
     p = api.sppm_params(1024, alpha=1.5)
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
     assert b"alpha" in L.pm_last_error()

@@ -223,3 +223,65 @@ def test_checkpoint_resume_is_bit_identical(torch_cuda):
         e2.load(ck[:len(ck) - 8])
     assert e2.views()["iterations"] == 0
     e2.destroy()
+
+
+def _run_stochastic_parity(torch, oracle_lib, sc, Np, K, r0, seed, alpha=0.7, **kw):
+    """Stochastic spatial hashing: per-iteration M and Phi, the final state and
+    the image equal the oracle's estimate bit for bit (the survivor of each
+    entry is the smallest key, whatever the order of the atomics)."""
+    osc = oracle_lib.OracleScene(sc)
+    lo = oracle_lib.scene_lo(sc)
+    s = api.Sppm(sc, api.sppm_params(Np, alpha=alpha, r0=r0, seed=seed, gather_mode=1, **kw))
+    P = osc.P
+    N, R2, tau, D = np.zeros(P), np.full(P, r0 * r0), np.zeros(P), np.zeros(P)
+    for k in range(K):
+        s.iterate(1)
+        hp = oracle_lib.eye_pass(osc, seed, k)
+        ph = oracle_lib.photon_pass(osc, seed, k, Np)
+        M, Phi = oracle_lib.gather_stochastic(hp, ph, R2, lo, Np, seed, k)
+        g = _gpu_stage(torch, s)
+        assert g["n_photons"] == ph.n
+        assert np.array_equal(g["M"].view(np.uint32), M)
+        assert np.array_equal(g["Phi"].view(np.uint64), Phi)
+        oracle_lib.update(hp.valid, M, Phi, alpha, N, R2, tau)
+        D += hp.d_add
+    img = s.resolve().cpu().numpy().ravel()
+    s.status()
+    g = _gpu_stage(torch, s)
+    for name, ref in (("N", N), ("R2", R2), ("tau", tau), ("D", D)):
+        assert np.array_equal(g[name], ref), name
+    ref = oracle_lib.resolve(R2, tau, D, K)
+    assert np.array_equal(img, ref)
+    full = oracle_lib.sppm_run(osc, seed, Np, K, alpha=alpha, r0=r0, gather_method=2)
+    assert np.array_equal(full.image, ref)
+    s.destroy()
+    return img
+
+
+@pytest.mark.parametrize("case", ["box", "specular", "tiny"])
+def test_stochastic_hashing_parity(torch_cuda, oracle_lib, case):
+    _log(f"case: stochastic spatial hashing, {case}")
+    if case == "box":
+        _run_stochastic_parity(torch_cuda, oracle_lib, scenes.box_scene(64, 64), 1 << 14, 3, 0.05 * math.sqrt(3.0), 1)
+    elif case == "specular":
+        sc = scenes.procedural_scene(width=97, height=61, hf_cells=20, sphere_level=2, glass_level=3, seed=3)
+        _run_stochastic_parity(torch_cuda, oracle_lib, sc, 3 * (1 << 12) + 7, 2, 0.02, 5, photon_kernel=1)
+    else:
+        _run_stochastic_parity(torch_cuda, oracle_lib, scenes.box_scene(5, 3), 1, 2, 0.1, 4)
+
+
+def test_stochastic_hashing_full_size_iteration(torch_cuda, oracle_lib):
+    """250k triangles, 1280x720, 2^20 photons: one stochastic-hashing iteration
+    equals the oracle's."""
+    _log("case: stochastic spatial hashing, procedural 250k triangles, 2^20 photons")
+    sc = scenes.procedural_scene()
+    diag = float(np.linalg.norm(sc.verts.reshape(-1, 3).max(0) - sc.verts.reshape(-1, 3).min(0)))
+    _run_stochastic_parity(torch_cuda, oracle_lib, sc, 1 << 20, 1, 0.05 * diag * 64 / 1280, 3)
+
+
+def test_stochastic_hashing_is_refused_where_unsupported(torch_cuda):
+    _log("case: stochastic hashing in a batch")
+    sc = scenes.box_scene(8, 8)
+    with pytest.raises(api.PMError) as e:
+        api.Batch([sc, sc], [api.sppm_params(256, r0=0.1), api.sppm_params(256, r0=0.1, gather_mode=1)])
+    assert e.value.code == api.PM_ERR_ARG
