@@ -76,10 +76,12 @@ __global__ __launch_bounds__(kBs) void k_batch(BatchDev b) {
         const int64_t e0 = (int64_t)(it - off[s]) * b.chunk;
         const int64_t end = min(e0 + (int64_t)b.chunk, stage_elems<kStage>(d));
         if (kStage == kStRmax) {
-            for (int64_t base = e0; base < end; base += kBs) {
-                int64_t e = base + threadIdx.x;
-                rmax_elem(d, d.R2, e, e < end);
+            unsigned long long v = 0ull;
+            for (int64_t e = e0 + threadIdx.x; e < end; e += kBs) {
+                unsigned long long x = rmax_lane(d, d.R2, e);
+                v = x > v ? x : v;
             }
+            rmax_flush(d, v);
             continue;
         }
         if (kStage == kStCount || kStage == kStScatter || kStage == kStGather) {

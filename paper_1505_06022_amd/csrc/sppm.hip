@@ -40,9 +40,29 @@ __global__ void k_begin(SppmDev d) {
     }
 }
 
+// Largest R^2 over valid hit points: a grid-stride maximum per lane, reduced
+// across the workgroup, then one atomic per workgroup (positive doubles order
+// like their bit patterns).  Launched with few workgroups so the atomics on
+// the single result do not serialise.
+constexpr uint32_t kRmaxBlocks = 512;
+
 __global__ __launch_bounds__(kBlock) void k_rmax(SppmDev d, const double *__restrict__ R2src) {
-    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    rmax_elem(d, R2src, p, p < d.P);
+    __shared__ unsigned long long part[kBlock / 64];
+    unsigned long long v = 0ull;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < d.P; p += (int64_t)gridDim.x * kBlock) {
+        unsigned long long x = rmax_lane(d, R2src, p);
+        v = x > v ? x : v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) v = part[w] > v ? part[w] : v;
+        if (v) atomicMax(d.r2max, v);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_count(SppmDev d, uint32_t *__restrict__ cell_count) {
@@ -524,7 +544,7 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
         else
             hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
                                (double *)nullptr);
-        hipLaunchKernelGGL(k_rmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, (const double *)s->R2);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, st, d, (const double *)s->R2);
         if (d.gather_mode == PM_GATHER_STOCHASTIC) {
             hipLaunchKernelGGL(k_sh_clear, dim3(std::min<uint32_t>(blocks_for(T), 4096u)), dim3(kBlock), 0, st, d, T);
             hipLaunchKernelGGL(k_sh_insert, dim3(ph_blocks), dim3(kBlock), 0, st, d, k, s->cell_count);
@@ -592,7 +612,7 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
         hipLaunchKernelGGL(k_photon<true>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, (uint32_t)k, s->mat_tab,
                            s->adj_tab);
-        hipLaunchKernelGGL(k_rmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, R2k);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, st, d, R2k);
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
         launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
         hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_fill, s->sorted);

@@ -310,11 +310,16 @@ __device__ __forceinline__ uint32_t photon_bucket(const Grid &gr, float x, float
 __device__ __forceinline__ uint32_t stored_photons(const SppmDev &d) { return min(d.counters[0], d.cap); }
 
 // Largest squared radius among valid hit points (positive doubles order like
-// their bit patterns).  Called by every lane of a wave (in_range false for
-// padding lanes); the wave's lanes must belong to one scene.
-__device__ __forceinline__ void rmax_elem(const SppmDev &d, const double *__restrict__ R2src, int64_t p, bool in_range) {
-    unsigned long long v = 0ull;
-    if (in_range && __float_as_int(d.hp_nrm[p].w) >= 0) v = (unsigned long long)__double_as_longlong(R2src[p]);
+// their bit patterns): rmax_lane gives one pixel's candidate, rmax_flush
+// reduces a wave's candidates and folds them into the result with one atomic.
+// rmax_flush is called by every lane of a wave; its lanes must belong to one
+// scene.
+__device__ __forceinline__ unsigned long long rmax_lane(const SppmDev &d, const double *__restrict__ R2src, int64_t p) {
+    if (__float_as_int(d.hp_nrm[p].w) < 0) return 0ull;
+    return (unsigned long long)__double_as_longlong(R2src[p]);
+}
+
+__device__ __forceinline__ void rmax_flush(const SppmDev &d, unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) {
         unsigned long long o = __shfl_xor(v, off);
         v = o > v ? o : v;
