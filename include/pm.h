@@ -73,7 +73,16 @@ typedef struct {
     int32_t n_threads; /* host build threads, 0 = all */
     float trav_cost;   /* SAH cost of a node visit relative to a triangle
                           test (0 = default 1; range (0, 64]) */
+    int32_t builder;   /* PM_BUILD_*: pm_build_bvh only */
 } pm_bvh_opts;
+
+/* BVH builders.  HOST_SAH: binned SAH on the host threads, then threading and
+ * upload (Sec. 3.1).  GPU_LBVH: on the device from sorted 30-bit Morton codes
+ * of the triangle centres (a linear BVH, the GPU build named as future work
+ * in Sec. 4.1), subtrees of at most max_leaf triangles collapsed into leaves,
+ * threaded into the same six link sets; much faster to build, usually slower
+ * to traverse.  Both give identical traversal results. */
+enum { PM_BUILD_HOST_SAH = 0, PM_BUILD_GPU_LBVH = 1 };
 
 typedef struct {
     uint32_t size;        /* sizeof(pm_bvh_info) */
@@ -118,6 +127,11 @@ PM_API int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, in
 
 PM_API int pm_bvh_destroy(pm_bvh *bvh);
 PM_API int pm_bvh_get_info(const pm_bvh *bvh, pm_bvh_info *info);
+
+/* Copy a device BVH to host memory, in the layout of pm_build_bvh_host
+ * (nodes [6][n_nodes][4] words, tris [n_tri][12] words; either may be NULL).
+ * Synchronises `stream`.  Errors: PM_ERR_ARG for a NULL bvh. */
+PM_API int pm_bvh_download(const pm_bvh *bvh, uint32_t *nodes, uint32_t *tris, void *stream);
 
 /* Closest hit of every ray (the traversal loop of Sec. 3.1, Fig. "mtbvh").
  *   rays  device, float32 [n][8] = o.xyz, tmin, d.xyz, tmax

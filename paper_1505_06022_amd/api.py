@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libpm.so")
 PM_OK, PM_ERR_ARG, PM_ERR_HIP, PM_ERR_OVERFLOW, PM_ERR_STATE, PM_ERR_NOMEM = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host", "pm_bvh_destroy",
-           "pm_bvh_get_info", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
+           "pm_bvh_get_info", "pm_bvh_download", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
            "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
            "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch"]
@@ -33,7 +33,10 @@ class PMError(RuntimeError):
 
 class BvhOpts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("bins", C.c_int32), ("max_leaf", C.c_int32), ("n_threads", C.c_int32),
-                ("trav_cost", C.c_float)]
+                ("trav_cost", C.c_float), ("builder", C.c_int32)]
+
+
+BUILD_HOST_SAH, BUILD_GPU_LBVH = 0, 1
 
 
 class BvhInfo(C.Structure):
@@ -109,6 +112,7 @@ def lib() -> C.CDLL:
         L.pm_build_bvh_host.argtypes = [P, P, I64, P, P, P, P, P]
         L.pm_bvh_destroy.argtypes = [P]
         L.pm_bvh_get_info.argtypes = [P, P]
+        L.pm_bvh_download.argtypes = [P, P, P, P]
         L.pm_trace_rays.argtypes = [P, P, I64, P, P, P]
         L.pm_trace_rays_ex.argtypes = [P, P, I64, P, P, P, P]
         L.pm_sppm_create.argtypes = [P, P, P, P]
@@ -151,10 +155,10 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _opts(bins, max_leaf, n_threads, trav_cost=0.0):
+def _opts(bins, max_leaf, n_threads, trav_cost=0.0, builder=0):
     o = BvhOpts()
     o.size, o.bins, o.max_leaf, o.n_threads = C.sizeof(BvhOpts), bins, max_leaf, n_threads
-    o.trav_cost = trav_cost
+    o.trav_cost, o.builder = trav_cost, builder
     return o
 
 
@@ -188,6 +192,14 @@ class Bvh:
         _check(lib().pm_bvh_get_info(self.h, C.byref(inf)))
         return _info_dict(inf)
 
+    def download(self, stream=None):
+        """(nodes uint32 [6, n_nodes, 4], tris uint32 [n_tri, 12]) copied from the device."""
+        n_nodes = self.info()["n_nodes"]
+        nodes = np.zeros((6, n_nodes, 4), np.uint32)
+        tris = np.zeros((self.n_tri, 12), np.uint32)
+        _check(lib().pm_bvh_download(self.h, _ptr(nodes), _ptr(tris), _stream(stream)))
+        return nodes, tris
+
     def destroy(self):
         if self.h:
             _check(lib().pm_bvh_destroy(self.h))
@@ -201,11 +213,12 @@ class Bvh:
 
 
 def build_bvh(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0,
-              trav_cost=0.0, stream=None) -> Bvh:
+              trav_cost=0.0, builder=0, stream=None) -> Bvh:
+    """Build a device BVH: builder 0 = SAH on the host, 1 = linear BVH on the GPU."""
     v = np.ascontiguousarray(verts, np.float32)
     m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
     out = C.c_void_p()
-    o = _opts(bins, max_leaf, n_threads, trav_cost)
+    o = _opts(bins, max_leaf, n_threads, trav_cost, builder)
     _check(lib().pm_build_bvh(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), _stream(stream),
                               C.byref(out)))
     return Bvh(out.value, v.shape[0])

@@ -11,6 +11,7 @@ struct BuildOptions {
     int max_leaf = 4;
     int n_threads = 0;
     double trav_cost = 1.0;  // SAH: node visit cost relative to a triangle test
+    int builder = 0;         // PM_BUILD_HOST_SAH or PM_BUILD_GPU_LBVH
 };
 
 // Device layout (words are 32-bit):

@@ -33,6 +33,11 @@ static bool read_opts(const pm_bvh_opts *o, BuildOptions &bo) {
     bo.max_leaf = o->max_leaf;
     bo.n_threads = o->n_threads;
     bo.trav_cost = o->trav_cost == 0.0f ? 1.0 : (double)o->trav_cost;
+    bo.builder = o->builder;
+    if (bo.builder != PM_BUILD_HOST_SAH && bo.builder != PM_BUILD_GPU_LBVH) {
+        set_error("builder must be PM_BUILD_HOST_SAH or PM_BUILD_GPU_LBVH");
+        return false;
+    }
     return true;
 }
 
@@ -66,6 +71,7 @@ int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n
         if (info && info->size < sizeof(pm_bvh_info)) return pm::set_error("pm_bvh_info.size too small"), PM_ERR_ARG;
         pm::BuildOptions bo;
         if (!pm::read_opts(opts, bo)) return PM_ERR_ARG;
+        if (bo.builder != PM_BUILD_HOST_SAH) return pm::set_error("the host build is the SAH builder"), PM_ERR_ARG;
         pm::HostBvh hb;
         std::string err;
         if (!pm::build_bvh_host(tri_verts, tri_mat, n_tri, bo, hb, err)) return pm::set_error(err), PM_ERR_ARG;
@@ -97,11 +103,25 @@ int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri,
         *out = nullptr;
         pm::BuildOptions bo;
         if (!pm::read_opts(opts, bo)) return PM_ERR_ARG;
-        pm::HostBvh hb;
-        std::string err;
-        if (!pm::build_bvh_host(tri_verts, tri_mat, n_tri, bo, hb, err)) return pm::set_error(err), PM_ERR_ARG;
-        pm_bvh *b = new pm_bvh();
-        int rc = pm::upload_bvh(hb, (hipStream_t)stream, b);
+        pm_bvh *b = nullptr;
+        int rc;
+        if (bo.builder == PM_BUILD_GPU_LBVH) {
+            if (n_tri < 1 || n_tri >= (int64_t(1) << 28)) return pm::set_error("n_tri must be in [1, 2^28)"), PM_ERR_ARG;
+            if (bo.max_leaf < 1 || bo.max_leaf > 7 || !(bo.trav_cost > 0.0) || bo.trav_cost > 64.0)
+                return pm::set_error("max_leaf must be in [1,7] and trav_cost in (0,64]"), PM_ERR_ARG;
+            for (int64_t i = 0; i < 9 * n_tri; ++i)
+                if (!std::isfinite(tri_verts[i]))
+                    return pm::set_error("non-finite vertex coordinate at triangle " + std::to_string(i / 9)),
+                           PM_ERR_ARG;
+            b = new pm_bvh();
+            rc = pm::build_bvh_gpu(tri_verts, tri_mat, n_tri, bo.max_leaf, bo.trav_cost, (hipStream_t)stream, b);
+        } else {
+            pm::HostBvh hb;
+            std::string err;
+            if (!pm::build_bvh_host(tri_verts, tri_mat, n_tri, bo, hb, err)) return pm::set_error(err), PM_ERR_ARG;
+            b = new pm_bvh();
+            rc = pm::upload_bvh(hb, (hipStream_t)stream, b);
+        }
         if (rc) {
             pm::free_bvh(b);
             delete b;
@@ -117,6 +137,20 @@ int pm_bvh_destroy(pm_bvh *bvh) {
         if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
         pm::free_bvh(bvh);
         delete bvh;
+        return PM_OK;
+    })
+}
+
+int pm_bvh_download(const pm_bvh *b, uint32_t *nodes, uint32_t *tris, void *stream) {
+    PM_GUARD({
+        if (!b) return pm::set_error("NULL bvh"), PM_ERR_ARG;
+        hipStream_t s = (hipStream_t)stream;
+        if (nodes)
+            PM_HIP(hipMemcpyAsync(nodes, b->d_nodes, sizeof(uint32_t) * 4 * 6 * (size_t)b->n_nodes,
+                                  hipMemcpyDeviceToHost, s));
+        if (tris)
+            PM_HIP(hipMemcpyAsync(tris, b->d_tris, sizeof(uint32_t) * 12 * (size_t)b->n_tri, hipMemcpyDeviceToHost, s));
+        PM_HIP(hipStreamSynchronize(s));
         return PM_OK;
     })
 }

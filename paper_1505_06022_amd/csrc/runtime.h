@@ -51,6 +51,11 @@ namespace pm {
 // Device view of a BVH handle (node/triangle pointers and the box grid).
 pmd::Bvh make_device_bvh(const pm_bvh *b);
 
+// Build the BVH on the device from sorted Morton codes (same layout as the
+// host build); fills b.  The caller validates the inputs.
+int build_bvh_gpu(const float *verts, const uint32_t *mats, int64_t n_tri, int max_leaf, double trav_cost,
+                  hipStream_t s, pm_bvh *b);
+
 // Upload a host-built BVH; fills b (device buffers owned by b).
 int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b);
 void free_bvh(pm_bvh *b);

@@ -8,6 +8,7 @@ import re
 import numpy as np
 import pytest
 
+from bvh_structure import check_structure, decode, f32
 from paper_1505_06022_amd import api, scenes
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -41,6 +42,14 @@ def test_host_validation_errors_without_gpu():
     o = api.BvhOpts(C.sizeof(api.BvhOpts), 32, 9, 0, 0.0)
     assert L.pm_build_bvh_host(v.ctypes.data, None, 1, C.byref(o), C.byref(nn), None, None, None) == api.PM_ERR_ARG
     assert L.pm_trace_rays(None, None, 0, None, None, None) == api.PM_ERR_ARG
+    # builder selection is validated before any device work
+    o = api._opts(32, 4, 0, 0.0, builder=2)
+    out_bvh = C.c_void_p()
+    assert L.pm_build_bvh(v.ctypes.data, None, 1, C.byref(o), None, C.byref(out_bvh)) == api.PM_ERR_ARG
+    assert b"builder" in L.pm_last_error()
+    o = api._opts(32, 4, 0, 0.0, builder=api.BUILD_GPU_LBVH)
+    assert L.pm_build_bvh_host(v.ctypes.data, None, 1, C.byref(o), C.byref(nn), None, None, None) == api.PM_ERR_ARG
+    assert L.pm_bvh_download(None, None, None, None) == api.PM_ERR_ARG
     # scene/param validation happens before any device work
     sc = scenes.box_scene(8, 8)
     args = api._SceneArgs(sc)
@@ -69,74 +78,12 @@ def test_host_validation_errors_without_gpu():
     assert L.pm_sppm_load(None, None, 0, None) == api.PM_ERR_ARG
 
 
-def _f(words):
-    return words.view(np.float32)
-
-
-def _decode(nodes_s, info):
-    """Dequantised boxes (float64), leaf flags, leaf ranges and next-on-miss links."""
-    w = nodes_s.astype(np.int64)
-    q = np.stack([w[:, 0] & 0xffff, w[:, 0] >> 16, w[:, 1] & 0xffff,
-                  w[:, 1] >> 16, w[:, 2] & 0xffff, w[:, 2] >> 16], 1).astype(np.float64)
-    g0 = np.asarray(info["grid_lo"], np.float64)
-    gs = np.asarray(info["grid_step"], np.float64)
-    lo = g0 + q[:, 0:3] * gs
-    hi = g0 + q[:, 3:6] * gs
-    leaf = (w[:, 3] >> 31) != 0
-    first = (w[:, 3] >> 3) & 0x0fffffff
-    cnt = w[:, 3] & 7
-    n = len(w)
-    skip = np.where(leaf, np.arange(n) + 1, w[:, 3])
-    return lo, hi, leaf, first, cnt, skip
-
-
-def _check_structure(verts, nodes, tris, max_leaf, info):
-    T = len(verts)
-    S, n, _ = nodes.shape
-    assert S == 6
-    # triangles: every original index exactly once, edges = fl32(v - v0)
-    ids = tris[:, 9].astype(np.int64)
-    assert np.array_equal(np.sort(ids), np.arange(T))
-    tf = _f(tris)
-    v = verts[ids]
-    assert np.array_equal(tf[:, 0:3], v[:, 0])
-    assert np.array_equal(tf[:, 3:6], (v[:, 1] - v[:, 0]).astype(np.float32))
-    assert np.array_equal(tf[:, 6:9], (v[:, 2] - v[:, 0]).astype(np.float32))
-    for s in range(6):
-        lo, hi, is_leaf, first, cnt, skip = _decode(nodes[s], info)
-        assert skip[0] == n                              # root's miss link ends the walk
-        assert np.all(skip > np.arange(n)) and np.all(skip <= n)
-        assert np.all(cnt[is_leaf] >= 1) and np.all(cnt[is_leaf] <= max_leaf)
-        # every triangle in exactly one leaf, inside its (padded, quantised) box
-        cover = np.zeros(T, np.int64)
-        for i in np.nonzero(is_leaf)[0]:
-            cover[first[i]:first[i] + cnt[i]] += 1
-            tv = verts[ids[first[i]:first[i] + cnt[i]]].reshape(-1, 3).astype(np.float64)
-            assert np.all(tv > lo[i]) and np.all(tv < hi[i])
-        assert np.all(cover == 1)
-        # inner nodes: children are i+1 and skip[i+1]; their boxes nest
-        for i in np.nonzero(~is_leaf)[0]:
-            a = i + 1
-            b = skip[a]
-            assert skip[b] == skip[i]
-            for c in (a, b):
-                assert np.all(lo[c] >= lo[i]) and np.all(hi[c] <= hi[i])
-            # children pre-sorted along the set's direction (centres of the
-            # quantised boxes can tie; the order then follows the exact boxes)
-            axis, neg = s // 2, s % 2
-            ka = lo[a][axis] + hi[a][axis]
-            kb = lo[b][axis] + hi[b][axis]
-            tol = 4 * info["grid_step"][axis]
-            assert (ka >= kb - tol) if neg else (ka <= kb + tol)
-    return True
-
-
 def _py_traverse(nodes, tris, info, ray, s):
     """Stackless walk of one link set (hit link = next node, miss = skip)."""
-    lo, hi, leaf, first, cnt, skip = _decode(nodes[s], info)
+    lo, hi, leaf, first, cnt, skip = decode(nodes[s], info)
     o, d = ray[0:3].astype(np.float64), ray[4:7].astype(np.float64)
     tmin, tmax = float(ray[3]), float(ray[7])
-    tf = _f(tris)
+    tf = f32(tris)
     best, tb = -1, tmax
     i, n = 0, nodes.shape[1]
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -188,7 +135,7 @@ def _mt32(ray, tri):
 def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, seed, n):
     sc = scenes.small_soup(n, seed, spread=0.4 / max(1.0, np.cbrt(n)))
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
-    assert _check_structure(sc.verts, nodes, tris, 4, info)
+    assert check_structure(sc.verts, nodes, tris, 4, info)
     assert info["n_nodes"] == nodes.shape[1] and info["n_tri"] == n
     rays = scenes.random_rays(60, seed)
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
@@ -204,8 +151,8 @@ def _py_wave_postponed(nodes, tris, info, rays, s, late):
     """Lockstep model of one wavefront running the postponed-leaf walk: box
     visits until at most `late` lanes still search (and one lane holds a leaf),
     then every held leaf is tested; a holding lane halts at its next leaf hit."""
-    lo, hi, leaf, first, cnt, skip = _decode(nodes[s], info)
-    tf = _f(tris)
+    lo, hi, leaf, first, cnt, skip = decode(nodes[s], info)
+    tf = f32(tris)
     L, n = len(rays), nodes.shape[1]
     o = rays[:, 0:3].astype(np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -277,16 +224,16 @@ def test_postponed_leaf_walk_model_matches_brute_force(oracle_lib, late):
 def test_host_bvh_box_scene_and_soup_statistics():
     sc = scenes.box_scene()
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
-    _check_structure(sc.verts, nodes, tris, 4, info)
+    check_structure(sc.verts, nodes, tris, 4, info)
     assert np.array_equal(tris[:, 10], sc.tri_mat[tris[:, 9]])
     sc = scenes.soup_scene(1 << 14, seed=9)
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8)
-    _check_structure(sc.verts, nodes, tris, 2, info)
+    check_structure(sc.verts, nodes, tris, 2, info)
     # SAH tree: cheaper than the worst case of one leaf per 2 triangles in a chain
     assert info["depth"] < 64 and info["sah_cost"] > 0
     # a costlier node visit gives fewer nodes and fuller leaves
     n2, t2, info2 = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8, trav_cost=4.0)
-    _check_structure(sc.verts, n2, t2, 2, info2)
+    check_structure(sc.verts, n2, t2, 2, info2)
     assert info2["n_nodes"] < info["n_nodes"]
     # storage: 6 link sets x 16 B per node + 48 B per triangle
     assert info["device_bytes"] == 6 * 16 * info["n_nodes"] + 48 * info["n_tri"]
