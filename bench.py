@@ -185,6 +185,34 @@ def traversal_bench(args, torch, api, scenes):
             tbvh[f"link_set_{ls}"] = {"coherent_mrays_s": round(len(rc) / ms[0] / 1e3, 1),
                                       "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1),
                                       "mrays_s": round((len(rc) + len(ri)) / ms.sum() / 1e3, 1)}
+    # the GPU linear-BVH builder: build time and traversal rate with the timed options
+    lbvh = None
+    if not args.no_variants:
+        for _ in range(2):   # the first build also loads the sort kernels
+            t_b = time.perf_counter()
+            lb = api.build_bvh(sc.verts, sc.tri_mat, builder=api.BUILD_GPU_LBVH)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t_b) * 1e3
+            if _ == 0:
+                lb.destroy()
+        linf = lb.info()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
+        ms = np.zeros(len(batches))
+        for rep in range(4):
+            for b, (r, (h, t), kw) in enumerate(zip(batches, outs, trace_kw)):
+                e[2 * b].record(stream)
+                api.trace_rays(lb, r, h, t, **kw)
+                e[2 * b + 1].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                ms += [e[2 * b].elapsed_time(e[2 * b + 1]) for b in range(len(batches))]
+        ms /= 3
+        lbvh = {"build_ms_wall": round(wall_ms, 1), "n_nodes": linf["n_nodes"], "depth": linf["depth"],
+                "sah_cost": round(linf["sah_cost"], 1), "host_sah_build_ms": round(info["build_ms"], 1),
+                "coherent_mrays_s": round(len(rc) / ms[0] / 1e3, 1),
+                "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1),
+                "mrays_s": round((len(rc) + len(ri)) / ms.sum() / 1e3, 1)}
+        lb.destroy()
     # SAH node-visit cost (relative to a triangle test): tree size vs traversal rate
     sah = {}
     if not args.no_variants:
@@ -216,6 +244,7 @@ def traversal_bench(args, torch, api, scenes):
     return dict(
         n_rays=n_rays, step_ms=step_ms, kern_ms=kern_ms, info=info, per_batch=per_batch,
         achieved=achieved, per_launch_bytes=per_launch_bytes, hit_frac=hit_frac, variants=variants, tbvh=tbvh,
+        lbvh=lbvh,
         coherent_mrays=len(rc) / (kern_ms[:, 0].mean() * 1e-3) / 1e6,
         incoherent_mrays=len(ri) / (kern_ms[:, 1].mean() * 1e-3) / 1e6,
         scene=sc, rays=(coh, inc),
@@ -441,6 +470,7 @@ def main():
         "kernel_mrays_s": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6, 2),
         "bvh": {k: tb["info"][k] for k in ("n_nodes", "n_leaves", "depth", "sah_cost", "device_bytes", "build_ms")},
         "kernel_variants": tb["variants"],
+        "gpu_lbvh": tb["lbvh"],
         "tbvh_ablation": ({"single_link_set": tb["tbvh"],
                            "mtbvh_over_mean_tbvh": round(tb["n_rays"] / (tb["kern_ms"].sum(1).mean() * 1e-3) / 1e6 /
                                                          float(np.mean([v["mrays_s"] for v in tb["tbvh"].values()])), 3)}
