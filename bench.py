@@ -387,6 +387,31 @@ def batch_bench(args, torch, api, scenes):
             "setup_s": round(t_setup, 2)}
 
 
+def achievable_bandwidth(torch):
+    """Measured streaming bandwidth of the device: a 1 GiB device-to-device
+    copy (read + write bytes) and a reduction that reads 1 GiB (the traversal's
+    bytes are almost all reads).  Each is the best of 5."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best_ms(fn):
+        best = 1e30
+        for _ in range(5):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    copy_ms = best_ms(lambda: dst.copy_(src))
+    read_ms = best_ms(lambda: src.sum())
+    nb = src.numel() * 4
+    del src, dst
+    return {"copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1), "read_GBps": round(nb / (read_ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(tb, scenes):
     import oracle
     nth = _cpu_threads()
@@ -485,6 +510,9 @@ def main():
                      "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4),
                      "launch_ms_by_batch": [round(float(x), 4) for x in tb["kern_ms"].mean(0)]},
     }
+    ach = achievable_bandwidth(torch)
+    best = max(ach["copy_GBps"], ach["read_GBps"])
+    out["roofline"]["achievable"] = dict(ach, frac=round(tb["achieved"] / best, 4))
     if not args.no_sppm:
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
