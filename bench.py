@@ -52,7 +52,22 @@ KERNEL_VARIANTS = (
     ("two_rays_reorder2_block64", dict(kernel=5, reorder=2, block=64)),
     ("persistent_reorder1_refill4", dict(kernel=2, refill=4, reorder=1)),
     ("persistent_reorder1_refill16", dict(kernel=2, refill=16, reorder=1)),
-    ("persistent_reorder1_refill32", dict(kernel=2, refill=32, reorder=1)))
+    ("persistent_reorder1_refill32", dict(kernel=2, refill=32, reorder=1)),
+    ("per_ray_tiles_block64", dict(kernel=1, block=64, tile_width="image")),
+    ("packet_block64", dict(kernel=6, block=64)), ("packet_tiles", dict(kernel=6, tile_width="image")),
+    ("packet_tiles_block64", dict(kernel=6, block=64, tile_width="image")),
+    ("packet_reorder1_block64", dict(kernel=6, block=64, reorder=1)))
+
+IMAGE_WIDTH = 1920   # of the camera batch
+
+
+def _kw_for(kw: dict, batch: int) -> dict:
+    """Trace options for one batch: tile_width "image" takes the camera batch in
+    8x8 pixel tiles and does not apply to the incoherent batch."""
+    d = dict(kw)
+    if d.get("tile_width") == "image":
+        d["tile_width"] = IMAGE_WIDTH if batch == 0 else 0
+    return d
 
 
 def measured_traffic():
@@ -117,7 +132,7 @@ def traversal_bench(args, torch, api, scenes):
     # camera rays are traced in pixel order; the incoherent batch is first
     # bucketed by (link set, origin cell) -- an option of the trace call
     table = dict(KERNEL_VARIANTS)
-    trace_kw = [table[args.coherent], table[args.incoherent]]
+    trace_kw = [_kw_for(table[args.coherent], 0), _kw_for(table[args.incoherent], 1)]
     outs = [(torch.empty(len(r), dtype=torch.int32, device=dev), torch.empty(len(r), dtype=torch.float32, device=dev))
             for r in batches]
     n_rays = sum(len(r) for r in batches)
@@ -158,7 +173,7 @@ def traversal_bench(args, torch, api, scenes):
         for rep in range(4):
             for b, (r, (h, t)) in enumerate(zip(batches, outs)):
                 e[2 * b].record(stream)
-                api.trace_rays(bvh, r, h, t, **kw)
+                api.trace_rays(bvh, r, h, t, **_kw_for(kw, b))
                 e[2 * b + 1].record(stream)
             torch.cuda.synchronize()
             if rep:

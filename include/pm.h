@@ -149,16 +149,19 @@ PM_API int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_
  * ray per lane testing nodes i and i+1 from one memory round trip; one ray
  * per lane with leaf tests postponed until the wavefront's lanes hold leaf
  * hits together (box visits and triangle tests then run in separate phases
- * instead of sharing each iteration); or two consecutive rays per lane walked
- * in lockstep (two node loads in flight per lane).  All return the same
- * result. */
+ * instead of sharing each iteration); two consecutive rays per lane walked
+ * in lockstep (two node loads in flight per lane); or a wavefront's rays as
+ * one packet (the wavefront follows one node index, taking the hit link when
+ * any lane's box test passes; used when all its rays share a link set, else
+ * the per-ray walk).  All return the same result. */
 enum {
     PM_TRACE_AUTO = 0,
     PM_TRACE_PER_RAY = 1,
     PM_TRACE_PERSISTENT = 2,
     PM_TRACE_PAIRED = 3,
     PM_TRACE_POSTPONED = 4,
-    PM_TRACE_TWO_RAYS = 5
+    PM_TRACE_TWO_RAYS = 5,
+    PM_TRACE_PACKET = 6
 };
 
 typedef struct {
@@ -181,6 +184,10 @@ typedef struct {
                            library-owned scratch of 4 B per ray. */
     int32_t block;      /* threads per workgroup of every kernel but the
                            persistent one: 64, 128 or 256 (0 = default) */
+    int32_t tile_width; /* > 0: the rays are the pixels of an image this
+                           wide in row-major order (n a multiple of it); each
+                           wavefront takes an 8x8 pixel tile.  Not with
+                           reorder, the persistent or the two-ray kernel. */
 } pm_trace_opts;
 
 /* pm_trace_rays with options (ablation of the link-set choice; per-ray

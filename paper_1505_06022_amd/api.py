@@ -48,10 +48,10 @@ class BvhInfo(C.Structure):
 
 class TraceOpts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("link_set", C.c_int32), ("counters", C.c_void_p), ("kernel", C.c_int32),
-                ("refill", C.c_int32), ("reorder", C.c_int32), ("block", C.c_int32)]
+                ("refill", C.c_int32), ("reorder", C.c_int32), ("block", C.c_int32), ("tile_width", C.c_int32)]
 
 
-TRACE_AUTO, TRACE_PER_RAY, TRACE_PERSISTENT, TRACE_PAIRED, TRACE_POSTPONED, TRACE_TWO_RAYS = 0, 1, 2, 3, 4, 5
+TRACE_AUTO, TRACE_PER_RAY, TRACE_PERSISTENT, TRACE_PAIRED, TRACE_POSTPONED, TRACE_TWO_RAYS, TRACE_PACKET = range(7)
 
 
 class SceneDesc(C.Structure):
@@ -244,7 +244,7 @@ def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32
 
 
 def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=None, kernel: int = 0, refill: int = 0,
-               reorder: int = 0, block: int = 0, stream=None):
+               reorder: int = 0, block: int = 0, tile_width: int = 0, stream=None):
     """Closest hit of each ray.  rays: float32 cuda tensor [n, 8]; returns (hit int32 [n], t float32 [n])."""
     import torch
     assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
@@ -253,13 +253,15 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
         hit = torch.empty(n, dtype=torch.int32, device=rays.device)
     if t is None:
         t = torch.empty(n, dtype=torch.float32, device=rays.device)
-    if link_set == -1 and counters is None and kernel == 0 and refill == 0 and not reorder and not block:
+    if link_set == -1 and counters is None and kernel == 0 and refill == 0 and not reorder and not block \
+            and not tile_width:
         _check(lib().pm_trace_rays(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), _stream(stream)))
     else:
         o = TraceOpts()
         o.size, o.link_set, o.kernel, o.refill = C.sizeof(TraceOpts), link_set, kernel, refill
         o.reorder = int(reorder)   # 0 none, 1 coarse, 2 fine
         o.block = int(block)
+        o.tile_width = int(tile_width)
         o.counters = None if counters is None else counters.data_ptr()
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t

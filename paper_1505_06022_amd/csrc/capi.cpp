@@ -180,12 +180,12 @@ int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *h
         if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
         if (n < 0) return pm::set_error("n must be >= 0"), PM_ERR_ARG;
         if (n > 0 && (!rays || !hit || !t)) return pm::set_error("NULL ray or output pointer"), PM_ERR_ARG;
-        int set = -1, kernel = PM_TRACE_AUTO, refill = 0, reorder = 0, block = 0;
+        int set = -1, kernel = PM_TRACE_AUTO, refill = 0, reorder = 0, block = 0, tile_w = 0;
         uint32_t *counters = nullptr;
         if (opts) {
             if (opts->size < sizeof(pm_trace_opts)) return pm::set_error("pm_trace_opts.size too small"), PM_ERR_ARG;
             if (opts->link_set < -1 || opts->link_set > 5) return pm::set_error("link_set must be in [-1,5]"), PM_ERR_ARG;
-            if (opts->kernel < 0 || opts->kernel > PM_TRACE_TWO_RAYS)
+            if (opts->kernel < 0 || opts->kernel > PM_TRACE_PACKET)
                 return pm::set_error("unknown traversal kernel"), PM_ERR_ARG;
             if (opts->refill < 0 || opts->refill > 64) return pm::set_error("refill must be in [0,64]"), PM_ERR_ARG;
             if (opts->kernel == PM_TRACE_POSTPONED && opts->refill > 63)
@@ -193,15 +193,25 @@ int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *h
             if (opts->reorder < 0 || opts->reorder > 2) return pm::set_error("reorder must be 0, 1 or 2"), PM_ERR_ARG;
             if (opts->block != 0 && opts->block != 64 && opts->block != 128 && opts->block != 256)
                 return pm::set_error("block must be 0, 64, 128 or 256"), PM_ERR_ARG;
+            if (opts->tile_width < 0) return pm::set_error("tile_width must be >= 0"), PM_ERR_ARG;
+            if (opts->tile_width > 0) {
+                if (n % opts->tile_width != 0)
+                    return pm::set_error("tile_width must divide the number of rays"), PM_ERR_ARG;
+                if (opts->reorder != 0 || opts->kernel == PM_TRACE_PERSISTENT || opts->kernel == PM_TRACE_TWO_RAYS)
+                    return pm::set_error("tile_width takes the rays in image order: no reorder, persistent or "
+                                         "two-ray kernel"),
+                           PM_ERR_ARG;
+            }
             set = opts->link_set;
             counters = opts->counters;
+            tile_w = opts->tile_width;
             kernel = opts->kernel;
             refill = opts->refill;
             reorder = opts->reorder;
             block = opts->block;
         }
         if (n >= (int64_t(1) << 31)) return pm::set_error("n must be below 2^31"), PM_ERR_ARG;
-        return pm::launch_trace(bvh, rays, n, hit, t, set, counters, kernel, refill, reorder, block,
+        return pm::launch_trace(bvh, rays, n, hit, t, set, counters, kernel, refill, reorder, block, tile_w,
                                 (hipStream_t)stream);
     })
 }

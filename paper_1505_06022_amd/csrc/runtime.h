@@ -61,8 +61,9 @@ int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b);
 void free_bvh(pm_bvh *b);
 
 // Launch the closest-hit kernel.  link_set < 0 selects by direction; block:
-// threads per workgroup of the one-ray-per-lane kernels (64, 128 or 256).
+// threads per workgroup of the one-ray-per-lane kernels (64, 128 or 256);
+// tile_w > 0: the rays are an image tile_w wide, taken in 8x8 tiles per wave.
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s);
+                 uint32_t *counters, int kernel, int refill, int reorder, int block, int tile_w, hipStream_t s);
 
 }  // namespace pm

@@ -14,9 +14,36 @@ constexpr uint32_t kNoRay = 0xffffffffu;
 // Walk orders: one ray per lane, one node per visit with the leaf's
 // triangles tested at once (kWalkStep); nodes i and i + 1 from one memory
 // round trip (kWalkPaired); leaf tests postponed until the wave's lanes hold
-// leaves together (kWalkPostponed); or two rays per lane in lockstep
-// (kWalkTwo).  All give the same closest hit.
-enum { kWalkStep = 0, kWalkPaired = 1, kWalkPostponed = 2, kWalkTwo = 3 };
+// leaves together (kWalkPostponed); two rays per lane in lockstep (kWalkTwo);
+// or the wave's rays as one packet (kWalkPacket).  All give the same closest
+// hit.
+enum { kWalkStep = 0, kWalkPaired = 1, kWalkPostponed = 2, kWalkTwo = 3, kWalkPacket = 4 };
+
+// Packet walk, for a wave whose lanes all walk one link set: the wave follows
+// one node index, taking the hit link when any lane's box test passes and the
+// skip link otherwise; at a leaf each lane whose own box test passes tests the
+// triangles.  The nodes a lane meets are a superset of those of its own walk
+// and its box tests use its own t_best, so its closest hit is unchanged.  The
+// node index, the link words and so every branch are uniform across the wave,
+// and all lanes read the same node and triangle records.
+template <bool kStats>
+__device__ __forceinline__ void walk_packet(pmd::Walker &w, const uint4 *__restrict__ nodes, uint32_t n,
+                                            const float4 *__restrict__ tris, pmd::TraceStats &st) {
+    uint32_t i = 0;
+    while (i < n) {
+        const uint4 q = nodes[i];
+        const uint32_t link = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.w);
+        const bool hit = w.box_hit(q);
+        if (kStats) st.boxes++;
+        if ((link >> 31) != 0u) {
+            if (hit) w.leaf_tris<kStats>(tris, link, st);
+            ++i;
+        } else {
+            i = __ballot(hit) != 0ull ? i + 1 : link;
+        }
+    }
+    w.i = n;
+}
 
 template <int kWalk, bool kStats>
 __device__ __forceinline__ void walk(pmd::Walker &w, const float4 *__restrict__ tris, uint32_t late,
@@ -53,12 +80,14 @@ __device__ __forceinline__ void finish_walk(const pmd::Walker &w, const pmd::Tra
 }
 
 // The rays of slot j: ray j (kPerm false) or perm[j]; two consecutive slots
-// per lane for kWalkTwo.  Results go to each ray's own index.
+// per lane for kWalkTwo.  With tile_w > 0 (kPerm false) the rays are the
+// pixels of an image tile_w wide in row-major order and each wave takes an
+// 8x8 tile.  Results go to each ray's own index.
 template <bool kStats, int kWalk, bool kPerm>
 __device__ __forceinline__ void trace_slot(const pmd::Bvh &bvh, const float4 *__restrict__ rays,
                                            const uint32_t *__restrict__ perm, uint64_t lane, uint64_t n,
                                            int32_t *__restrict__ hit, float *__restrict__ tout, int32_t force_set,
-                                           uint32_t *__restrict__ counters, uint32_t late) {
+                                           uint32_t *__restrict__ counters, uint32_t late, uint32_t tile_w) {
     if (kWalk == kWalkTwo) {
         const uint64_t ja = 2 * lane, jb = ja + 1;
         if (ja >= n) return;
@@ -78,12 +107,29 @@ __device__ __forceinline__ void trace_slot(const pmd::Bvh &bvh, const float4 *__
         finish_walk<kStats>(a, sa, ra, hit, tout, counters);
         if (has_b) finish_walk<kStats>(b, sb, rb, hit, tout, counters);
     } else {
-        if (lane >= n) return;
-        const size_t r = kPerm ? perm[lane] : lane;
+        size_t r;
+        if (!kPerm && tile_w > 0) {
+            const uint64_t wave = lane >> 6, l = lane & 63u, tiles_x = (tile_w + 7u) / 8u;
+            const uint64_t x = (wave % tiles_x) * 8u + (l & 7u), y = (wave / tiles_x) * 8u + (l >> 3);
+            if (x >= tile_w || y >= n / tile_w) return;
+            r = (size_t)(y * tile_w + x);
+        } else {
+            if (lane >= n) return;
+            r = kPerm ? perm[lane] : lane;
+        }
         pmd::Walker w;
         pmd::TraceStats st{0u, 0u};
         start_walk(w, bvh, rays, r, force_set);
-        walk<kWalk, kStats>(w, bvh.tris, late, st);
+        if (kWalk == kWalkPacket) {
+            const int set = (int)((w.nodes - bvh.nodes) / bvh.n_nodes);
+            const int set0 = __builtin_amdgcn_readfirstlane(set);
+            if (__ballot(set != set0) == 0ull)  // one link set for the whole wave: its base is uniform
+                walk_packet<kStats>(w, bvh.nodes + (size_t)(uint32_t)set0 * bvh.n_nodes, bvh.n_nodes, bvh.tris, st);
+            else
+                walk<kWalkStep, kStats>(w, bvh.tris, late, st);  // link sets differ within the wave
+        } else {
+            walk<kWalk, kStats>(w, bvh.tris, late, st);
+        }
         finish_walk<kStats>(w, st, r, hit, tout, counters);
     }
 }
@@ -93,9 +139,10 @@ template <bool kStats, int kWalk>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(pmd::Bvh bvh, const float4 *__restrict__ rays, int64_t n,
                                                        int32_t *__restrict__ hit, float *__restrict__ tout,
                                                        int32_t force_set, uint32_t *__restrict__ counters,
-                                                       uint32_t late) {
+                                                       uint32_t late, uint32_t tile_w) {
     const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    trace_slot<kStats, kWalk, false>(bvh, rays, nullptr, lane, (uint64_t)n, hit, tout, force_set, counters, late);
+    trace_slot<kStats, kWalk, false>(bvh, rays, nullptr, lane, (uint64_t)n, hit, tout, force_set, counters, late,
+                                     tile_w);
 }
 
 // Persistent wavefronts with ray replacement (the scheduling idea of the
@@ -224,7 +271,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const 
                                                             int32_t force_set, uint32_t *__restrict__ counters,
                                                             uint32_t late) {
     const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    trace_slot<kStats, kWalk, true>(bvh, rays, perm, lane, n, hit, tout, force_set, counters, late);
+    trace_slot<kStats, kWalk, true>(bvh, rays, perm, lane, n, hit, tout, force_set, counters, late, 0u);
 }
 
 }  // namespace
@@ -307,13 +354,18 @@ static int walk_of(int kernel) {
     case PM_TRACE_PAIRED: return kWalkPaired;
     case PM_TRACE_POSTPONED: return kWalkPostponed;
     case PM_TRACE_TWO_RAYS: return kWalkTwo;
+    case PM_TRACE_PACKET: return kWalkPacket;
     default: return kWalkStep;
     }
 }
 
 template <class K>
-static K pick_walk(int wk, K step, K paired, K postponed, K two) {
-    return wk == kWalkPaired ? paired : wk == kWalkPostponed ? postponed : wk == kWalkTwo ? two : step;
+static K pick_walk(int wk, K step, K paired, K postponed, K two, K packet) {
+    return wk == kWalkPaired       ? paired
+           : wk == kWalkPostponed ? postponed
+           : wk == kWalkTwo       ? two
+           : wk == kWalkPacket    ? packet
+                                  : step;
 }
 
 static int launch_persistent(const pm_bvh *b, const pmd::Bvh &bvh, const float *rays, uint32_t n, int32_t *hit,
@@ -369,9 +421,11 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
                           uint32_t *, uint32_t);
     const int wk = walk_of(kernel);
     Kern kern = counters ? pick_walk<Kern>(wk, k_trace_perm<true, kWalkStep>, k_trace_perm<true, kWalkPaired>,
-                                           k_trace_perm<true, kWalkPostponed>, k_trace_perm<true, kWalkTwo>)
+                                           k_trace_perm<true, kWalkPostponed>, k_trace_perm<true, kWalkTwo>,
+                                           k_trace_perm<true, kWalkPacket>)
                          : pick_walk<Kern>(wk, k_trace_perm<false, kWalkStep>, k_trace_perm<false, kWalkPaired>,
-                                           k_trace_perm<false, kWalkPostponed>, k_trace_perm<false, kWalkTwo>);
+                                           k_trace_perm<false, kWalkPostponed>, k_trace_perm<false, kWalkTwo>,
+                                           k_trace_perm<false, kWalkPacket>);
     const uint32_t lanes = wk == kWalkTwo ? (nn + 1) / 2 : nn;
     hipLaunchKernelGGL(kern, dim3((lanes + block - 1) / block), dim3(block), 0, s, bvh, (const float4 *)rays,
                        (const uint32_t *)b->d_perm, nn, hit, t, link_set, counters, late);
@@ -380,7 +434,7 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
 }
 
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s) {
+                 uint32_t *counters, int kernel, int refill, int reorder, int block, int tile_w, hipStream_t s) {
     if (block == 0) block = kDefaultWalkBlock;
     if (n == 0) return PM_OK;
     pmd::Bvh bvh = make_device_bvh(b);
@@ -399,19 +453,26 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
         return launch_persistent(b, bvh, rays, (uint32_t)n, hit, t, link_set, counters, refill, nullptr, s);
     }
     const int wk = walk_of(kernel);
-    const int64_t lanes = wk == kWalkTwo ? (n + 1) / 2 : n;
+    int64_t lanes = wk == kWalkTwo ? (n + 1) / 2 : n;
+    if (tile_w > 0) {  // one wave per 8x8 tile of a tile_w x (n / tile_w) image
+        const int64_t tiles = ((tile_w + 7) / 8) * ((n / tile_w + 7) / 8);
+        lanes = tiles * 64;
+    }
     int64_t nblk = (lanes + block - 1) / block;
     if (nblk > 0x7fffffff) {
         set_error("too many rays for one launch");
         return PM_ERR_ARG;
     }
-    using Kern = void (*)(pmd::Bvh, const float4 *, int64_t, int32_t *, float *, int32_t, uint32_t *, uint32_t);
+    using Kern = void (*)(pmd::Bvh, const float4 *, int64_t, int32_t *, float *, int32_t, uint32_t *, uint32_t,
+                          uint32_t);
     Kern kern = counters ? pick_walk<Kern>(wk, k_trace<true, kWalkStep>, k_trace<true, kWalkPaired>,
-                                           k_trace<true, kWalkPostponed>, k_trace<true, kWalkTwo>)
+                                           k_trace<true, kWalkPostponed>, k_trace<true, kWalkTwo>,
+                                           k_trace<true, kWalkPacket>)
                          : pick_walk<Kern>(wk, k_trace<false, kWalkStep>, k_trace<false, kWalkPaired>,
-                                           k_trace<false, kWalkPostponed>, k_trace<false, kWalkTwo>);
+                                           k_trace<false, kWalkPostponed>, k_trace<false, kWalkTwo>,
+                                           k_trace<false, kWalkPacket>);
     hipLaunchKernelGGL(kern, dim3((uint32_t)nblk), dim3(block), 0, s, bvh, (const float4 *)rays, n, hit, t,
-                       link_set, counters, late);
+                       link_set, counters, late, (uint32_t)tile_w);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

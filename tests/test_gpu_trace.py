@@ -90,7 +90,7 @@ def test_every_link_set_and_stats_mode_agree(torch_cuda, oracle_lib):
     (1, 0, False, 0), (2, 1, False, 0), (2, 16, False, 0), (2, 64, False, 0), (1, 0, 1, 0), (1, 0, 2, 0),
     (3, 0, 0, 0), (4, 0, 0, 0), (4, 7, 0, 0), (4, 63, 0, 0), (4, 0, 1, 0), (4, 16, 2, 0), (3, 0, 1, 0),
     (1, 0, 0, 64), (1, 0, 1, 128), (4, 16, 1, 64), (3, 0, 0, 128), (5, 0, 0, 0), (5, 0, 1, 64),
-    (5, 0, 2, 128), (2, 16, 1, 0), (2, 1, 2, 0)])
+    (5, 0, 2, 128), (2, 16, 1, 0), (2, 1, 2, 0), (6, 0, 0, 0), (6, 0, 1, 64), (6, 0, 0, 128)])
 def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder, block):
     _log(f"case: traversal kernel={kernel} refill={refill} reorder={reorder} block={block}")
     sc = scenes.small_soup(5000, 11, spread=0.02)
@@ -103,6 +103,32 @@ def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder
     h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, counters=cnt, reorder=reorder,
                       block=block)
     _compare(h, t, h_ref, t_ref)
+
+
+@pytest.mark.parametrize("kernel,block", [(1, 0), (3, 64), (4, 128), (6, 0), (6, 64)])
+def test_image_tiles_and_packets(torch_cuda, oracle_lib, kernel, block):
+    """Camera rays taken in 8x8 pixel tiles per wave (a ragged 37x23 image and
+    a 64x64 one), each kernel, against brute force; packets of random rays
+    (mixed link sets) take the per-ray walk."""
+    _log(f"case: image tiles kernel={kernel} block={block}")
+    sc = scenes.small_soup(3000, 12, spread=0.03)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    for w, h in ((37, 23), (64, 64)):
+        cam = scenes.Camera(pos=(0.5, 0.5, -1.5), look=(0.5, 0.5, 0.5), up=(0.0, 1.0, 0.0), tan_half_fov=0.4,
+                            width=w, height=h)
+        rays = scenes.pinhole_rays(cam)
+        h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+        hh, tt = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, block=block, tile_width=w)
+        _compare(hh, tt, h_ref, t_ref)
+        cnt = torch_cuda.zeros((len(rays), 2), dtype=torch_cuda.int32, device="cuda")
+        hh, tt = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, block=block, tile_width=w, counters=cnt)
+        _compare(hh, tt, h_ref, t_ref)
+        assert cnt.cpu().numpy()[:, 0].min() >= 1
+    rays = scenes.random_rays(4100, 12)
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+    hh, tt = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, block=block, tile_width=41)
+    _compare(hh, tt, h_ref, t_ref)
+    bvh.destroy()
 
 
 def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
@@ -123,6 +149,11 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
         assert np.array_equal(h, h4) and np.array_equal(t, t4)
     h5, t5 = _gpu_trace(torch_cuda, bvh, rays, kernel=5)     # two rays per lane: identical
     assert np.array_equal(h, h5) and np.array_equal(t, t5)
+    nc = len(coh)                                             # camera rays as packets of 8x8 tiles: identical
+    h6, t6 = _gpu_trace(torch_cuda, bvh, coh, kernel=6, block=64, tile_width=1920)
+    assert np.array_equal(h[:nc], h6) and np.array_equal(t[:nc], t6)
+    h6, t6 = _gpu_trace(torch_cuda, bvh, rays, kernel=6)
+    assert np.array_equal(h, h6) and np.array_equal(t, t6)
     h5, t5 = _gpu_trace(torch_cuda, bvh, rays[:-1], kernel=5, reorder=1, block=64)   # odd count
     assert np.array_equal(h[:-1], h5) and np.array_equal(t[:-1], t5)
     for level in (1, 2):                                      # reordered: identical
@@ -148,7 +179,8 @@ def test_trace_option_errors(torch_cuda):
     sc = scenes.small_soup(64, 1)
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     r = torch_cuda.from_numpy(scenes.random_rays(100, 1)).cuda()
-    for kw in (dict(block=100), dict(block=512), dict(kernel=6), dict(kernel=4, refill=64), dict(reorder=3),
+    for kw in (dict(block=100), dict(block=512), dict(kernel=7), dict(kernel=4, refill=64), dict(reorder=3),
+               dict(tile_width=7), dict(tile_width=-1), dict(tile_width=10, reorder=1), dict(tile_width=10, kernel=2),
                dict(link_set=6)):
         with pytest.raises(api.PMError) as e:
             api.trace_rays(bvh, r, **kw)
