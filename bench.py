@@ -5,8 +5,9 @@ Default workload (the traversal-only configuration): 2^20 random triangles
 SAH-binned BVH (32 bins, <= 4 triangles per leaf), 1920x1080 coherent pinhole
 rays plus 2^21 incoherent rays.  One step = closest-hit traversal of all
 4,170,752 rays: two trace calls, inputs resident in HBM.  The camera batch is
-traced in pixel order (--coherent), the incoherent batch after bucketing by
-(link set, origin cell) with postponed leaf tests (--incoherent); every
+traced as packets, one wavefront per 8x8 pixel tile (--coherent), the
+incoherent batch after bucketing by (link set, origin cell) with postponed
+leaf tests (--incoherent); every
 option listed in KERNEL_VARIANTS gives identical results and is also timed.
 The JSON line reports Mrays/s, the traversal's algorithmic-bytes roofline,
 the CPU oracle timed on the host, the SPPM iteration on the 250k-triangle
@@ -104,7 +105,7 @@ def _parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the comparison of traversal kernels")
     names = [k for k, _ in KERNEL_VARIANTS]
-    ap.add_argument("--coherent", default="per_ray_block64", choices=names,
+    ap.add_argument("--coherent", default="packet_tiles_block64", choices=names,
                     help="traversal options of the camera batch")
     ap.add_argument("--incoherent", default="postponed_late16_reorder1_block64", choices=names,
                     help="traversal options of the incoherent batch")
@@ -519,8 +520,8 @@ def main():
                             for vn, vt, n in tb["per_batch"]],
         "roofline": {"bound": "hbm", "achieved": round(tb["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(tb["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "trace call: k_trace (coherent batch); k_ray_count + scan + k_ray_scatter + "
-                               "k_trace_perm (incoherent batch)",
+                     "kernel": "trace call: k_trace packets over 8x8 pixel tiles (coherent batch); k_ray_count + "
+                               "scan + k_ray_scatter + k_trace_perm with postponed leaf tests (incoherent batch)",
                      "bytes_per_launch": tb["per_launch_bytes"],
                      "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4),
                      "launch_ms_by_batch": [round(float(x), 4) for x in tb["kern_ms"].mean(0)]},
