@@ -325,6 +325,33 @@ struct Walker {
     __device__ __forceinline__ float t_hit() const { return best >= 0 ? tbest : __builtin_inff(); }
 };
 
+// Packet walk, for a wave whose lanes all walk one link set (nodes = that
+// set's node array, the same on every lane): the wave follows one node index,
+// taking the hit link when any lane's box test passes and the skip link
+// otherwise; at a leaf each lane whose own box test passes tests the
+// triangles.  The nodes a lane meets are a superset of those of its own walk
+// and its box tests use its own t_best, so its closest hit is unchanged.  The
+// node index, the link words and so every branch are uniform across the wave,
+// and all lanes read the same node and triangle records.
+template <bool kStats>
+__device__ __forceinline__ void walk_packet(Walker &w, const uint4 *__restrict__ nodes, uint32_t n,
+                                            const float4 *__restrict__ tris, TraceStats &st) {
+    uint32_t i = 0;
+    while (i < n) {
+        const uint4 q = nodes[i];
+        const uint32_t link = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.w);
+        const bool hit = w.box_hit(q);
+        if (kStats) st.boxes++;
+        if ((link >> 31) != 0u) {
+            if (hit) w.leaf_tris<kStats>(tris, link, st);
+            ++i;
+        } else {
+            i = __ballot(hit) != 0ull ? i + 1 : link;
+        }
+    }
+    w.i = n;
+}
+
 // Two rays per lane walked in lockstep: both node records are requested
 // before either box is tested, so each lane keeps two loads in flight.  A
 // walker that has finished re-reads node 0 of its link set (an in-bounds,

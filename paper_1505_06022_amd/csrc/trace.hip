@@ -19,32 +19,6 @@ constexpr uint32_t kNoRay = 0xffffffffu;
 // hit.
 enum { kWalkStep = 0, kWalkPaired = 1, kWalkPostponed = 2, kWalkTwo = 3, kWalkPacket = 4 };
 
-// Packet walk, for a wave whose lanes all walk one link set: the wave follows
-// one node index, taking the hit link when any lane's box test passes and the
-// skip link otherwise; at a leaf each lane whose own box test passes tests the
-// triangles.  The nodes a lane meets are a superset of those of its own walk
-// and its box tests use its own t_best, so its closest hit is unchanged.  The
-// node index, the link words and so every branch are uniform across the wave,
-// and all lanes read the same node and triangle records.
-template <bool kStats>
-__device__ __forceinline__ void walk_packet(pmd::Walker &w, const uint4 *__restrict__ nodes, uint32_t n,
-                                            const float4 *__restrict__ tris, pmd::TraceStats &st) {
-    uint32_t i = 0;
-    while (i < n) {
-        const uint4 q = nodes[i];
-        const uint32_t link = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.w);
-        const bool hit = w.box_hit(q);
-        if (kStats) st.boxes++;
-        if ((link >> 31) != 0u) {
-            if (hit) w.leaf_tris<kStats>(tris, link, st);
-            ++i;
-        } else {
-            i = __ballot(hit) != 0ull ? i + 1 : link;
-        }
-    }
-    w.i = n;
-}
-
 template <int kWalk, bool kStats>
 __device__ __forceinline__ void walk(pmd::Walker &w, const float4 *__restrict__ tris, uint32_t late,
                                      pmd::TraceStats &st) {
@@ -124,7 +98,7 @@ __device__ __forceinline__ void trace_slot(const pmd::Bvh &bvh, const float4 *__
             const int set = (int)((w.nodes - bvh.nodes) / bvh.n_nodes);
             const int set0 = __builtin_amdgcn_readfirstlane(set);
             if (__ballot(set != set0) == 0ull)  // one link set for the whole wave: its base is uniform
-                walk_packet<kStats>(w, bvh.nodes + (size_t)(uint32_t)set0 * bvh.n_nodes, bvh.n_nodes, bvh.tris, st);
+                pmd::walk_packet<kStats>(w, bvh.nodes + (size_t)(uint32_t)set0 * bvh.n_nodes, bvh.n_nodes, bvh.tris, st);
             else
                 walk<kWalkStep, kStats>(w, bvh.tris, late, st);  // link sets differ within the wave
         } else {
