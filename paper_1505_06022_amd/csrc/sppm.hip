@@ -260,6 +260,9 @@ void sppm_free(pm_sppm *s) {
                     s->sh_key, s->sh_surv};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    if (s->side) (void)hipStreamDestroy(s->side);
     if (s->own_bvh && s->bvh) {
         free_bvh(s->bvh);
         delete s->bvh;
@@ -385,6 +388,9 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     PM_HIPF(hipMalloc(&s->counters, sizeof(uint32_t) * 4));
     PM_HIPF(hipMalloc(&s->r2max, sizeof(unsigned long long)));
     if (own_grid) {
+        PM_HIPF(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+        PM_HIPF(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+        PM_HIPF(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
         PM_HIPF(hipMalloc(&s->cell_count, sizeof(uint32_t) * T));
         if (p->gather_mode == PM_GATHER_STOCHASTIC) {
             PM_HIPF(hipMalloc(&s->sh_key, sizeof(unsigned long long) * T));
@@ -536,15 +542,23 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
     for (int32_t it = 0; it < n_iter; ++it) {
         uint32_t k = (uint32_t)s->K;
         const SppmDev &d = s->dev;
-        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, k, 1);
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
+        // eye pass and R_max on the side stream, photon pass on the caller's:
+        // they share no data, and the eye pass's long specular paths would
+        // otherwise leave the device idle at its end
+        PM_HIP(hipEventRecord(s->ev_fork, st));
+        PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, k, 1);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d,
+                           (const double *)s->R2);
+        PM_HIP(hipEventRecord(s->ev_join, s->side));
         if (d.photon_kernel == PM_PHOTON_REGEN)
             hipLaunchKernelGGL(k_photon_regen, dim3(s->regen_grid), dim3(kBlock), 0, st, d, k);
         else
             hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
                                (double *)nullptr);
-        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, st, d, (const double *)s->R2);
+        PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         if (d.gather_mode == PM_GATHER_STOCHASTIC) {
             hipLaunchKernelGGL(k_sh_clear, dim3(std::min<uint32_t>(blocks_for(T), 4096u)), dim3(kBlock), 0, st, d, T);
             hipLaunchKernelGGL(k_sh_insert, dim3(ph_blocks), dim3(kBlock), 0, st, d, k, s->cell_count);

@@ -43,6 +43,10 @@ struct pm_sppm {
     uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
     double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
     uint64_t scene_hash = 0;      // fingerprint of the scene description (checkpoint matching)
+    // the eye pass runs beside the photon pass on a second stream (default
+    // priority), forked from and joined back to the caller's stream by events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     unsigned long long *sh_key = nullptr;  // stochastic hashing (gather_mode 1): [T] keys
     uint32_t *sh_surv = nullptr;           // and [T] survivors
 };
