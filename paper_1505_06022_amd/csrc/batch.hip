@@ -157,6 +157,8 @@ struct pm_batch {
     uint32_t total_buckets = 0;
     uint32_t grid[kNumStages] = {};
     hipStream_t cap_stream = nullptr;
+    hipStream_t side = nullptr;  // eye and r_max stages beside the photon stage (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<double> tune_ms;  // per candidate
@@ -221,12 +223,22 @@ int enqueue_iteration(const pm_batch *b, hipStream_t st) {
         if (b->block == 128) enqueue_stage<128>(b, s, bd, st);
         else enqueue_stage<256>(b, s, bd, st);
     };
+    auto stage_on = [&](int s, hipStream_t q) {
+        if (b->block == 128) enqueue_stage<128>(b, s, bd, q);
+        else enqueue_stage<256>(b, s, bd, q);
+    };
     hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(256), 0, st, bd);
-    stage(kStEye);
+    // eye and r_max stages on the side stream, photon stage on st: they share
+    // no data, and the photon stage fills the device while eye paths finish
+    PM_HIP(hipEventRecord(b->ev_fork, st));
+    PM_HIP(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+    stage_on(kStEye, b->side);
+    stage_on(kStRmax, b->side);
+    PM_HIP(hipEventRecord(b->ev_join, b->side));
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(b->total_buckets)), dim3(kBlock), 0, st, b->cell_count,
                        b->total_buckets, 0u);
     stage(kStPhoton);
-    stage(kStRmax);
+    PM_HIP(hipStreamWaitEvent(st, b->ev_join, 0));
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, st, bd, b->item_off);
     stage(kStCount);
     launch_bucket_scan(b->cell_count, b->cell_start, b->cell_fill, b->bsum, b->total_buckets, st);
@@ -411,6 +423,9 @@ void batch_free(pm_batch *b) {
         if (p) (void)hipFree(p);
     for (pm_sppm *m : b->members) sppm_free(m);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
 }
 
@@ -475,6 +490,9 @@ int batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const 
     PM_HIPB(hipMemsetAsync(b->iter, 0, sizeof(uint32_t), st));
     PM_HIPB(hipStreamSynchronize(st));
     PM_HIPB(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    PM_HIPB(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+    PM_HIPB(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    PM_HIPB(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
 #undef PM_HIPB
     uint32_t chunk = 1024;
     int32_t block = 256;

@@ -621,12 +621,17 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
                        (int64_t)s->n_mat + 1);
     for (int32_t k = 0; k < s->K; ++k) {
         const double *R2k = s->R2_hist + (size_t)k * s->P;
-        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, (uint32_t)k, 0);
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
+        // replayed eye pass and R_max beside the replayed photon pass, as in the forward iteration
+        PM_HIP(hipEventRecord(s->ev_fork, st));
+        PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, (uint32_t)k, 0);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d, R2k);
+        PM_HIP(hipEventRecord(s->ev_join, s->side));
         hipLaunchKernelGGL(k_photon<true>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, (uint32_t)k, s->mat_tab,
                            s->adj_tab);
-        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, st, d, R2k);
+        PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
         launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
         hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_fill, s->sorted);
