@@ -266,7 +266,11 @@ PM_API int pm_sppm_destroy(pm_sppm *s);
 
 /* Enqueue n_iter iterations (eye pass, photon pass, hashed-grid build,
  * range query, progressive update).  Counts stay on the device; a photon
- * store overflow sets a sticky device flag reported by pm_sppm_status. */
+ * store overflow sets a sticky device flag reported by pm_sppm_status.
+ * Within an iteration the eye pass runs on a stream the handle owns, forked
+ * from `stream` and joined back to it by events before the range query, so
+ * everything enqueued later on `stream` sees the finished iteration (and the
+ * sequence can be captured into a graph from `stream`). */
 PM_API int pm_sppm_iterate(pm_sppm *s, int32_t n_iter, void *stream);
 
 /* Radiance estimate of the iterations so far into `image` (device, float32
