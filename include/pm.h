@@ -269,8 +269,7 @@ PM_API int pm_sppm_destroy(pm_sppm *s);
  * store overflow sets a sticky device flag reported by pm_sppm_status.
  * Within an iteration the eye pass runs on a stream the handle owns, forked
  * from `stream` and joined back to it by events before the range query, so
- * everything enqueued later on `stream` sees the finished iteration (and the
- * sequence can be captured into a graph from `stream`). */
+ * everything enqueued later on `stream` sees the finished iteration. */
 PM_API int pm_sppm_iterate(pm_sppm *s, int32_t n_iter, void *stream);
 
 /* Radiance estimate of the iterations so far into `image` (device, float32
