@@ -57,7 +57,12 @@ KERNEL_VARIANTS = (
     ("per_ray_tiles_block64", dict(kernel=1, block=64, tile_width="image")),
     ("packet_block64", dict(kernel=6, block=64)), ("packet_tiles", dict(kernel=6, tile_width="image")),
     ("packet_tiles_block64", dict(kernel=6, block=64, tile_width="image")),
-    ("packet_reorder1_block64", dict(kernel=6, block=64, reorder=1)))
+    ("packet_reorder1_block64", dict(kernel=6, block=64, reorder=1)),
+    ("postponed_late8_reorder1_block64", dict(kernel=4, refill=8, reorder=1, block=64)),
+    ("postponed_late24_reorder1_block64", dict(kernel=4, refill=24, reorder=1, block=64)),
+    ("postponed_late32_reorder1_block64", dict(kernel=4, refill=32, reorder=1, block=64)),
+    ("postponed_late16_reorder2_block64", dict(kernel=4, refill=16, reorder=2, block=64)),
+    ("postponed_late16_reorder1_block128", dict(kernel=4, refill=16, reorder=1, block=128)))
 
 IMAGE_WIDTH = 1920   # of the camera batch
 
