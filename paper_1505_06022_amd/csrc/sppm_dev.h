@@ -351,12 +351,31 @@ __device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const 
     int32_t bx = (int32_t)floorf((hx.x - gr.lo[0]) * gr.inv_h - 0.5f);
     int32_t by = (int32_t)floorf((hx.y - gr.lo[1]) * gr.inv_h - 0.5f);
     int32_t bz = (int32_t)floorf((hx.z - gr.lo[2]) * gr.inv_h - 0.5f);
+    // A hit point whose radius is below R_max may have its disc inside one of
+    // the two cells along an axis; the other is then skipped.  In cell units:
+    // the disc spans cx -/+ rr, widened by a slack far above the rounding of
+    // the cell coordinates, so no cell holding a photon of the disc is skipped.
+    uint32_t need = 0;  // bit 2a: lower cell along axis a, bit 2a+1: upper cell
+    {
+        const float cc[3] = {(hx.x - gr.lo[0]) * gr.inv_h, (hx.y - gr.lo[1]) * gr.inv_h, (hx.z - gr.lo[2]) * gr.inv_h};
+        const int32_t bb[3] = {bx, by, bz};
+        const float rc = (float)sqrt(r2) * gr.inv_h;
+        for (int a = 0; a < 3; ++a) {
+            const float rr = rc * (1.0f + 0x1p-8f) + (fabsf(cc[a]) + 1.0f) * 0x1p-16f;
+            const float mid = (float)(bb[a] + 1);
+            if (cc[a] - rr < mid) need |= 1u << (2 * a);
+            if (cc[a] + rr >= mid) need |= 2u << (2 * a);
+        }
+    }
     uint32_t seen[8];
     for (int c = 0; c < 8; ++c) {
-        uint32_t hb = cell_hash(bx + (c & 1), by + ((c >> 1) & 1), bz + (c >> 2), gr.mask);
+        const bool used = ((need >> ((c & 1) ? 1 : 0)) & 1u) && ((need >> (((c >> 1) & 1) ? 3 : 2)) & 1u) &&
+                          ((need >> ((c >> 2) ? 5 : 4)) & 1u);
+        uint32_t hb = used ? cell_hash(bx + (c & 1), by + ((c >> 1) & 1), bz + (c >> 2), gr.mask) : 0xffffffffu;
+        seen[c] = hb;
+        if (!used) continue;
         bool dup = false;
         for (int e = 0; e < c; ++e) dup |= (seen[e] == hb);
-        seen[c] = hb;
         if (dup) continue;
         uint32_t q0 = start[d.table_off + hb], q1 = start[d.table_off + hb + 1];
         for (uint32_t q = q0; q < q1; ++q) {
