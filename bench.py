@@ -295,8 +295,14 @@ def sppm_bench(args, torch, api, scenes):
     variants, tbvh = {}, {}
     runs = [("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
             ("regen_refill16", dict(photon_kernel=2, refill=16)), ("regen_refill32", dict(photon_kernel=2, refill=32))]
+    # the paper's own schedule: one bounce per thread per launch (threads = pixels, then fixed pools)
+    P = sc.camera.width * sc.camera.height
+    runs += [("passes_threads_per_pixel", dict(photon_kernel=3)),
+             ("passes_threads_2^18", dict(photon_kernel=3, pass_threads=1 << 18)),
+             ("passes_threads_2^20_passes_24", dict(photon_kernel=3, pass_threads=1 << 20, passes=24))]
     # the paper's TBVH comparison: every ray walks one link set (a single threaded BVH)
     runs += [(f"single_link_set_{k}", dict(single_link_set=k + 1)) for k in range(6)]
+    schedule = {}
     for name, kw in runs:
         sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, **kw), bvh=bvh)
         sv.iterate(1)
@@ -306,6 +312,10 @@ def sppm_bench(args, torch, api, scenes):
         e1.record(st)
         torch.cuda.synchronize()
         (tbvh if name.startswith("single") else variants)[name] = round(e0.elapsed_time(e1) / 3, 3)
+        if kw.get("photon_kernel") == 3:
+            S = kw.get("pass_threads") or min(P, 1 << 26)
+            schedule[name] = {"threads": S, "passes": kw.get("passes") or -(-Np // S) + 8,
+                              "paths_left_to_drain": int(sv.views()["photon_count"][3].item())}
         sv.destroy()
     # stochastic spatial hashing (Sec. 3.4) against the exact gather: time per
     # iteration, and RMSE after 8 iterations against a 64-iteration exact render
@@ -328,7 +338,7 @@ def sppm_bench(args, torch, api, scenes):
         sv.destroy()
     bvh.destroy()
     return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
-                tbvh=tbvh, stochastic_hashing=sh,
+                tbvh=tbvh, stochastic_hashing=sh, pass_schedule=schedule,
                 workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
@@ -539,6 +549,7 @@ def main():
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
                        "stored_photons": sp["n_stored"], "workload": sp["workload"],
                        "iteration_ms_by_photon_kernel": sp["variants"],
+                       "one_bounce_per_pass_schedule": sp["pass_schedule"],
                        "gather_exact_vs_stochastic_hashing": sp["stochastic_hashing"],
                        "tbvh_ablation": {"iteration_ms_single_link_set": sp["tbvh"],
                                          "mean_ratio_tbvh_over_mtbvh": round(

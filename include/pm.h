@@ -239,6 +239,14 @@ typedef struct {
                                  threaded BVH (the paper's TBVH comparison).
                                  Results are identical; only speed differs. */
     int32_t gather_mode;      /* PM_GATHER_*: the range query's estimator */
+    int32_t pass_threads;     /* PM_PHOTON_PASSES: threads (path slots) per
+                                 pass, 1..2^26; 0 = one per pixel, capped at
+                                 2^26 (the paper's setting).  Must be 0 for
+                                 the other photon kernels. */
+    int32_t passes;           /* PM_PHOTON_PASSES: one-bounce passes per
+                                 iteration, 1..1024; 0 = ceil(n_photons /
+                                 threads) + 8.  Must be 0 for the other
+                                 photon kernels. */
 } pm_sppm_params;
 
 /* Range query.  EXACT: every photon inside a hit point's disc, found through
@@ -254,9 +262,17 @@ typedef struct {
 enum { PM_GATHER_EXACT = 0, PM_GATHER_STOCHASTIC = 1 };
 
 /* Photon pass scheduling (results are identical): one lane traces one whole
- * path, or persistent lanes trace one bounce per step and switch to a new path
- * when theirs ends (the paper's photon path regeneration, Sec. 3.3). */
-enum { PM_PHOTON_AUTO = 0, PM_PHOTON_PER_PATH = 1, PM_PHOTON_REGEN = 2 };
+ * path (PER_PATH); persistent lanes trace one bounce per step and switch to a
+ * new path as soon as theirs ends (REGEN, the paper's photon path
+ * regeneration of Sec. 3.3 inside one launch); or the paper's schedule as
+ * written (PASSES): each launch is one pass in which every thread moves its
+ * path by one bounce, so it stores at most one photon, and a thread whose
+ * path was killed or left the scene starts the next path in the following
+ * pass.  Path state stays in device memory between passes (56 B per thread).
+ * The passes are enqueued without any host synchronisation, so their number
+ * is fixed in advance (`passes`); one last launch finishes whatever paths the
+ * passes left (views: photon_count[3] counts them). */
+enum { PM_PHOTON_AUTO = 0, PM_PHOTON_PER_PATH = 1, PM_PHOTON_REGEN = 2, PM_PHOTON_PASSES = 3 };
 
 /* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)
  * and allocates the per-pixel state (N = 0, R^2 = r0^2, tau = 0, D = 0).
@@ -332,7 +348,10 @@ typedef struct {
     float *hp_pos;            /* [n_pixels][4]: x, y, z, W*rho/pi */
     float *hp_nrm;            /* [n_pixels][4]: n (toward the eye), int bits: material or -1 */
     float *photons;           /* [capacity][8]: x, y, z, phi, w.xyz, bits: path << 5 | bounce */
-    uint32_t *photon_count;   /* [1] photons stored in the last iteration */
+    uint32_t *photon_count;   /* [4]: photons stored in the last iteration,
+                                 overflow flag (sticky), paths handed out,
+                                 and (PM_PHOTON_PASSES) paths the passes left
+                                 unfinished or unstarted */
     uint32_t *gather_M;       /* [n_pixels] photons found in the last iteration */
     uint64_t *gather_Phi;     /* [n_pixels] their fixed-point flux */
 } pm_sppm_views;
@@ -365,7 +384,9 @@ typedef struct {
 /* Create a batch of SPPM renderers (one per scene; descs[i]/params[i] as for
  * pm_sppm_create, record_iterations ignored).  Every stage of an iteration is
  * one persistent launch for all scenes: workgroups take (scene, chunk) items
- * from a device work counter.  The library owns all device buffers. */
+ * from a device work counter.  The library owns all device buffers.  Every
+ * scene must use the exact gather and photon_kernel 0, 1 or 2 (the batch
+ * schedules its own photon stage). */
 PM_API int pm_batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
                            const pm_batch_opts *opts, void *stream, pm_batch **out);
 PM_API int pm_batch_destroy(pm_batch *b);

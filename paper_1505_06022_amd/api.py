@@ -68,10 +68,10 @@ class SppmParams(C.Structure):
                 ("seed", C.c_uint64), ("max_eye_depth", C.c_int32), ("max_photon_bounces", C.c_int32),
                 ("fixed_shift", C.c_int32), ("store_factor", C.c_int32), ("record_iterations", C.c_int32),
                 ("photon_kernel", C.c_int32), ("refill", C.c_int32), ("single_link_set", C.c_int32),
-                ("gather_mode", C.c_int32)]
+                ("gather_mode", C.c_int32), ("pass_threads", C.c_int32), ("passes", C.c_int32)]
 
 
-PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN = 0, 1, 2
+PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN, PHOTON_PASSES = 0, 1, 2, 3
 GATHER_EXACT, GATHER_STOCHASTIC = 0, 1
 
 
@@ -272,7 +272,7 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
 # ---------------------------------------------------------------------------
 def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, max_photon_bounces=32,
                 fixed_shift=40, store_factor=8, record_iterations=0, photon_kernel=0, refill=0,
-                single_link_set=0, gather_mode=0) -> SppmParams:
+                single_link_set=0, gather_mode=0, pass_threads=0, passes=0) -> SppmParams:
     p = SppmParams()
     p.size = C.sizeof(SppmParams)
     p.n_photons, p.alpha, p.r0, p.seed = n_photons, alpha, float(r0), seed
@@ -282,6 +282,7 @@ def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, ma
     p.photon_kernel, p.refill = photon_kernel, refill
     p.single_link_set = single_link_set
     p.gather_mode = gather_mode
+    p.pass_threads, p.passes = pass_threads, passes
     return p
 
 

@@ -31,6 +31,21 @@ __global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint8_
 // Persistent photon lanes with path regeneration.
 __global__ __launch_bounds__(kBlock) void k_photon_regen(SppmDev d, uint32_t k) { photon_regen_loop(d, k, d.refill); }
 
+// One pass of the one-bounce-per-pass schedule; the grid covers the slots
+// with the same workgroup-to-slot map in every pass.
+__global__ __launch_bounds__(kBlock) void k_photon_pass(SppmDev d, uint32_t k, PassSlots ps) {
+    photon_pass_elem(d, k, ps, xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
+}
+
+// Paths no pass started, before the drain adds the paths still in flight.
+__global__ void k_pass_tally(SppmDev d) {
+    if (threadIdx.x == 0) d.counters[3] = d.n_paths - min(d.counters[2], d.n_paths);
+}
+
+__global__ __launch_bounds__(kBlock) void k_photon_drain(SppmDev d, uint32_t k, PassSlots ps) {
+    photon_drain_elem(d, k, ps, xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
+}
+
 // Frame setup: clear the photon and path counters and the R_max accumulator.
 __global__ void k_begin(SppmDev d) {
     if (threadIdx.x == 0) {
@@ -257,7 +272,7 @@ void sppm_free(pm_sppm *s) {
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
                     s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
-                    s->sh_key, s->sh_surv};
+                    s->sh_key, s->sh_surv, s->slot_mem};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
@@ -301,8 +316,12 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->store_factor < 1 || p->n_photons * p->store_factor > (int64_t(1) << 30))
         return set_error("store_factor must be >= 1 and the store below 2^30 photons"), PM_ERR_ARG;
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
-    if (p->photon_kernel < 0 || p->photon_kernel > 2 || p->refill < 0 || p->refill > 64)
-        return set_error("photon_kernel must be 0..2 and refill 0..64"), PM_ERR_ARG;
+    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_PASSES || p->refill < 0 || p->refill > 64)
+        return set_error("photon_kernel must be 0..3 and refill 0..64"), PM_ERR_ARG;
+    if (p->pass_threads < 0 || p->pass_threads > (1 << 26) || p->passes < 0 || p->passes > 1024)
+        return set_error("pass_threads must be in [0, 2^26] and passes in [0, 1024]"), PM_ERR_ARG;
+    if (p->photon_kernel != PM_PHOTON_PASSES && (p->pass_threads != 0 || p->passes != 0))
+        return set_error("pass_threads and passes apply to photon_kernel PM_PHOTON_PASSES only"), PM_ERR_ARG;
     if (p->gather_mode != PM_GATHER_EXACT && p->gather_mode != PM_GATHER_STOCHASTIC)
         return set_error("gather_mode must be PM_GATHER_EXACT or PM_GATHER_STOCHASTIC"), PM_ERR_ARG;
     if (p->gather_mode == PM_GATHER_STOCHASTIC && p->record_iterations > 0)
@@ -404,6 +423,20 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     }
     PM_HIPF(hipMalloc(&s->M, sizeof(uint32_t) * s->P));
     PM_HIPF(hipMalloc(&s->Phi, sizeof(unsigned long long) * s->P));
+    if (p->photon_kernel == PM_PHOTON_PASSES) {
+        // one slot per thread of a pass; the paper runs one thread per pixel
+        const uint32_t S = p->pass_threads > 0 ? (uint32_t)p->pass_threads
+                                               : (uint32_t)std::min<int64_t>(s->P, int64_t(1) << 26);
+        PM_HIPF(hipMalloc(&s->slot_mem, (size_t)56 * S));
+        char *m = (char *)s->slot_mem;
+        s->slots.g = (int4 *)m;
+        s->slots.o = (float4 *)(m + (size_t)16 * S);
+        s->slots.w = (float4 *)(m + (size_t)32 * S);
+        s->slots.nb = (uint2 *)(m + (size_t)48 * S);
+        s->slots.S = S;
+        const int64_t auto_pass = (p->n_photons + S - 1) / S + 8;
+        s->n_pass = p->passes > 0 ? p->passes : (int32_t)std::min<int64_t>(auto_pass, 1024);
+    }
     s->n_mat = nm;
     s->rho_host.assign(d->mat_rho, d->mat_rho + nm);
     s->rec_iters = p->record_iterations;
@@ -483,7 +516,9 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.P = s->P;
     dv.mask = T - 1u;
     dv.table_off = 0;
-    dv.photon_kernel = p->photon_kernel == PM_PHOTON_PER_PATH ? PM_PHOTON_PER_PATH : PM_PHOTON_REGEN;
+    dv.photon_kernel = (p->photon_kernel == PM_PHOTON_PER_PATH || p->photon_kernel == PM_PHOTON_PASSES)
+                           ? p->photon_kernel
+                           : PM_PHOTON_REGEN;
     dv.refill = p->refill > 0 ? (uint32_t)p->refill : 16u;
     dv.force_set = p->single_link_set - 1;
     dv.gather_mode = p->gather_mode;
@@ -553,9 +588,17 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
         hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d,
                            (const double *)s->R2);
         PM_HIP(hipEventRecord(s->ev_join, s->side));
-        if (d.photon_kernel == PM_PHOTON_REGEN)
+        if (d.photon_kernel == PM_PHOTON_REGEN) {
             hipLaunchKernelGGL(k_photon_regen, dim3(s->regen_grid), dim3(kBlock), 0, st, d, k);
-        else
+        } else if (d.photon_kernel == PM_PHOTON_PASSES) {
+            const PassSlots &ps = s->slots;
+            hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)ps.S)), dim3(kBlock), 0, st,
+                               (uint32_t *)ps.nb, 2u * ps.S, kSlotIdle);
+            for (int32_t j = 0; j < s->n_pass; ++j)
+                hipLaunchKernelGGL(k_photon_pass, dim3(blocks_for(ps.S)), dim3(kBlock), 0, st, d, k, ps);
+            hipLaunchKernelGGL(k_pass_tally, dim3(1), dim3(64), 0, st, d);
+            hipLaunchKernelGGL(k_photon_drain, dim3(blocks_for(ps.S)), dim3(kBlock), 0, st, d, k, ps);
+        } else
             hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
                                (double *)nullptr);
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));

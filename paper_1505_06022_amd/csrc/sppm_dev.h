@@ -274,6 +274,85 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
 }
 
 // ---------------------------------------------------------------------------
+// Photon paths one bounce per pass (Sec. 3.3 as the paper schedules it): a
+// fixed pool of threads, each owning one slot; every launch (a pass) moves the
+// path of each slot by exactly one bounce, so a thread stores at most one
+// photon per pass.  A slot whose path was killed or left the scene takes the
+// next path index in the following pass and traces that path's first segment
+// there.  A slot's path state lives in memory between passes.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSlotIdle = 0xffffffffu;
+
+struct PassSlots {
+    int4 *g;     // [S] random stream state
+    float4 *o;   // [S] origin, flux
+    float4 *w;   // [S] direction, excluded triangle (int bits)
+    uint2 *nb;   // [S] path index (kSlotIdle: none), next bounce
+    uint32_t S;
+};
+
+__device__ __forceinline__ bool slot_load(const PassSlots &ps, uint32_t s, PhotonPath &P) {
+    const uint2 nb = ps.nb[s];
+    if (nb.x == kSlotIdle) return false;
+    const int4 g = ps.g[s];
+    const float4 o = ps.o[s], w = ps.w[s];
+    P.g = Rng{g.x, g.y, g.z, g.w};
+    P.org = v3(o.x, o.y, o.z);
+    P.phi = o.w;
+    P.dir = v3(w.x, w.y, w.z);
+    P.excl = __float_as_int(w.w);
+    P.n = nb.x;
+    P.b = (int32_t)nb.y;
+    P.last = -1;
+    return true;
+}
+
+__device__ __forceinline__ void slot_store(const PassSlots &ps, uint32_t s, const PhotonPath &P, bool live) {
+    if (live) {
+        ps.g[s] = make_int4(P.g.s0, P.g.s1, P.g.s2, P.g.s3);
+        ps.o[s] = make_float4(P.org.x, P.org.y, P.org.z, P.phi);
+        ps.w[s] = make_float4(P.dir.x, P.dir.y, P.dir.z, __int_as_float(P.excl));
+        ps.nb[s] = make_uint2(P.n, (uint32_t)P.b);
+    } else {
+        ps.nb[s] = make_uint2(kSlotIdle, 0u);
+    }
+}
+
+// The path counter as one value for the whole wave (it only grows).
+__device__ __forceinline__ uint32_t paths_handed_out(const SppmDev &d) {
+    const uint32_t c = __hip_atomic_load(&d.counters[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+}
+
+// One pass of slot s.  Called by every lane of a wave; lanes with s >= S
+// only take part in the wave's votes.
+__device__ __forceinline__ void photon_pass_elem(const SppmDev &d, uint32_t k, const PassSlots &ps, uint32_t s) {
+    const bool in = s < ps.S;
+    PhotonPath P;
+    const bool was_live = in && slot_load(ps, s, P);
+    bool live = was_live;
+    const bool want = in && !was_live;
+    const uint64_t want_mask = __ballot(want);
+    if (want_mask != 0ull && paths_handed_out(d) < d.n_paths) {
+        const uint32_t n = wave_fetch_add(&d.counters[2], want_mask, want);
+        if (want && n < d.n_paths) live = photon_emit(d, k, n, P);
+    }
+    if (live) live = photon_bounce<false>(d, P, nullptr, nullptr);
+    if (in && (live || was_live)) slot_store(ps, s, P, live);
+}
+
+// After the last pass: the paths still in flight are traced to their end and
+// the paths no pass started are taken by regenerating lanes.  Called by every
+// lane of a wave.
+__device__ __forceinline__ void photon_drain_elem(const SppmDev &d, uint32_t k, const PassSlots &ps, uint32_t s) {
+    PhotonPath P;
+    bool live = s < ps.S && slot_load(ps, s, P);
+    if (live) wave_append(&d.counters[3]);
+    while (live) live = photon_bounce<false>(d, P, nullptr, nullptr);
+    if (paths_handed_out(d) < d.n_paths) photon_regen_loop(d, k, d.refill);
+}
+
+// ---------------------------------------------------------------------------
 // Hashed grid (exact): cell edge h = 2 R_max (1 + 2^-10), so the 2x2x2 cells
 // around a hit point cover its disc; cells hash (Teschner et al. 2003) into a
 // power-of-two table; photons are counting-sorted by bucket.

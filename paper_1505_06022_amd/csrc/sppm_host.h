@@ -49,6 +49,11 @@ struct pm_sppm {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     unsigned long long *sh_key = nullptr;  // stochastic hashing (gather_mode 1): [T] keys
     uint32_t *sh_surv = nullptr;           // and [T] survivors
+    // one-bounce-per-pass photon schedule (PM_PHOTON_PASSES): path slots and
+    // the number of passes enqueued per iteration before the drain
+    void *slot_mem = nullptr;
+    pmd::PassSlots slots{};
+    int32_t n_pass = 0;
 };
 
 namespace pm {

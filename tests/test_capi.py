@@ -67,6 +67,23 @@ def test_host_validation_errors_without_gpu():
     p = api.sppm_params(1024, alpha=1.5)
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
     assert b"alpha" in L.pm_last_error()
+    # the one-bounce-per-pass photon schedule and its two knobs
+    for bad in (dict(photon_kernel=4), dict(photon_kernel=-1)):
+        p = api.sppm_params(1024, **bad)
+        assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+        assert b"photon_kernel" in L.pm_last_error()
+    for bad in (dict(photon_kernel=api.PHOTON_PASSES, pass_threads=-1),
+                dict(photon_kernel=api.PHOTON_PASSES, pass_threads=(1 << 26) + 1),
+                dict(photon_kernel=api.PHOTON_PASSES, passes=1025),
+                dict(photon_kernel=api.PHOTON_PASSES, passes=-2)):
+        p = api.sppm_params(1024, **bad)
+        assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+        assert b"pass_threads" in L.pm_last_error()
+    for kern in (api.PHOTON_AUTO, api.PHOTON_PER_PATH, api.PHOTON_REGEN):
+        for knob in (dict(pass_threads=64), dict(passes=4)):
+            p = api.sppm_params(1024, photon_kernel=kern, **knob)
+            assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+            assert b"PM_PHOTON_PASSES only" in L.pm_last_error()
     sc.tri_mat[3] = 99
     args = api._SceneArgs(sc)
     p = api.sppm_params(1024)

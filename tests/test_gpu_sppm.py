@@ -128,6 +128,31 @@ def test_photon_kernels_parity(torch_cuda, oracle_lib, photon_kernel, refill):
                 photon_kernel=photon_kernel, refill=refill)
 
 
+@pytest.mark.parametrize("pass_threads,passes", [(0, 0), (100, 3), (1 << 16, 1), (4096, 64), (1 << 14, 32)])
+def test_one_bounce_per_pass_parity(torch_cuda, oracle_lib, pass_threads, passes):
+    """The paper's schedule as written (one bounce per thread per launch, a new
+    path in the pass after one ends) stores the same photons as the other
+    schedules, whatever the thread count and however many paths the passes
+    leave to the final drain."""
+    _log(f"case: one bounce per pass, threads {pass_threads} passes {passes}")
+    sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
+    Np = 3 * (1 << 12) + 5
+    _run_parity(torch_cuda, oracle_lib, sc, Np, 2, 0.02, seed=8, stage_iters=2,
+                photon_kernel=api.PHOTON_PASSES, pass_threads=pass_threads, passes=passes)
+    # photon_count[3]: paths the passes left unfinished or unstarted
+    s = api.Sppm(sc, api.sppm_params(Np, r0=0.02, seed=8, photon_kernel=api.PHOTON_PASSES,
+                                     pass_threads=pass_threads, passes=passes))
+    s.iterate(1)
+    torch_cuda.cuda.synchronize()
+    left = int(s.views()["photon_count"][3])
+    if pass_threads >= Np and passes >= 32:
+        assert left == 0      # every path starts in the first pass and has at most 32 bounces
+    elif pass_threads == 100:
+        assert left >= Np - 3 * 100
+    assert 0 <= left <= Np
+    s.destroy()
+
+
 @pytest.mark.parametrize("single_link_set", [1, 4, 6])
 def test_single_link_set_parity(torch_cuda, oracle_lib, single_link_set):
     """Every ray walking one link set (a single threaded BVH) changes nothing
@@ -284,4 +309,8 @@ def test_stochastic_hashing_is_refused_where_unsupported(torch_cuda):
     sc = scenes.box_scene(8, 8)
     with pytest.raises(api.PMError) as e:
         api.Batch([sc, sc], [api.sppm_params(256, r0=0.1), api.sppm_params(256, r0=0.1, gather_mode=1)])
+    assert e.value.code == api.PM_ERR_ARG
+    _log("case: one-bounce-per-pass photons in a batch")
+    with pytest.raises(api.PMError) as e:
+        api.Batch([sc, sc], [api.sppm_params(256, r0=0.1), api.sppm_params(256, r0=0.1, photon_kernel=3)])
     assert e.value.code == api.PM_ERR_ARG
