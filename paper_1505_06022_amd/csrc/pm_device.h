@@ -286,10 +286,17 @@ struct Walker {
     // least one lane holds one); then every lane that holds a leaf tests its
     // triangles, all lanes together.  A lane that holds a leaf keeps visiting
     // boxes while others search and halts in front of its next leaf hit, which
-    // it visits again after the tests.  Each box iteration advances every
-    // searching lane, so the walk ends.  The closest hit under the lower-index
-    // tie rule does not depend on the order of the visits: the result is the
-    // one of step().
+    // it visits again after the tests.  The wave votes once per
+    // kPostponedSteps box visits (fewer ballots and branches per visit; an
+    // idle lane just waits a few steps longer).  Each round of visits advances
+    // every searching lane, so the walk ends.  The closest hit under the
+    // lower-index tie rule does not depend on the order of the visits: the
+    // result is the one of step().
+#ifndef PM_POSTPONED_STEPS
+#define PM_POSTPONED_STEPS 8
+#endif
+    static constexpr int kPostponedSteps = PM_POSTPONED_STEPS;
+
     template <bool kStats>
     __device__ __forceinline__ void walk_postponed(const float4 *__restrict__ tris, uint32_t late, TraceStats &st) {
         uint32_t held = 0u;  // link word of a leaf hit not yet tested, or 0
@@ -299,19 +306,16 @@ struct Walker {
                 const uint64_t searching = __ballot(i < n && held == 0u);
                 if (searching == 0ull) break;
                 if ((uint32_t)__popcll(searching) <= late && __ballot(held != 0u) != 0ull) break;
-                if (i < n && !halted) {
-                    uint4 q = nodes[i];
-                    if (kStats) st.boxes++;
-                    const bool leaf = (q.w >> 31) != 0u, hit = box_hit(q);
-                    if (hit && leaf) {
-                        if (held == 0u) {
-                            held = q.w;
-                            ++i;
-                        } else {
-                            halted = true;
-                        }
-                    } else {
-                        i = (hit || leaf) ? i + 1 : q.w;
+#pragma unroll
+                for (int u = 0; u < kPostponedSteps; ++u) {
+                    if (i < n && !halted) {
+                        const uint4 q = nodes[i];
+                        if (kStats) st.boxes++;
+                        const bool leaf = (q.w >> 31) != 0u, hit = box_hit(q);
+                        const bool leaf_hit = hit && leaf;
+                        halted = leaf_hit && held != 0u;
+                        held = (leaf_hit && held == 0u) ? q.w : held;
+                        i = halted ? i : ((hit || leaf) ? i + 1 : q.w);
                     }
                 }
             }

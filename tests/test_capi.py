@@ -164,10 +164,11 @@ def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, s
                 assert np.float32(t) == t_ref[r]
 
 
-def _py_wave_postponed(nodes, tris, info, rays, s, late):
+def _py_wave_postponed(nodes, tris, info, rays, s, late, steps=1):
     """Lockstep model of one wavefront running the postponed-leaf walk: box
     visits until at most `late` lanes still search (and one lane holds a leaf),
-    then every held leaf is tested; a holding lane halts at its next leaf hit."""
+    then every held leaf is tested; a holding lane halts at its next leaf hit.
+    The wave votes once per `steps` box visits."""
     lo, hi, leaf, first, cnt, skip = decode(nodes[s], info)
     tf = f32(tris)
     L, n = len(rays), nodes.shape[1]
@@ -198,18 +199,19 @@ def _py_wave_postponed(nodes, tris, info, rays, s, late):
                 break
             visits += 1
             assert visits < 64 * n, "box loop does not end"
-            for r in range(L):
-                if i[r] >= n or halted[r]:
-                    continue
-                k = i[r]
-                hit = box_hit(r, k)
-                if hit and leaf[k]:
-                    if held[r] < 0:
-                        held[r], i[r] = k, k + 1
+            for _ in range(steps):
+                for r in range(L):
+                    if i[r] >= n or halted[r]:
+                        continue
+                    k = i[r]
+                    hit = box_hit(r, k)
+                    if hit and leaf[k]:
+                        if held[r] < 0:
+                            held[r], i[r] = k, k + 1
+                        else:
+                            halted[r] = True
                     else:
-                        halted[r] = True
-                else:
-                    i[r] = k + 1 if (hit or leaf[k]) else skip[k]
+                        i[r] = k + 1 if (hit or leaf[k]) else skip[k]
         if not (held >= 0).any():
             break
         for r in np.nonzero(held >= 0)[0]:
@@ -224,16 +226,17 @@ def _py_wave_postponed(nodes, tris, info, rays, s, late):
     return best, tb
 
 
-@pytest.mark.parametrize("late", [0, 5, 63])
-def test_postponed_leaf_walk_model_matches_brute_force(oracle_lib, late):
+@pytest.mark.parametrize("late,steps", [(0, 1), (5, 1), (63, 1), (16, 8), (0, 8), (63, 3)])
+def test_postponed_leaf_walk_model_matches_brute_force(oracle_lib, late, steps):
     """The wave schedule of the postponed traversal kernel, modelled on the
-    CPU: it ends, and every lane's closest hit equals brute force."""
+    CPU: it ends, and every lane's closest hit equals brute force, whether
+    the wave votes after every box visit or after several."""
     sc = scenes.small_soup(300, 4, spread=0.4 / np.cbrt(300))
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
     rays = scenes.random_rays(64, 4)
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
     for s in (0, 3):
-        h, t = _py_wave_postponed(nodes, tris, info, rays, s, late)
+        h, t = _py_wave_postponed(nodes, tris, info, rays, s, late, steps)
         assert np.array_equal(h, h_ref)
         assert np.array_equal(np.float32(t[h >= 0]), t_ref[h >= 0])
 
