@@ -115,8 +115,9 @@ PM_API int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t
  * call with nodes == tris == NULL to learn *n_nodes; then call again with
  *   nodes  host, [6][n_nodes][4] 32-bit words per link set s (0:+x 1:-x 2:+y
  *          3:-y 4:+z 5:-z), node i in that set's preorder: its padded box
- *          rounded outward to 16-bit grid coordinates (lo.x | lo.y << 16,
- *          lo.z | hi.x << 16, hi.y | hi.z << 16; see info->grid_*), then the
+ *          rounded outward to 16-bit grid coordinates, one word per axis
+ *          (lo.x | hi.x << 16, lo.y | hi.y << 16, lo.z | hi.z << 16; see
+ *          info->grid_*), then the
  *          link word: an inner node stores its skip link (preorder index after
  *          its subtree, n_nodes at the end; its hit link is i + 1); a leaf has
  *          bit 31 set and first_tri << 3 | count (both of its links are i + 1)

@@ -295,9 +295,7 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
             lo3[a] = q_down(a, (double)bx.lo[a] - pad);
             hi3[a] = q_up(a, (double)bx.hi[a] + pad);
         }
-        qbox[3 * v] = lo3[0] | (lo3[1] << 16);
-        qbox[3 * v + 1] = lo3[2] | (hi3[0] << 16);
-        qbox[3 * v + 2] = hi3[1] | (hi3[2] << 16);
+        for (int a = 0; a < 3; ++a) qbox[3 * v + a] = lo3[a] | (hi3[a] << 16);
     }
     out.nodes.assign((size_t)kLinkSets * nn * kNodeWords, 0u);
     auto thread_set = [&](int s) {

@@ -295,9 +295,9 @@ __global__ __launch_bounds__(kLb) void k_lb_thread(int n, int max_leaf, const in
         hi3[a] = lb_q_up(g, a, (double)nbox[6 * (size_t)v + 3 + a] + g.pad);
     }
     uint4 rec;
-    rec.x = lo3[0] | (lo3[1] << 16);
-    rec.y = lo3[2] | (hi3[0] << 16);
-    rec.z = hi3[1] | (hi3[2] << 16);
+    rec.x = lo3[0] | (hi3[0] << 16);
+    rec.y = lo3[1] | (hi3[1] << 16);
+    rec.z = lo3[2] | (hi3[2] << 16);
     if (dep >= (uint32_t)kMaxWalk) {
         atomicOr(&stats->bad, 1u);
         return;

@@ -184,6 +184,7 @@ struct Walker {
     uint32_t n, i;
     V3 o, d;
     float sx, sy, sz, bx, by, bz;  // slab planes: t = q * s + b per axis
+    uint32_t rx, ry, rz;           // 16 where the axis is walked backwards (near plane = hi), else 0
     float tmin, tbest;
     int32_t best, exclude;
     uint32_t best_k;
@@ -206,6 +207,9 @@ struct Walker {
         bx = (bvh.qlo[0] - o.x) * ix;
         by = (bvh.qlo[1] - o.y) * iy;
         bz = (bvh.qlo[2] - o.z) * iz;
+        rx = sx < 0.0f ? 16u : 0u;
+        ry = sy < 0.0f ? 16u : 0u;
+        rz = sz < 0.0f ? 16u : 0u;
         tmin = tmin_;
         tbest = tmax_;
         best = -1;
@@ -232,13 +236,19 @@ struct Walker {
         i = (hit || leaf) ? i + 1 : q.w;
     }
 
-    // Slab test of a quantised node box against [tmin, tbest].
+    // Slab test of a quantised node box against [tmin, tbest].  Each word
+    // holds one axis as lo | hi << 16; rotating it by 16 where the ray runs
+    // towards -axis puts that axis's entry plane in the low half, so the
+    // entry and exit distances need no min/max per axis (the values equal
+    // min/max of the two plane distances).
     __device__ __forceinline__ bool box_hit(const uint4 &q) const {
-        float tx0 = fmaf((float)(q.x & 0xffffu), sx, bx), tx1 = fmaf((float)(q.y >> 16), sx, bx);
-        float ty0 = fmaf((float)(q.x >> 16), sy, by), ty1 = fmaf((float)(q.z & 0xffffu), sy, by);
-        float tz0 = fmaf((float)(q.y & 0xffffu), sz, bz), tz1 = fmaf((float)(q.z >> 16), sz, bz);
-        float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), tmin));
-        float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tbest));
+        const uint32_t ax = __builtin_rotateright32(q.x, rx), ay = __builtin_rotateright32(q.y, ry),
+                       az = __builtin_rotateright32(q.z, rz);
+        const float nx = fmaf((float)(ax & 0xffffu), sx, bx), fx = fmaf((float)(ax >> 16), sx, bx);
+        const float ny = fmaf((float)(ay & 0xffffu), sy, by), fy = fmaf((float)(ay >> 16), sy, by);
+        const float nz = fmaf((float)(az & 0xffffu), sz, bz), fz = fmaf((float)(az >> 16), sz, bz);
+        const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, tmin));
+        const float tf = fminf(fminf(fx, fy), fminf(fz, tbest));
         return tn <= tf;
     }
 

@@ -11,8 +11,8 @@ def f32(words):
 def decode(nodes_s, info):
     """Dequantised boxes (float64), leaf flags, leaf ranges and next-on-miss links."""
     w = nodes_s.astype(np.int64)
-    q = np.stack([w[:, 0] & 0xffff, w[:, 0] >> 16, w[:, 1] & 0xffff,
-                  w[:, 1] >> 16, w[:, 2] & 0xffff, w[:, 2] >> 16], 1).astype(np.float64)
+    q = np.stack([w[:, 0] & 0xffff, w[:, 1] & 0xffff, w[:, 2] & 0xffff,
+                  w[:, 0] >> 16, w[:, 1] >> 16, w[:, 2] >> 16], 1).astype(np.float64)
     g0 = np.asarray(info["grid_lo"], np.float64)
     gs = np.asarray(info["grid_step"], np.float64)
     lo = g0 + q[:, 0:3] * gs
