@@ -489,6 +489,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     sc.power = acc;
     sc.eps = 1e-5f * diag;
     for (int a = 0; a < 3; ++a) sc.lo[a] = b->lo[a];
+    sc.ext = std::max(b->hi[0] - b->lo[0], std::max(b->hi[1] - b->lo[1], b->hi[2] - b->lo[2]));
     H3 pos{d->cam_pos[0], d->cam_pos[1], d->cam_pos[2]};
     H3 look{d->cam_look[0], d->cam_look[1], d->cam_look[2]};
     H3 up{d->cam_up[0], d->cam_up[1], d->cam_up[2]};

@@ -21,6 +21,7 @@ struct SceneDev {
     double power;
     float eps;
     float lo[3];
+    float ext;  // largest extent of the scene box
     V3 cpos, cf, cr, cu;
     float tanh_fov, aspect;
     int32_t W, H;
@@ -353,24 +354,44 @@ __device__ __forceinline__ void photon_drain_elem(const SppmDev &d, uint32_t k, 
 }
 
 // ---------------------------------------------------------------------------
-// Hashed grid (exact): cell edge h = 2 R_max (1 + 2^-10), so the 2x2x2 cells
-// around a hit point cover its disc; cells hash (Teschner et al. 2003) into a
-// power-of-two table; photons are counting-sorted by bucket.
+// Hashed grid: cell edge h = 2 R_max (1 + 2^-10), so the 2x2x2 cells around a
+// hit point cover its disc; cells hash (Teschner et al. 2003) into a
+// power-of-two table; photons are counting-sorted by bucket.  The exact
+// gather uses fine cells instead, h = R_max (1 + 2^-5): a disc then touches
+// at most 3 cells per axis, and a hit point examines the photons of a smaller
+// region.
 // ---------------------------------------------------------------------------
 struct Grid {
     float lo[3];
     float inv_h;
     uint32_t mask;
+    uint32_t fine;
 };
 
 __device__ __forceinline__ uint32_t cell_hash(int32_t ix, int32_t iy, int32_t iz, uint32_t mask) {
     return (((uint32_t)ix * 73856093u) ^ ((uint32_t)iy * 19349663u) ^ ((uint32_t)iz * 83492791u)) & mask;
 }
 
+// Fine cells only while the scene spans at most 4096 of them, which bounds the
+// rounding slack of the cell coordinates (see photons_in_disc_fine).
+constexpr double kFineMaxCells = 4096.0;
+
+// The exact gather uses fine cells wherever they are allowed: on the box and
+// procedural scenes they cost the same as 2 R_max cells when discs hold tens
+// of photons and save 11-14% of the iteration when they hold thousands.  The
+// stochastic estimator is defined on the 2 R_max grid.
 __device__ __forceinline__ Grid make_grid(const SppmDev &d) {
     double r2 = __longlong_as_double((long long)*d.r2max);
     double h = 2.0 * sqrt(r2) * (1.0 + 1.0 / 1024.0);
     Grid gr;
+    gr.fine = 0u;
+    if (d.gather_mode == PM_GATHER_EXACT) {
+        const double hf = sqrt(r2) * (1.0 + 1.0 / 32.0);
+        if (hf > 0.0 && (double)d.sc.ext <= kFineMaxCells * hf) {
+            h = hf;
+            gr.fine = 1u;
+        }
+    }
     gr.lo[0] = d.sc.lo[0];
     gr.lo[1] = d.sc.lo[1];
     gr.lo[2] = d.sc.lo[2];
@@ -420,13 +441,77 @@ __device__ __forceinline__ void scatter_elem(const SppmDev &d, const Grid &gr, u
     sorted[2 * (size_t)pos + 1] = b;
 }
 
-// Visit every photon of the (deduplicated) buckets of the 8 cells around a
-// hit point that is inside its disc (squared distance < R^2, float32 distance
-// compared in double) and arrived from the eye's side.
+// The photons of one bucket inside the disc (squared distance < R^2, float32
+// distance compared in double) that arrived from the eye's side.
+template <typename F>
+__device__ __forceinline__ void photons_of_bucket(const SppmDev &d, uint32_t hb, float4 hx, float4 hn, double r2,
+                                                  const uint32_t *__restrict__ start, const float4 *__restrict__ sorted,
+                                                  F &f) {
+    uint32_t q0 = start[d.table_off + hb], q1 = start[d.table_off + hb + 1];
+    for (uint32_t q = q0; q < q1; ++q) {
+        float4 a = sorted[2 * (size_t)q];
+        float dx = a.x - hx.x, dy = a.y - hx.y, dz = a.z - hx.z;
+        float d2 = (dx * dx + dy * dy) + dz * dz;
+        if ((double)d2 < r2) {
+            float4 b = sorted[2 * (size_t)q + 1];
+            float c2 = (b.x * hn.x + b.y * hn.y) + b.z * hn.z;
+            if (c2 < 0.0f) f(a, b);
+        }
+    }
+}
+
+// Fine cells: the disc spans cc -/+ rr per axis in cell units (rr widened by
+// 2^-8 relative and by (|cc| + 1) 2^-20, far above the rounding of the cell
+// coordinates).  With h = R_max (1 + 2^-5) and at most 4096 cells across the
+// scene, rr < 0.98, so the cells floor(cc - rr) .. floor(cc + rr) are at most
+// 3 per axis; every photon of the disc lies in one of them.  Buckets shared
+// by two of those cells (hash collisions) are visited once.
+template <typename F>
+__device__ __forceinline__ void photons_in_disc_fine(const SppmDev &d, const Grid &gr, float4 hx, float4 hn, double r2,
+                                                     const uint32_t *__restrict__ start,
+                                                     const float4 *__restrict__ sorted, F &f) {
+    const float cc[3] = {(hx.x - gr.lo[0]) * gr.inv_h, (hx.y - gr.lo[1]) * gr.inv_h, (hx.z - gr.lo[2]) * gr.inv_h};
+    const float rc = (float)sqrt(r2) * gr.inv_h;
+    int32_t c0[3];
+    uint32_t nc[3];
+    for (int a = 0; a < 3; ++a) {
+        const float rr = rc * (1.0f + 0x1p-8f) + (fabsf(cc[a]) + 1.0f) * 0x1p-20f;
+        c0[a] = (int32_t)floorf(cc[a] - rr);
+        nc[a] = (uint32_t)min((int32_t)floorf(cc[a] + rr) - c0[a] + 1, 3);
+    }
+    uint32_t hs[27];
+    uint32_t uniq = 0u;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const uint32_t tx = (uint32_t)(t % 3), ty = (uint32_t)((t / 3) % 3), tz = (uint32_t)(t / 9);
+        const bool used = tx < nc[0] && ty < nc[1] && tz < nc[2];
+        const uint32_t hb =
+            used ? cell_hash(c0[0] + (int32_t)tx, c0[1] + (int32_t)ty, c0[2] + (int32_t)tz, gr.mask) : 0xffffffffu;
+        hs[t] = hb;
+        bool dup = false;
+#pragma unroll
+        for (int e = 0; e < t; ++e) dup |= (hs[e] == hb);
+        if (used && !dup) uniq |= 1u << t;
+    }
+    while (uniq != 0u) {
+        const int t = __builtin_ctz(uniq);
+        uniq &= uniq - 1u;
+        const int32_t tx = t % 3, ty = (t / 3) % 3, tz = t / 9;
+        photons_of_bucket(d, cell_hash(c0[0] + tx, c0[1] + ty, c0[2] + tz, gr.mask), hx, hn, r2, start, sorted, f);
+    }
+}
+
+// Visit every photon inside a hit point's disc that arrived from the eye's
+// side, through the (deduplicated) buckets of the cells that the disc can
+// reach: of the 2x2x2 cells around it, or (fine grid) of up to 3x3x3.
 template <typename F>
 __device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const Grid &gr, float4 hx, float4 hn, double r2,
                                                        const uint32_t *__restrict__ start,
                                                        const float4 *__restrict__ sorted, F &&f) {
+    if (gr.fine) {
+        photons_in_disc_fine(d, gr, hx, hn, r2, start, sorted, f);
+        return;
+    }
     int32_t bx = (int32_t)floorf((hx.x - gr.lo[0]) * gr.inv_h - 0.5f);
     int32_t by = (int32_t)floorf((hx.y - gr.lo[1]) * gr.inv_h - 0.5f);
     int32_t bz = (int32_t)floorf((hx.z - gr.lo[2]) * gr.inv_h - 0.5f);
@@ -456,17 +541,7 @@ __device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const 
         bool dup = false;
         for (int e = 0; e < c; ++e) dup |= (seen[e] == hb);
         if (dup) continue;
-        uint32_t q0 = start[d.table_off + hb], q1 = start[d.table_off + hb + 1];
-        for (uint32_t q = q0; q < q1; ++q) {
-            float4 a = sorted[2 * (size_t)q];
-            float dx = a.x - hx.x, dy = a.y - hx.y, dz = a.z - hx.z;
-            float d2 = (dx * dx + dy * dy) + dz * dz;
-            if ((double)d2 < r2) {
-                float4 b = sorted[2 * (size_t)q + 1];
-                float c2 = (b.x * hn.x + b.y * hn.y) + b.z * hn.z;
-                if (c2 < 0.0f) f(a, b);
-            }
-        }
+        photons_of_bucket(d, hb, hx, hn, r2, start, sorted, f);
     }
 }
 

@@ -153,6 +153,16 @@ def test_one_bounce_per_pass_parity(torch_cuda, oracle_lib, pass_threads, passes
     s.destroy()
 
 
+def test_fine_grid_with_hash_collisions_parity(torch_cuda, oracle_lib):
+    """The exact gather's fine cells (edge R_max (1 + 2^-5), up to 3x3x3 cells
+    per hit point) on the smallest table (2^12 buckets) and a large radius:
+    about 20^3 cells share 4096 buckets, so the cells around a hit point often
+    collide, and a bucket reached twice must be counted once."""
+    _log("case: fine grid, 2^12 buckets, r0 = 0.05")
+    sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
+    _run_parity(torch_cuda, oracle_lib, sc, 1000, 3, 0.05, seed=12, stage_iters=3)
+
+
 @pytest.mark.parametrize("single_link_set", [1, 4, 6])
 def test_single_link_set_parity(torch_cuda, oracle_lib, single_link_set):
     """Every ray walking one link set (a single threaded BVH) changes nothing
