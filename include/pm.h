@@ -251,9 +251,11 @@ typedef struct {
 } pm_sppm_params;
 
 /* Range query.  EXACT: every photon inside a hit point's disc, found through
- * a hashed grid with cell edge 2 R_max (1 + 2^-10) and 2^bits entries,
+ * a hashed grid with cell edge R_max (1 + 2^-5) (2 R_max (1 + 2^-10) when the
+ * scene would span more than 4096 such cells) and 2^bits entries,
  * bits = clamp(ceil(log2(4 n_photons)), 12, 24).  STOCHASTIC: the paper's
- * stochastic spatial hashing (Sec. 3.4) on the same grid and table: each
+ * stochastic spatial hashing (Sec. 3.4) on a grid of cell edge
+ * 2 R_max (1 + 2^-10) and the same table: each
  * entry keeps one photon, the one of smallest (random depth, path * 32 +
  * bounce), with the depth drawn for each photon from its own counter-keyed
  * stream, and a hit point counts that photon, when inside its disc, once per
