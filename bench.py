@@ -112,7 +112,7 @@ def _parse():
     names = [k for k, _ in KERNEL_VARIANTS]
     ap.add_argument("--coherent", default="packet_tiles_block64", choices=names,
                     help="traversal options of the camera batch")
-    ap.add_argument("--incoherent", default="postponed_late16_reorder1_block64", choices=names,
+    ap.add_argument("--incoherent", default="postponed_late32_reorder1_block64", choices=names,
                     help="traversal options of the incoherent batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")

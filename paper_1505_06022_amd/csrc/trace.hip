@@ -182,8 +182,11 @@ __global__ void k_reset_counter(uint32_t *next) {
 // Ray reordering: bucket = (link set, [signs of the two minor direction
 // components,] Morton code of the origin cell in a grid over the scene box),
 // so that the rays of a wave share a direction set and start near each other.
-// Counting sort of ray indices (count, scan, scatter); a wave whose rays all
-// fall in one bucket uses one atomic and keeps its lanes in order.
+// Counting sort of ray indices: the count pass keeps each ray's bucket and its
+// rank among that bucket's rays (the counter value its atomic returned), the
+// scan turns counts into bucket starts, and the scatter places ray i at
+// start + rank with no further atomics.  A wave whose rays all fall in one
+// bucket uses one atomic and keeps its lanes in order.
 constexpr uint32_t kOrderBucketsCoarse = 6 * 4096;        // 16^3 cells
 constexpr uint32_t kOrderBucketsFine = 6 * 4 * 32768;      // minor signs x 32^3 cells
 
@@ -225,16 +228,24 @@ __device__ __forceinline__ uint32_t bucket_add(uint32_t *counters, uint32_t key)
 }
 
 __global__ __launch_bounds__(kTraceBlock) void k_ray_count(const float4 *__restrict__ rays, uint32_t n, OrderBox ob,
-                                                           int32_t force_set, uint32_t *__restrict__ counts) {
+                                                           int32_t force_set, uint32_t *__restrict__ counts,
+                                                           uint2 *__restrict__ key_rank) {
     uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
-    if (i < n) bucket_add(counts, ray_bucket(rays, i, ob, force_set));
+    if (i < n) {
+        const uint32_t key = ray_bucket(rays, i, ob, force_set);
+        key_rank[i] = make_uint2(key, bucket_add(counts, key));
+    }
 }
 
-__global__ __launch_bounds__(kTraceBlock) void k_ray_scatter(const float4 *__restrict__ rays, uint32_t n, OrderBox ob,
-                                                             int32_t force_set, uint32_t *__restrict__ fill,
+// rank < final count of the bucket, so start[key] + rank < n
+__global__ __launch_bounds__(kTraceBlock) void k_ray_scatter(const uint2 *__restrict__ key_rank, uint32_t n,
+                                                             const uint32_t *__restrict__ start,
                                                              uint32_t *__restrict__ perm) {
     uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
-    if (i < n) perm[bucket_add(fill, ray_bucket(rays, i, ob, force_set))] = i;
+    if (i < n) {
+        const uint2 kr = key_rank[i];
+        perm[start[kr.x] + kr.y] = i;
+    }
 }
 
 // Rays taken in the order of perm.
@@ -366,7 +377,8 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
             PM_HIP(hipFree(b->d_perm));
             b->d_perm = nullptr;
         }
-        PM_HIP(hipMalloc(&b->d_perm, sizeof(uint32_t) * (size_t)n));
+        // ray order, then each ray's (bucket, rank) pair at an 8-byte aligned offset
+        PM_HIP(hipMalloc(&b->d_perm, sizeof(uint32_t) * (3 * (size_t)n + 2)));
         b->perm_cap = (uint64_t)n;
     }
     const uint32_t nbk = reorder == 2 ? kOrderBucketsFine : kOrderBucketsCoarse;
@@ -384,11 +396,12 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
     }
     const uint32_t nn = (uint32_t)n, blocks = (uint32_t)((n + kTraceBlock - 1) / kTraceBlock);
     hipLaunchKernelGGL(k_fill_u32, dim3((nbk + 255) / 256), dim3(256), 0, s, counts, nbk, 0u);
+    uint2 *key_rank = (uint2 *)(b->d_perm + ((b->perm_cap + 1) & ~uint64_t(1)));
     hipLaunchKernelGGL(k_ray_count, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
-                       counts);
+                       counts, key_rank);
     launch_bucket_scan(counts, start, fill, bsum, nbk, s);
-    hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
-                       fill, b->d_perm);
+    hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const uint2 *)key_rank, nn,
+                       (const uint32_t *)start, b->d_perm);
     if (kernel == PM_TRACE_PERSISTENT)
         return launch_persistent(b, bvh, rays, nn, hit, t, link_set, counters, (int)late, b->d_perm, s);
     using Kern = void (*)(pmd::Bvh, const float4 *, const uint32_t *, uint32_t, int32_t *, float *, int32_t,
