@@ -233,7 +233,7 @@ typedef struct {
                                   max_photon_bounces of replay scratch) */
     int32_t photon_kernel;    /* PM_PHOTON_*: 0 = default (regeneration) */
     int32_t refill;           /* regeneration: idle lanes of a wave that
-                                 trigger taking new paths (1..64; 0 = 16) */
+                                 trigger taking new paths (1..64; 0 = 32) */
     int32_t single_link_set;  /* 0: each ray walks the link set of its
                                  direction (MTBVH, Sec. 3.1); s + 1 (1..6):
                                  every ray walks link set s, i.e. a single

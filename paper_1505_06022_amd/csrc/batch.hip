@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBs) void k_batch(BatchDev b) {
             Grid gr = make_grid(d);
             for (int64_t e = e0 + threadIdx.x; e < end; e += kBs) {
                 if (kStage == kStCount) count_elem(d, gr, (uint32_t)e, b.cell_count);
-                if (kStage == kStScatter) scatter_elem(d, gr, (uint32_t)e, b.cell_fill, b.sorted);
+                if (kStage == kStScatter) scatter_elem(d, (uint32_t)e, b.cell_start, b.sorted);
                 if (kStage == kStGather) gather_elem(d, gr, e, b.cell_start, b.sorted);
             }
             continue;

@@ -86,11 +86,11 @@ __global__ __launch_bounds__(kBlock) void k_count(SppmDev d, uint32_t *__restric
     for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < n_ph; j += gridDim.x * kBlock) count_elem(d, gr, j, cell_count);
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(SppmDev d, uint32_t *__restrict__ fill, float4 *__restrict__ sorted) {
+__global__ __launch_bounds__(kBlock) void k_scatter(SppmDev d, const uint32_t *__restrict__ start,
+                                                    float4 *__restrict__ sorted) {
     uint32_t n_ph = stored_photons(d);
-    Grid gr = make_grid(d);
     for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < n_ph; j += gridDim.x * kBlock)
-        scatter_elem(d, gr, j, fill, sorted);
+        scatter_elem(d, j, start, sorted);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(SppmDev d, const uint32_t *__restrict__ start,
@@ -272,7 +272,7 @@ void sppm_free(pm_sppm *s) {
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
                     s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
-                    s->sh_key, s->sh_surv, s->slot_mem};
+                    s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
@@ -423,6 +423,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     }
     PM_HIPF(hipMalloc(&s->M, sizeof(uint32_t) * s->P));
     PM_HIPF(hipMalloc(&s->Phi, sizeof(unsigned long long) * s->P));
+    if (p->gather_mode == PM_GATHER_EXACT) PM_HIPF(hipMalloc(&s->key_rank, sizeof(uint2) * (size_t)cap64));
     if (p->photon_kernel == PM_PHOTON_PASSES) {
         // one slot per thread of a pass; the paper runs one thread per pixel
         const uint32_t S = p->pass_threads > 0 ? (uint32_t)p->pass_threads
@@ -520,7 +521,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.photon_kernel = (p->photon_kernel == PM_PHOTON_PER_PATH || p->photon_kernel == PM_PHOTON_PASSES)
                            ? p->photon_kernel
                            : PM_PHOTON_REGEN;
-    dv.refill = p->refill > 0 ? (uint32_t)p->refill : 16u;
+    dv.refill = p->refill > 0 ? (uint32_t)p->refill : 32u;
     dv.force_set = p->single_link_set - 1;
     dv.gather_mode = p->gather_mode;
     dv.sh_key = s->sh_key;
@@ -539,6 +540,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.tau = s->tau;
     dv.D = s->D;
     dv.store = s->store;
+    dv.key_rank = s->key_rank;
     dv.counters = s->counters;
     dv.r2max = s->r2max;
     dv.M = s->M;
@@ -612,7 +614,8 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
         } else {
             hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
             launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
-            hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_fill, s->sorted);
+            hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, (const uint32_t *)s->cell_start,
+                               s->sorted);
             hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d,
                                (const uint32_t *)s->cell_start, (const float4 *)s->sorted);
         }
@@ -678,7 +681,8 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
         launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
-        hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_fill, s->sorted);
+        hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, (const uint32_t *)s->cell_start,
+                               s->sorted);
         hipLaunchKernelGGL(k_gather_adj, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, R2k,
                            (const uint32_t *)s->cell_start, (const float4 *)s->sorted, g, K, s->adj_tab, s->n_mat,
                            s->grad_mat);

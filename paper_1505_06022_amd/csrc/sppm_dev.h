@@ -47,6 +47,7 @@ struct SppmDev {
     float4 *hp_pos, *hp_nrm;  // (x, W*rho/pi), (n toward the eye, material bits | -1)
     double *N, *R2, *tau, *D;
     float4 *store;            // [cap][2]: (x, phi), (w, path << 5 | bounce)
+    uint2 *key_rank;          // [cap] exact gather: each stored photon's bucket and its rank in the bucket
     uint32_t *counters;       // [0] photons stored, [1] overflow flag, [2] next path (regeneration)
     unsigned long long *r2max;
     uint32_t *M;
@@ -427,16 +428,22 @@ __device__ __forceinline__ void rmax_flush(const SppmDev &d, unsigned long long 
     if ((threadIdx.x & 63) == 0 && v) atomicMax(d.r2max, v);
 }
 
+// Counting sort of the stored photons by bucket: the count pass keeps each
+// photon's bucket and its rank in the bucket (the value its atomic returned);
+// after the scan the scatter places it at the bucket's start + rank, which
+// is below the next bucket's start, with no further atomics.
 __device__ __forceinline__ void count_elem(const SppmDev &d, const Grid &gr, uint32_t j, uint32_t *__restrict__ cell_count) {
     float4 a = d.store[2 * (size_t)j];
-    atomicAdd(&cell_count[d.table_off + photon_bucket(gr, a.x, a.y, a.z)], 1u);
+    const uint32_t hb = photon_bucket(gr, a.x, a.y, a.z);
+    d.key_rank[j] = make_uint2(hb, atomicAdd(&cell_count[d.table_off + hb], 1u));
 }
 
-__device__ __forceinline__ void scatter_elem(const SppmDev &d, const Grid &gr, uint32_t j, uint32_t *__restrict__ fill,
+__device__ __forceinline__ void scatter_elem(const SppmDev &d, uint32_t j, const uint32_t *__restrict__ start,
                                              float4 *__restrict__ sorted) {
     float4 a = d.store[2 * (size_t)j];
     float4 b = d.store[2 * (size_t)j + 1];
-    uint32_t pos = atomicAdd(&fill[d.table_off + photon_bucket(gr, a.x, a.y, a.z)], 1u);
+    const uint2 kr = d.key_rank[j];
+    const uint32_t pos = start[d.table_off + kr.x] + kr.y;
     sorted[2 * (size_t)pos] = a;
     sorted[2 * (size_t)pos + 1] = b;
 }

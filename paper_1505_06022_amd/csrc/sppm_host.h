@@ -27,6 +27,7 @@ struct pm_sppm {
     double *N = nullptr, *R2 = nullptr, *tau = nullptr, *D = nullptr;
     float4 *hp_pos = nullptr, *hp_nrm = nullptr;
     float4 *store = nullptr, *sorted = nullptr;
+    uint2 *key_rank = nullptr;  // exact gather: [cap] bucket and rank of each stored photon
     uint32_t *counters = nullptr;  // [0] photons stored, [1] overflow flag
     unsigned long long *r2max = nullptr;
     // bucket arrays (absent for a batch member, which uses the batch's)
