@@ -28,6 +28,10 @@ using namespace pmd;
 
 enum Stage : int { kStEye = 0, kStPhoton, kStRmax, kStCount, kStScatter, kStGather, kStUpdate, kNumStages };
 
+// A photon-stage item holds kPhotonItem chunks of paths, split between the
+// workgroup's wavefronts, which regenerate paths within their share.
+constexpr uint32_t kPhotonItem = 8;
+
 struct BatchDev {
     const SppmDev *scenes;  // [S]
     int32_t S;
@@ -73,8 +77,16 @@ __global__ __launch_bounds__(kBs) void k_batch(BatchDev b) {
         if (it >= total) break;
         const int s = __builtin_amdgcn_readfirstlane(find_scene(off, b.S, it));
         const SppmDev &d = b.scenes[s];
-        const int64_t e0 = (int64_t)(it - off[s]) * b.chunk;
-        const int64_t end = min(e0 + (int64_t)b.chunk, stage_elems<kStage>(d));
+        const int64_t per = kStage == kStPhoton ? (int64_t)b.chunk * kPhotonItem : (int64_t)b.chunk;
+        const int64_t e0 = (int64_t)(it - off[s]) * per;
+        const int64_t end = min(e0 + per, stage_elems<kStage>(d));
+        if (kStage == kStPhoton) {
+            constexpr int kWaves = kBs / 64;
+            const int64_t span = (end - e0 + kWaves - 1) / kWaves;
+            const int64_t w0 = min(e0 + (int64_t)(threadIdx.x >> 6) * span, end), w1 = min(w0 + span, end);
+            photon_regen_range(d, k, (uint32_t)w0, (uint32_t)w1, d.refill);
+            continue;
+        }
         if (kStage == kStRmax) {
             unsigned long long v = 0ull;
             for (int64_t e = e0 + threadIdx.x; e < end; e += kBs) {
@@ -95,7 +107,6 @@ __global__ __launch_bounds__(kBs) void k_batch(BatchDev b) {
         }
         for (int64_t e = e0 + threadIdx.x; e < end; e += kBs) {
             if (kStage == kStEye) eye_elem(d, k, e, true);
-            if (kStage == kStPhoton) photon_elem<false>(d, k, (uint32_t)e, nullptr, nullptr);
             if (kStage == kStUpdate) update_elem(d, e, nullptr);
         }
     }
@@ -260,7 +271,8 @@ int upload_items(pm_batch *b, hipStream_t st) {
             off[(size_t)stg * (S + 1) + s] = acc;
             const pm_sppm *m = b->members[s];
             int64_t n = stg == kStPhoton ? m->prm.n_photons : (stg == kStCount || stg == kStScatter ? 0 : m->P);
-            acc += (uint32_t)((n + b->chunk - 1) / b->chunk);
+            const int64_t per = stg == kStPhoton ? (int64_t)b->chunk * kPhotonItem : (int64_t)b->chunk;
+            acc += (uint32_t)((n + per - 1) / per);
         }
         off[(size_t)stg * (S + 1) + S] = acc;
     }

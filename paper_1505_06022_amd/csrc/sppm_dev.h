@@ -275,6 +275,31 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
     }
 }
 
+// Regeneration over the paths [n0, n1) of one wavefront (batched photon
+// stage): the path cursor is a wave-uniform register, so lanes take new paths
+// without atomics.  Called by every lane of a wave; the loop ends once the
+// range is handed out and no path is live.
+__device__ __forceinline__ void photon_regen_range(const SppmDev &d, uint32_t k, uint32_t n0, uint32_t n1,
+                                                   uint32_t refill) {
+    PhotonPath P;
+    bool live = false;
+    uint32_t next = n0;
+    for (;;) {
+        const bool idle = !live;
+        const uint64_t idle_mask = __ballot(idle);
+        uint64_t live_mask = __ballot(live);
+        if (next < n1 && idle_mask != 0ull && (live_mask == 0ull || (uint32_t)__popcll(idle_mask) >= refill)) {
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
+            if (idle && next + rank < n1) live = photon_emit(d, k, next + rank, P);
+            next += (uint32_t)__popcll(idle_mask);
+            live_mask = __ballot(live);
+        }
+        if (live_mask == 0ull && next >= n1) break;
+        if (live) live = photon_bounce<false>(d, P, nullptr, nullptr);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Photon paths one bounce per pass (Sec. 3.3 as the paper schedules it): a
 // fixed pool of threads, each owning one slot; every launch (a pass) moves the
