@@ -96,12 +96,20 @@ __global__ __launch_bounds__(kBs) void k_batch(BatchDev b) {
             rmax_flush(d, v);
             continue;
         }
-        if (kStage == kStCount || kStage == kStScatter || kStage == kStGather) {
+        if (kStage == kStGather) {
+            // every lane of the workgroup takes part in each round (p = P: no pixel)
+            Grid gr = make_grid(d);
+            for (int64_t e = e0; e < end; e += kBs) {
+                const int64_t p = e + threadIdx.x;
+                gather_wave(d, gr, p < end ? p : d.P, b.cell_start, b.sorted);
+            }
+            continue;
+        }
+        if (kStage == kStCount || kStage == kStScatter) {
             Grid gr = make_grid(d);
             for (int64_t e = e0 + threadIdx.x; e < end; e += kBs) {
                 if (kStage == kStCount) count_elem(d, gr, (uint32_t)e, b.cell_count);
                 if (kStage == kStScatter) scatter_elem(d, (uint32_t)e, b.cell_start, b.sorted);
-                if (kStage == kStGather) gather_elem(d, gr, e, b.cell_start, b.sorted);
             }
             continue;
         }

@@ -95,10 +95,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SppmDev d, const uint32_t *_
 
 __global__ __launch_bounds__(kBlock) void k_gather(SppmDev d, const uint32_t *__restrict__ start,
                                                    const float4 *__restrict__ sorted) {
-    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (p >= d.P) return;
+    // every lane takes part (the wave may scan a dense hit point together)
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     Grid gr = make_grid(d);
-    gather_elem(d, gr, p, start, sorted);
+    gather_wave(d, gr, p, start, sorted);
 }
 
 // Stochastic spatial hashing: clear the keys, insert every stored photon

@@ -399,7 +399,7 @@ __device__ __forceinline__ uint32_t cell_hash(int32_t ix, int32_t iy, int32_t iz
 }
 
 // Fine cells only while the scene spans at most 4096 of them, which bounds the
-// rounding slack of the cell coordinates (see photons_in_disc_fine).
+// rounding slack of the cell coordinates (see disc_cells).
 constexpr double kFineMaxCells = 4096.0;
 
 // The exact gather uses fine cells wherever they are allowed: on the box and
@@ -492,89 +492,69 @@ __device__ __forceinline__ void photons_of_bucket(const SppmDev &d, uint32_t hb,
     }
 }
 
-// Fine cells: the disc spans cc -/+ rr per axis in cell units (rr widened by
-// 2^-8 relative and by (|cc| + 1) 2^-20, far above the rounding of the cell
-// coordinates).  With h = R_max (1 + 2^-5) and at most 4096 cells across the
-// scene, rr < 0.98, so the cells floor(cc - rr) .. floor(cc + rr) are at most
-// 3 per axis; every photon of the disc lies in one of them.  Buckets shared
-// by two of those cells (hash collisions) are visited once.
-template <typename F>
-__device__ __forceinline__ void photons_in_disc_fine(const SppmDev &d, const Grid &gr, float4 hx, float4 hn, double r2,
-                                                     const uint32_t *__restrict__ start,
-                                                     const float4 *__restrict__ sorted, F &f) {
+// The cells a hit point's disc can reach, as a block of at most 3x3x3 cells
+// from c0; bit t of `uniq` marks cell c0 + (t % 3, t / 3 % 3, t / 9) as the
+// first of the block's cells in its bucket (hash collisions are visited once).
+struct DiscCells {
+    int32_t c0[3];
+    uint32_t uniq;
+};
+
+__device__ __forceinline__ uint32_t disc_cell_bucket(const Grid &gr, const int32_t c0[3], int t) {
+    return cell_hash(c0[0] + t % 3, c0[1] + (t / 3) % 3, c0[2] + t / 9, gr.mask);
+}
+
+// In cell units the disc spans cc -/+ rr per axis, rr widened by 2^-8
+// relative and by (|cc| + 1) 2^-s absolute, far above the rounding of the cell
+// coordinates, so no cell holding a photon of the disc is left out.
+// * Fine cells (edge R_max (1 + 2^-5), at most 4096 across the scene, s = 20):
+//   rr < 0.98, so floor(cc - rr) .. floor(cc + rr) are at most 3 cells.
+// * Cells of edge 2 R_max (1 + 2^-10) (s = 16): the cells b and b + 1 with
+//   b = floor(cc - 1/2) contain the disc; one of them is dropped when the
+//   widened disc does not reach it.
+__device__ __forceinline__ DiscCells disc_cells(const Grid &gr, float4 hx, double r2) {
     const float cc[3] = {(hx.x - gr.lo[0]) * gr.inv_h, (hx.y - gr.lo[1]) * gr.inv_h, (hx.z - gr.lo[2]) * gr.inv_h};
     const float rc = (float)sqrt(r2) * gr.inv_h;
-    int32_t c0[3];
+    DiscCells dc;
     uint32_t nc[3];
     for (int a = 0; a < 3; ++a) {
-        const float rr = rc * (1.0f + 0x1p-8f) + (fabsf(cc[a]) + 1.0f) * 0x1p-20f;
-        c0[a] = (int32_t)floorf(cc[a] - rr);
-        nc[a] = (uint32_t)min((int32_t)floorf(cc[a] + rr) - c0[a] + 1, 3);
+        if (gr.fine) {
+            const float rr = rc * (1.0f + 0x1p-8f) + (fabsf(cc[a]) + 1.0f) * 0x1p-20f;
+            dc.c0[a] = (int32_t)floorf(cc[a] - rr);
+            nc[a] = (uint32_t)min((int32_t)floorf(cc[a] + rr) - dc.c0[a] + 1, 3);
+        } else {
+            const float rr = rc * (1.0f + 0x1p-8f) + (fabsf(cc[a]) + 1.0f) * 0x1p-16f;
+            const int32_t bb = (int32_t)floorf(cc[a] - 0.5f);
+            const float mid = (float)(bb + 1);
+            const bool lower = cc[a] - rr < mid, upper = cc[a] + rr >= mid;
+            dc.c0[a] = lower ? bb : bb + 1;
+            nc[a] = (lower ? 1u : 0u) + (upper ? 1u : 0u);
+        }
     }
     uint32_t hs[27];
-    uint32_t uniq = 0u;
+    dc.uniq = 0u;
 #pragma unroll
     for (int t = 0; t < 27; ++t) {
-        const uint32_t tx = (uint32_t)(t % 3), ty = (uint32_t)((t / 3) % 3), tz = (uint32_t)(t / 9);
-        const bool used = tx < nc[0] && ty < nc[1] && tz < nc[2];
-        const uint32_t hb =
-            used ? cell_hash(c0[0] + (int32_t)tx, c0[1] + (int32_t)ty, c0[2] + (int32_t)tz, gr.mask) : 0xffffffffu;
+        const bool used = (uint32_t)(t % 3) < nc[0] && (uint32_t)((t / 3) % 3) < nc[1] && (uint32_t)(t / 9) < nc[2];
+        const uint32_t hb = used ? disc_cell_bucket(gr, dc.c0, t) : 0xffffffffu;
         hs[t] = hb;
         bool dup = false;
 #pragma unroll
         for (int e = 0; e < t; ++e) dup |= (hs[e] == hb);
-        if (used && !dup) uniq |= 1u << t;
+        if (used && !dup) dc.uniq |= 1u << t;
     }
-    while (uniq != 0u) {
-        const int t = __builtin_ctz(uniq);
-        uniq &= uniq - 1u;
-        const int32_t tx = t % 3, ty = (t / 3) % 3, tz = t / 9;
-        photons_of_bucket(d, cell_hash(c0[0] + tx, c0[1] + ty, c0[2] + tz, gr.mask), hx, hn, r2, start, sorted, f);
-    }
+    return dc;
 }
 
 // Visit every photon inside a hit point's disc that arrived from the eye's
-// side, through the (deduplicated) buckets of the cells that the disc can
-// reach: of the 2x2x2 cells around it, or (fine grid) of up to 3x3x3.
+// side, through the distinct buckets of the cells its disc can reach.
 template <typename F>
 __device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const Grid &gr, float4 hx, float4 hn, double r2,
                                                        const uint32_t *__restrict__ start,
                                                        const float4 *__restrict__ sorted, F &&f) {
-    if (gr.fine) {
-        photons_in_disc_fine(d, gr, hx, hn, r2, start, sorted, f);
-        return;
-    }
-    int32_t bx = (int32_t)floorf((hx.x - gr.lo[0]) * gr.inv_h - 0.5f);
-    int32_t by = (int32_t)floorf((hx.y - gr.lo[1]) * gr.inv_h - 0.5f);
-    int32_t bz = (int32_t)floorf((hx.z - gr.lo[2]) * gr.inv_h - 0.5f);
-    // A hit point whose radius is below R_max may have its disc inside one of
-    // the two cells along an axis; the other is then skipped.  In cell units:
-    // the disc spans cx -/+ rr, widened by a slack far above the rounding of
-    // the cell coordinates, so no cell holding a photon of the disc is skipped.
-    uint32_t need = 0;  // bit 2a: lower cell along axis a, bit 2a+1: upper cell
-    {
-        const float cc[3] = {(hx.x - gr.lo[0]) * gr.inv_h, (hx.y - gr.lo[1]) * gr.inv_h, (hx.z - gr.lo[2]) * gr.inv_h};
-        const int32_t bb[3] = {bx, by, bz};
-        const float rc = (float)sqrt(r2) * gr.inv_h;
-        for (int a = 0; a < 3; ++a) {
-            const float rr = rc * (1.0f + 0x1p-8f) + (fabsf(cc[a]) + 1.0f) * 0x1p-16f;
-            const float mid = (float)(bb[a] + 1);
-            if (cc[a] - rr < mid) need |= 1u << (2 * a);
-            if (cc[a] + rr >= mid) need |= 2u << (2 * a);
-        }
-    }
-    uint32_t seen[8];
-    for (int c = 0; c < 8; ++c) {
-        const bool used = ((need >> ((c & 1) ? 1 : 0)) & 1u) && ((need >> (((c >> 1) & 1) ? 3 : 2)) & 1u) &&
-                          ((need >> ((c >> 2) ? 5 : 4)) & 1u);
-        uint32_t hb = used ? cell_hash(bx + (c & 1), by + ((c >> 1) & 1), bz + (c >> 2), gr.mask) : 0xffffffffu;
-        seen[c] = hb;
-        if (!used) continue;
-        bool dup = false;
-        for (int e = 0; e < c; ++e) dup |= (seen[e] == hb);
-        if (dup) continue;
-        photons_of_bucket(d, hb, hx, hn, r2, start, sorted, f);
-    }
+    const DiscCells dc = disc_cells(gr, hx, r2);
+    for (uint32_t m = dc.uniq; m != 0u; m &= m - 1u)
+        photons_of_bucket(d, disc_cell_bucket(gr, dc.c0, __builtin_ctz(m)), hx, hn, r2, start, sorted, f);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,24 +627,99 @@ __device__ __forceinline__ void sh_gather_elem(const SppmDev &d, const Grid &gr,
     d.Phi[p] = F;
 }
 
-// Range query of one hit point: M photons and their flux, each term rounded to
-// 2^-shift fixed point and summed as integers (order independent).
-__device__ __forceinline__ void gather_elem(const SppmDev &d, const Grid &gr, int64_t p, const uint32_t *__restrict__ start,
-                                            const float4 *__restrict__ sorted) {
-    float4 hn = d.hp_nrm[p];
-    uint32_t M = 0;
+// Range query: per hit point, M photons and their flux, each term rounded to
+// 2^-shift fixed point and summed as integers (order independent).  Called
+// by every lane of a wave, one pixel per lane (p >= P: no pixel).  A hit
+// point whose buckets hold at least kCoopMin photons is scanned by the whole
+// wave, 64 consecutive photons per step, and the lanes' partial counts and
+// sums are added up; the others are scanned by their own lane.  Both give the
+// same M and flux.
+constexpr uint32_t kCoopMin = 256;
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(0xffffffffu, __builtin_amdgcn_mbcnt_lo(0xffffffffu, 0u));
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ void gather_wave(const SppmDev &d, const Grid &gr, int64_t p,
+                                            const uint32_t *__restrict__ start, const float4 *__restrict__ sorted) {
+    const bool in = p < d.P;
+    const float4 hn = in ? d.hp_nrm[p] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
+    const bool valid = in && __float_as_int(hn.w) >= 0;
+    float4 hx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    double r2 = 0.0;
+    DiscCells dc{};
+    uint32_t load = 0u;
+    if (valid) {
+        hx = d.hp_pos[p];
+        r2 = d.R2[p];
+        dc = disc_cells(gr, hx, r2);
+        for (uint32_t m = dc.uniq; m != 0u; m &= m - 1u) {
+            const uint32_t hb = d.table_off + disc_cell_bucket(gr, dc.c0, __builtin_ctz(m));
+            load += start[hb + 1] - start[hb];
+        }
+    }
+    const double scale = d.scale;
+    uint32_t M = 0u;
     unsigned long long F = 0ull;
-    if (__float_as_int(hn.w) >= 0) {
-        float4 hx = d.hp_pos[p];
-        double wk = (double)hx.w;
-        const double scale = d.scale;
-        for_each_photon_in_disc(d, gr, hx, hn, d.R2[p], start, sorted, [&](const float4 &a, const float4 &) {
+    const bool coop = load >= kCoopMin;
+    if (valid && !coop) {
+        const double wk = (double)hx.w;
+        auto add = [&](const float4 &a, const float4 &) {
             M++;
             F += (unsigned long long)rint((wk * (double)a.w) * scale);
-        });
+        };
+        for (uint32_t m = dc.uniq; m != 0u; m &= m - 1u)
+            photons_of_bucket(d, disc_cell_bucket(gr, dc.c0, __builtin_ctz(m)), hx, hn, r2, start, sorted, add);
     }
-    d.M[p] = M;
-    d.Phi[p] = F;
+    const uint32_t lane = lane_id();
+    for (uint64_t todo = __ballot(coop); todo != 0ull; todo &= todo - 1ull) {
+        const int L = __ffsll((unsigned long long)todo) - 1;
+        const float4 xl = make_float4(readlane_f(hx.x, L), readlane_f(hx.y, L), readlane_f(hx.z, L), readlane_f(hx.w, L));
+        const float4 nl = make_float4(readlane_f(hn.x, L), readlane_f(hn.y, L), readlane_f(hn.z, L), 0.0f);
+        const unsigned long long r2b = (unsigned long long)__double_as_longlong(r2);
+        const double r2l = __longlong_as_double(
+            (long long)(((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r2b >> 32), L) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r2b, L)));
+        const int32_t c0l[3] = {__builtin_amdgcn_readlane(dc.c0[0], L), __builtin_amdgcn_readlane(dc.c0[1], L),
+                                __builtin_amdgcn_readlane(dc.c0[2], L)};
+        const uint32_t uniql = (uint32_t)__builtin_amdgcn_readlane((int)dc.uniq, L);
+        const double wk = (double)xl.w;
+        uint32_t m = 0u;
+        unsigned long long f = 0ull;
+        for (uint32_t bits = uniql; bits != 0u; bits &= bits - 1u) {
+            const uint32_t hb = d.table_off + disc_cell_bucket(gr, c0l, __builtin_ctz(bits));
+            const uint32_t q1 = start[hb + 1];
+            for (uint32_t q = start[hb] + lane; q < q1; q += 64u) {
+                const float4 a = sorted[2 * (size_t)q];
+                const float dx = a.x - xl.x, dy = a.y - xl.y, dz = a.z - xl.z;
+                const float d2 = (dx * dx + dy * dy) + dz * dz;
+                if ((double)d2 < r2l) {
+                    const float4 b = sorted[2 * (size_t)q + 1];
+                    const float c2 = (b.x * nl.x + b.y * nl.y) + b.z * nl.z;
+                    if (c2 < 0.0f) {
+                        m++;
+                        f += (unsigned long long)rint((wk * (double)a.w) * scale);
+                    }
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            m += __shfl_xor(m, off);
+            f += __shfl_xor(f, off);
+        }
+        if ((int)lane == L) {
+            M = m;
+            F = f;
+        }
+    }
+    if (in) {
+        d.M[p] = M;
+        d.Phi[p] = F;
+    }
 }
 
 // Progressive update (radius reduction and flux rescaling of SPPM); hist

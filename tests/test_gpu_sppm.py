@@ -163,6 +163,23 @@ def test_fine_grid_with_hash_collisions_parity(torch_cuda, oracle_lib):
     _run_parity(torch_cuda, oracle_lib, sc, 1000, 3, 0.05, seed=12, stage_iters=3)
 
 
+def test_dense_discs_wave_gather_parity(torch_cuda, oracle_lib):
+    """Radii large enough that most hit points' buckets hold hundreds to
+    thousands of photons, so the gather scans them with the whole wavefront
+    and adds the lanes' partial counts and fixed-point sums: M and flux must
+    still equal the oracle's exactly."""
+    _log("case: box scene 32x32, 2^15 photons, r0 = 0.2")
+    sc = scenes.box_scene(32, 32)
+    _run_parity(torch_cuda, oracle_lib, sc, 1 << 15, 2, 0.2, seed=14, stage_iters=2)
+    # both ways of scanning were taken: a hit point's buckets hold at least its
+    # M photons, and the wave scans them together from 256 photons on
+    osc = oracle_lib.OracleScene(sc)
+    hp = oracle_lib.eye_pass(osc, 14, 0)
+    M, _ = oracle_lib.gather(hp, oracle_lib.photon_pass(osc, 14, 0, 1 << 15), np.full(osc.P, 0.04))
+    v = hp.valid > 0
+    assert (M[v] >= 256).mean() > 0.5 and (M[v] < 64).any()
+
+
 @pytest.mark.parametrize("single_link_set", [1, 4, 6])
 def test_single_link_set_parity(torch_cuda, oracle_lib, single_link_set):
     """Every ray walking one link set (a single threaded BVH) changes nothing
