@@ -31,6 +31,12 @@ __global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint8_
 // Persistent photon lanes with path regeneration.
 __global__ __launch_bounds__(kBlock) void k_photon_regen(SppmDev d, uint32_t k) { photon_regen_loop(d, k, d.refill); }
 
+// The same, recording each path's stored-photon materials for the adjoint.
+__global__ __launch_bounds__(kBlock) void k_photon_regen_rec(SppmDev d, uint32_t k, uint8_t *__restrict__ mat_tab,
+                                                             double *__restrict__ adj_tab) {
+    photon_regen_loop<true>(d, k, d.refill, mat_tab, adj_tab);
+}
+
 // One pass of the one-bounce-per-pass schedule; the grid covers the slots
 // with the same workgroup-to-slot map in every pass.
 __global__ __launch_bounds__(kBlock) void k_photon_pass(SppmDev d, uint32_t k, PassSlots ps) {
@@ -532,6 +538,8 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         PM_HIPF(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_regen, kBlock, 0));
         s->regen_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_regen_rec, kBlock, 0));
+        s->regen_grid_rec = (uint32_t)std::max(1, cus * std::max(1, per_cu));
     }
     dv.hp_pos = s->hp_pos;
     dv.hp_nrm = s->hp_nrm;
@@ -676,8 +684,8 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
         hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, (uint32_t)k, 0);
         hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d, R2k);
         PM_HIP(hipEventRecord(s->ev_join, s->side));
-        hipLaunchKernelGGL(k_photon<true>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, (uint32_t)k, s->mat_tab,
-                           s->adj_tab);
+        hipLaunchKernelGGL(k_photon_regen_rec, dim3(s->regen_grid_rec), dim3(kBlock), 0, st, d, (uint32_t)k,
+                           s->mat_tab, s->adj_tab);
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
         launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);

@@ -255,7 +255,12 @@ __device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32
 // all are).  Every step advances each live path by one bounce and paths are
 // bounded by max_bounces, so every wave exits once the counter passes n_paths.
 // Called by every lane of a wave; the wave's lanes must share one scene.
-__device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, uint32_t refill) {
+// kRecord (adjoint replay): paths also write their rows of mat_tab / adj_tab
+// as in photon_elem.
+template <bool kRecord = false>
+__device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, uint32_t refill,
+                                                  uint8_t *__restrict__ mat_tab = nullptr,
+                                                  double *__restrict__ adj_tab = nullptr) {
     PhotonPath P;
     bool live = false, exhausted = false;
     for (;;) {
@@ -265,13 +270,20 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
         if (idle_mask != 0ull && (live_mask == 0ull || (uint32_t)__popcll(idle_mask) >= refill)) {
             uint32_t n = wave_fetch_add(&d.counters[2], idle_mask, idle);
             if (idle) {
-                if (n < d.n_paths) live = photon_emit(d, k, n, P);
-                else exhausted = true;
+                if (n < d.n_paths) {
+                    live = photon_emit(d, k, n, P);
+                    if (kRecord && !live) photon_finish<true>(d, P, mat_tab);
+                } else {
+                    exhausted = true;
+                }
             }
             live_mask = __ballot(live);
         }
         if (live_mask == 0ull && __ballot(!exhausted) == 0ull) break;
-        if (live) live = photon_bounce<false>(d, P, nullptr, nullptr);
+        if (live) {
+            live = photon_bounce<kRecord>(d, P, mat_tab, adj_tab);
+            if (kRecord && !live) photon_finish<true>(d, P, mat_tab);
+        }
     }
 }
 

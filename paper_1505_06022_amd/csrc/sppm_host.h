@@ -17,7 +17,8 @@ struct pm_sppm {
     int32_t K = 0;
     uint32_t cap = 0;
     uint32_t table_bits = 0;
-    uint32_t regen_grid = 1;  // workgroups of the regenerating photon kernel
+    uint32_t regen_grid = 1;      // workgroups of the regenerating photon kernel
+    uint32_t regen_grid_rec = 1;  // and of its recording variant (adjoint replay)
     float phi0 = 0.0f;
     // device buffers
     int32_t *mat_type = nullptr;
