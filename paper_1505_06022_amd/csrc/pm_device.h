@@ -385,12 +385,18 @@ __device__ __forceinline__ void walk_two(Walker &a, Walker &b, const float4 *__r
 
 // Returns the original index of the closest triangle (-1: none); t_out gets
 // its distance (+inf on a miss) and k_out its position in the triangle array.
+// paired: the walk requests nodes i and i + 1 together (step2).
 template <bool kStats>
 __device__ __forceinline__ int32_t closest_hit(const Bvh &bvh, int set, V3 o, V3 d, float tmin, float tmax,
-                                               int32_t exclude, float &t_out, uint32_t &k_out, TraceStats &st) {
+                                               int32_t exclude, float &t_out, uint32_t &k_out, TraceStats &st,
+                                               bool paired = false) {
     Walker w;
     w.init(bvh, set, o, d, tmin, tmax, exclude);
-    while (!w.done()) w.step<kStats>(bvh.tris, st);
+    if (paired) {
+        while (!w.done()) w.step2<kStats>(bvh.tris, st);
+    } else {
+        while (!w.done()) w.step<kStats>(bvh.tris, st);
+    }
     t_out = w.t_hit();
     k_out = w.best_k;
     return w.best;

@@ -529,6 +529,10 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
                            : PM_PHOTON_REGEN;
     dv.refill = p->refill > 0 ? (uint32_t)p->refill : 32u;
     dv.force_set = p->single_link_set - 1;
+    // Paired node requests pay off on one large scene (2.65 -> 2.55 ms per
+    // iteration of the 250k-triangle scene) but not on the many small scenes
+    // of a batch, whose BVHs stay in cache (24.5 -> 25.3 ms).
+    dv.paired_walk = own_grid ? 1 : 0;
     dv.gather_mode = p->gather_mode;
     dv.sh_key = s->sh_key;
     dv.sh_surv = s->sh_surv;

@@ -41,6 +41,7 @@ struct SppmDev {
     int32_t photon_kernel;    // PM_PHOTON_* (resolved: per path or regenerating)
     uint32_t refill;          // regeneration: idle lanes that trigger a refill
     int32_t force_set;        // -1: link set by ray direction; 0..5: that set for every ray
+    int32_t paired_walk;      // 1: walks request nodes i and i + 1 together (single-scene handles)
     int32_t gather_mode;      // PM_GATHER_EXACT or PM_GATHER_STOCHASTIC
     unsigned long long *sh_key;  // stochastic hashing: smallest (depth, photon id) per entry
     uint32_t *sh_surv;           // stochastic hashing: store index of each entry's survivor
@@ -85,7 +86,8 @@ __device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p
     for (int depth = 0; depth < d.max_depth; ++depth) {
         float t;
         uint32_t kp;
-        int32_t h = closest_hit<false>(sc.bvh, ray_set(d, dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st);
+        int32_t h = closest_hit<false>(sc.bvh, ray_set(d, dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st,
+                                       d.paired_walk != 0);
         if (h < 0) break;
         V3 x = vray(org, t, dir);
         Tri tr = load_tri(sc.bvh.tris, kp);
@@ -190,7 +192,8 @@ __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, u
     float t;
     uint32_t kp;
     TraceStats st;
-    int32_t h = closest_hit<false>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp, st);
+    int32_t h = closest_hit<false>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp, st,
+                                   d.paired_walk != 0);
     if (h < 0) return false;
     V3 x = vray(P.org, t, P.dir);
     Tri tr = load_tri(sc.bvh.tris, kp);
