@@ -154,6 +154,9 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
     assert np.array_equal(h[:nc], h6) and np.array_equal(t[:nc], t6)
     h6, t6 = _gpu_trace(torch_cuda, bvh, rays, kernel=6)
     assert np.array_equal(h, h6) and np.array_equal(t, t6)
+    # the incoherent batch as the bench times it: bucketed, postponed (late 32), 64-thread workgroups
+    hb, tb = _gpu_trace(torch_cuda, bvh, inc, kernel=4, refill=32, reorder=1, block=64)
+    assert np.array_equal(h[nc:], hb) and np.array_equal(t[nc:], tb)
     h5, t5 = _gpu_trace(torch_cuda, bvh, rays[:-1], kernel=5, reorder=1, block=64)   # odd count
     assert np.array_equal(h[:-1], h5) and np.array_equal(t[:-1], t5)
     for level in (1, 2):                                      # reordered: identical
