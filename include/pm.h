@@ -176,13 +176,15 @@ typedef struct {
                            of a wavefront still searching for a leaf hit at
                            which the held leaves are tested (0..63; 0 = only
                            once no lane is searching) */
-    int32_t reorder;    /* 1: first bucket the rays by (link set, origin cell of
-                           a 16^3 grid over the scene, Morton order) and trace
-                           them in that order; 2: the same with a 32^3 grid and
-                           the signs of the two minor direction components
-                           (for incoherent batches; results are unchanged and
-                           written to each ray's own slot).  Uses a
-                           library-owned scratch of 4 B per ray. */
+    int32_t reorder;    /* 1: first bucket the rays by (origin cell of a 16^3
+                           grid over the scene in Morton order, then link set)
+                           and trace them in that order; 2: the same with a
+                           32^3 grid and the signs of the two minor direction
+                           components (for incoherent batches; results are
+                           unchanged and written to each ray's own slot).
+                           Uses a library-owned scratch of 12 B per ray, kept
+                           for later calls (grown when a call has more rays;
+                           the growth waits for the stream). */
     int32_t block;      /* threads per workgroup of every kernel but the
                            persistent one: 64, 128 or 256 (0 = default) */
     int32_t tile_width; /* > 0: the rays are the pixels of an image this
