@@ -45,7 +45,8 @@ typedef enum {
     PM_OK = 0,
     PM_ERR_ARG = -1,      /* invalid argument (nothing enqueued) */
     PM_ERR_HIP = -2,      /* HIP runtime error */
-    PM_ERR_OVERFLOW = -3, /* a fixed-capacity device buffer overflowed */
+    PM_ERR_OVERFLOW = -3, /* a fixed-capacity device buffer overflowed, or a
+                             fixed-point flux sum left the range of u64 */
     PM_ERR_STATE = -4,    /* call not valid in the handle's current state */
     PM_ERR_NOMEM = -5     /* host or device allocation failed */
 } pm_status;
@@ -227,7 +228,9 @@ typedef struct {
     uint64_t seed;
     int32_t max_eye_depth;    /* specular eye-path length cap (16) */
     int32_t max_photon_bounces; /* photon path length cap (32) */
-    int32_t fixed_shift;      /* flux fixed point: value * 2^shift (40) */
+    int32_t fixed_shift;      /* flux fixed point: value * 2^shift (40); a term
+                                 or a pixel's sum of 2^64 or more sets the
+                                 flux-overflow flag */
     int32_t store_factor;     /* photon store capacity = n_photons * factor (8) */
     int32_t record_iterations; /* > 0: record what pm_sppm_adjoint needs for
                                   up to this many iterations (8 B per pixel
@@ -297,7 +300,9 @@ PM_API int pm_sppm_iterate(pm_sppm *s, int32_t n_iter, void *stream);
  * [height][width]): tau / (pi R^2 K) + D / K.  PM_ERR_STATE if K == 0. */
 PM_API int pm_sppm_resolve(pm_sppm *s, float *image, void *stream);
 
-/* Synchronise `stream` and report sticky device errors (PM_ERR_OVERFLOW). */
+/* Synchronise `stream` and report sticky device errors: PM_ERR_OVERFLOW for a
+ * photon store overflow (raise store_factor) or a flux fixed-point overflow
+ * (lower fixed_shift); pm_last_error() says which. */
 PM_API int pm_sppm_status(pm_sppm *s, void *stream);
 
 /* Checkpoint of an SPPM handle: the per-pixel state (N, R^2, tau, D as

@@ -652,7 +652,10 @@ int sppm_status(pm_sppm *s, hipStream_t st) {
     uint32_t c[4];
     PM_HIP(hipMemcpyAsync(c, s->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     PM_HIP(hipStreamSynchronize(st));
-    if (c[1]) return set_error("photon store overflow: raise store_factor"), PM_ERR_OVERFLOW;
+    if (c[1] & 1u) return set_error("photon store overflow: raise store_factor"), PM_ERR_OVERFLOW;
+    if (c[1] & 2u)
+        return set_error("flux fixed-point overflow (a term or a pixel's sum passed 2^64): lower fixed_shift"),
+               PM_ERR_OVERFLOW;
     return PM_OK;
 }
 
@@ -835,10 +838,7 @@ int sppm_load(pm_sppm *s, const void *buf, uint64_t size, hipStream_t st) {
         PM_HIP(hipMemcpyAsync(arrays[a], in + sizeof(h) + a * pb, pb, hipMemcpyHostToDevice, st));
     if (h.n_hist > 0)
         PM_HIP(hipMemcpyAsync(s->R2_hist, in + sizeof(h) + 4 * pb, pb * (size_t)h.n_hist, hipMemcpyHostToDevice, st));
-    if (h.overflow) {
-        const uint32_t one = 1u;
-        PM_HIP(hipMemcpyAsync(s->counters + 1, &one, sizeof(one), hipMemcpyHostToDevice, st));
-    }
+    if (h.overflow) PM_HIP(hipMemcpyAsync(s->counters + 1, &h.overflow, sizeof(h.overflow), hipMemcpyHostToDevice, st));
     PM_HIP(hipStreamSynchronize(st));
     s->K = h.iterations;
     return PM_OK;

@@ -49,7 +49,7 @@ struct SppmDev {
     double *N, *R2, *tau, *D;
     float4 *store;            // [cap][2]: (x, phi), (w, path << 5 | bounce)
     uint2 *key_rank;          // [cap] exact gather: each stored photon's bucket and its rank in the bucket
-    uint32_t *counters;       // [0] photons stored, [1] overflow flag, [2] next path (regeneration)
+    uint32_t *counters;       // [0] photons stored, [1] sticky flags (1: store overflow, 2: flux overflow), [2] next path
     unsigned long long *r2max;
     uint32_t *M;
     unsigned long long *Phi;
@@ -572,6 +572,19 @@ __device__ __forceinline__ void for_each_photon_in_disc(const SppmDev &d, const 
         photons_of_bucket(d, disc_cell_bucket(gr, dc.c0, __builtin_ctz(m)), hx, hn, r2, start, sorted, f);
 }
 
+// Adds n fixed-point flux terms rint(v) to F; `bad` is set when a term or the
+// sum leaves the range of u64 (the sum itself stays the sum modulo 2^64).
+__device__ __forceinline__ void flux_add(unsigned long long &F, double v, uint32_t n, bool &bad) {
+    const double t = rint(v);
+    const bool ok = t < 0x1p63;  // v >= 0; false for NaN too
+    const unsigned long long u = ok ? (unsigned long long)t : 0ull;
+    const unsigned long long un = u * (unsigned long long)n;
+    bad |= !ok || __umul64hi(u, (unsigned long long)n) != 0ull;
+    const unsigned long long s = F + un;
+    bad |= s < F;
+    F = s;
+}
+
 // ---------------------------------------------------------------------------
 // Stochastic spatial hashing (Sec. 3.4): every photon is hashed to the entry
 // of its cell (the same grid and table as above); the entry keeps one photon,
@@ -611,6 +624,7 @@ __device__ __forceinline__ void sh_gather_elem(const SppmDev &d, const Grid &gr,
     float4 hn = d.hp_nrm[p];
     uint32_t M = 0;
     unsigned long long F = 0ull;
+    bool bad = false;
     if (__float_as_int(hn.w) >= 0) {
         float4 hx = d.hp_pos[p];
         const double wk = (double)hx.w, r2 = d.R2[p];
@@ -635,9 +649,10 @@ __device__ __forceinline__ void sh_gather_elem(const SppmDev &d, const Grid &gr,
             float c2 = (b.x * hn.x + b.y * hn.y) + b.z * hn.z;
             if (!(c2 < 0.0f)) continue;
             M += n;
-            F += (unsigned long long)n * (unsigned long long)rint((wk * (double)a.w) * d.scale);
+            flux_add(F, (wk * (double)a.w) * d.scale, n, bad);
         }
     }
+    if (bad) atomicOr(&d.counters[1], 2u);
     d.M[p] = M;
     d.Phi[p] = F;
 }
@@ -680,12 +695,13 @@ __device__ __forceinline__ void gather_wave(const SppmDev &d, const Grid &gr, in
     const double scale = d.scale;
     uint32_t M = 0u;
     unsigned long long F = 0ull;
+    bool bad = false;
     const bool coop = load >= kCoopMin;
     if (valid && !coop) {
         const double wk = (double)hx.w;
         auto add = [&](const float4 &a, const float4 &) {
             M++;
-            F += (unsigned long long)rint((wk * (double)a.w) * scale);
+            flux_add(F, (wk * (double)a.w) * scale, 1u, bad);
         };
         for (uint32_t m = dc.uniq; m != 0u; m &= m - 1u)
             photons_of_bucket(d, disc_cell_bucket(gr, dc.c0, __builtin_ctz(m)), hx, hn, r2, start, sorted, add);
@@ -705,6 +721,7 @@ __device__ __forceinline__ void gather_wave(const SppmDev &d, const Grid &gr, in
         const double wk = (double)xl.w;
         uint32_t m = 0u;
         unsigned long long f = 0ull;
+        bool fbad = false;
         for (uint32_t bits = uniql; bits != 0u; bits &= bits - 1u) {
             const uint32_t hb = d.table_off + disc_cell_bucket(gr, c0l, __builtin_ctz(bits));
             const uint32_t q1 = start[hb + 1];
@@ -717,21 +734,26 @@ __device__ __forceinline__ void gather_wave(const SppmDev &d, const Grid &gr, in
                     const float c2 = (b.x * nl.x + b.y * nl.y) + b.z * nl.z;
                     if (c2 < 0.0f) {
                         m++;
-                        f += (unsigned long long)rint((wk * (double)a.w) * scale);
+                        flux_add(f, (wk * (double)a.w) * scale, 1u, fbad);
                     }
                 }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
             m += __shfl_xor(m, off);
-            f += __shfl_xor(f, off);
+            const unsigned long long s = f + __shfl_xor(f, off);
+            fbad |= s < f;  // a partial sum passing 2^64 wraps in some lane
+            f = s;
         }
+        const bool any_bad = __ballot(fbad) != 0ull;
         if ((int)lane == L) {
             M = m;
             F = f;
+            bad = any_bad;
         }
     }
     if (in) {
+        if (bad) atomicOr(&d.counters[1], 2u);
         d.M[p] = M;
         d.Phi[p] = F;
     }

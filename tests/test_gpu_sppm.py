@@ -200,6 +200,26 @@ def test_degenerate_cases(torch_cuda, oracle_lib):
     assert np.all(img == 0)
 
 
+def test_flux_fixed_point_overflow_is_reported(torch_cuda):
+    """A light so bright that each flux term at 2^52 fixed point passes 2^64:
+    the range query flags it and pm_sppm_status reports PM_ERR_OVERFLOW
+    naming fixed_shift; the same scene at 2^20 is clean."""
+    _log("case: flux fixed-point overflow")
+    import dataclasses
+    sc = scenes.box_scene(16, 16)
+    sc = dataclasses.replace(sc, mat_Le=np.where(sc.mat_Le > 0, np.float32(1e12), sc.mat_Le).astype(np.float32))
+    for shift, bad in ((52, True), (20, False)):
+        s = api.Sppm(sc, api.sppm_params(1 << 12, r0=0.1, fixed_shift=shift))
+        s.iterate(1)
+        if bad:
+            with pytest.raises(api.PMError) as e:
+                s.status()
+            assert e.value.code == api.PM_ERR_OVERFLOW and "fixed_shift" in str(e.value)
+        else:
+            s.status()
+        s.destroy()
+
+
 def test_photon_store_overflow_is_reported(torch_cuda):
     _log("case: photon store overflow")
     sc = scenes.furnace_scene(rho=0.9, width=8, height=8)
