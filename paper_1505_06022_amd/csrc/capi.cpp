@@ -5,12 +5,23 @@
 #include <new>
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "bvh_build.h"
 #include "pm.h"
 #include "runtime.h"
 #include "sppm.h"
 
 namespace pm {
+
+// A roctx range around each entry point that enqueues device work (host
+// time of the call; visible with rocprofv3 --marker-trace).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 static thread_local std::string g_err;
 
@@ -98,6 +109,7 @@ int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n
 
 int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
                  void *stream, pm_bvh **out) {
+    pm::TraceRange range_("pm_build_bvh");
     PM_GUARD({
         if (!tri_verts || !out) return pm::set_error("tri_verts and out must not be NULL"), PM_ERR_ARG;
         *out = nullptr;
@@ -176,6 +188,7 @@ int pm_bvh_get_info(const pm_bvh *b, pm_bvh_info *info) {
 
 int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
                      const pm_trace_opts *opts, void *stream) {
+    pm::TraceRange range_("pm_trace_rays_ex");
     PM_GUARD({
         if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
         if (n < 0) return pm::set_error("n must be >= 0"), PM_ERR_ARG;
@@ -221,6 +234,7 @@ int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit,
 }
 
 int pm_sppm_create(const pm_scene_desc *desc, const pm_sppm_params *params, void *stream, pm_sppm **out) {
+    pm::TraceRange range_("pm_sppm_create");
     PM_GUARD({
         if (!out) return pm::set_error("out must not be NULL"), PM_ERR_ARG;
         *out = nullptr;
@@ -231,10 +245,12 @@ int pm_sppm_create(const pm_scene_desc *desc, const pm_sppm_params *params, void
 int pm_sppm_destroy(pm_sppm *s) { PM_GUARD({ return pm::sppm_destroy(s); }) }
 
 int pm_sppm_iterate(pm_sppm *s, int32_t n_iter, void *stream) {
+    pm::TraceRange range_("pm_sppm_iterate");
     PM_GUARD({ return pm::sppm_iterate(s, n_iter, (hipStream_t)stream); })
 }
 
 int pm_sppm_resolve(pm_sppm *s, float *image, void *stream) {
+    pm::TraceRange range_("pm_sppm_resolve");
     PM_GUARD({ return pm::sppm_resolve(s, image, (hipStream_t)stream); })
 }
 
@@ -244,6 +260,7 @@ int pm_sppm_get_views(pm_sppm *s, pm_sppm_views *v) { PM_GUARD({ return pm::sppm
 
 int pm_sppm_adjoint(pm_sppm *s, const float *dloss_dimage, const int32_t *param_mats, int32_t n_par, double *grad,
                     void *stream) {
+    pm::TraceRange range_("pm_sppm_adjoint");
     PM_GUARD({ return pm::sppm_adjoint(s, dloss_dimage, param_mats, n_par, grad, (hipStream_t)stream); })
 }
 
@@ -256,6 +273,7 @@ int pm_sppm_load(pm_sppm *s, const void *buf, uint64_t size, void *stream) {
 }
 
 int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream) {
+    pm::TraceRange range_("pm_render");
     PM_GUARD({
         if (K < 1 || !image) return pm::set_error("K must be >= 1 and image non-NULL"), PM_ERR_ARG;
         int rc = pm::sppm_validate(desc, params);
@@ -273,6 +291,7 @@ int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K
 
 int pm_batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
                     const pm_batch_opts *opts, void *stream, pm_batch **out) {
+    pm::TraceRange range_("pm_batch_create");
     PM_GUARD({
         if (!out) return pm::set_error("out must not be NULL"), PM_ERR_ARG;
         *out = nullptr;
@@ -283,10 +302,12 @@ int pm_batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *con
 int pm_batch_destroy(pm_batch *b) { PM_GUARD({ return pm::batch_destroy(b); }) }
 
 int pm_batch_iterate(pm_batch *b, int32_t n_iter, void *stream) {
+    pm::TraceRange range_("pm_batch_iterate");
     PM_GUARD({ return pm::batch_iterate(b, n_iter, (hipStream_t)stream); })
 }
 
 int pm_batch_resolve(pm_batch *b, float *const *images, void *stream) {
+    pm::TraceRange range_("pm_batch_resolve");
     PM_GUARD({ return pm::batch_resolve(b, images, (hipStream_t)stream); })
 }
 
@@ -300,6 +321,7 @@ int pm_batch_get_views(pm_batch *b, int32_t scene, pm_sppm_views *v) {
 
 int pm_render_batch(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
                     int32_t K, float *const *images, const pm_batch_opts *opts, void *stream) {
+    pm::TraceRange range_("pm_render_batch");
     PM_GUARD({
         if (K < 1 || !images) return pm::set_error("K must be >= 1 and images non-NULL"), PM_ERR_ARG;
         pm_batch *b = nullptr;
