@@ -6,7 +6,7 @@ SAH-binned BVH (32 bins, <= 4 triangles per leaf), 1920x1080 coherent pinhole
 rays plus 2^21 incoherent rays.  One step = closest-hit traversal of all
 4,170,752 rays: two trace calls, inputs resident in HBM.  The camera batch is
 traced as packets, one wavefront per 8x8 pixel tile (--coherent), the
-incoherent batch after bucketing by (link set, origin cell) with postponed
+incoherent batch after bucketing by (origin cell, link set) with postponed
 leaf tests (--incoherent); every
 option listed in KERNEL_VARIANTS gives identical results and is also timed.
 The JSON line reports Mrays/s, the traversal's algorithmic-bytes roofline,
@@ -136,7 +136,7 @@ def traversal_bench(args, torch, api, scenes):
     ri = torch.from_numpy(inc).to(dev)
     batches = [rc, ri]
     # camera rays are traced in pixel order; the incoherent batch is first
-    # bucketed by (link set, origin cell) -- an option of the trace call
+    # bucketed by (origin cell, link set) -- an option of the trace call
     table = dict(KERNEL_VARIANTS)
     trace_kw = [_kw_for(table[args.coherent], 0), _kw_for(table[args.incoherent], 1)]
     outs = [(torch.empty(len(r), dtype=torch.int32, device=dev), torch.empty(len(r), dtype=torch.float32, device=dev))
