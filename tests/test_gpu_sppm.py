@@ -200,6 +200,27 @@ def test_degenerate_cases(torch_cuda, oracle_lib):
     assert np.all(img == 0)
 
 
+def test_determinism_across_schedules(torch_cuda):
+    """Integer counts and fixed-point sums make the result independent of
+    thread order: repeated runs and every photon schedule give bit-identical
+    per-pixel state and images (no oracle involved)."""
+    _log("case: determinism across runs and photon schedules")
+    sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
+    out = []
+    for kw in (dict(), dict(), dict(photon_kernel=1), dict(photon_kernel=2, refill=1), dict(photon_kernel=3),
+               dict(photon_kernel=3, pass_threads=333, passes=2)):
+        s = api.Sppm(sc, api.sppm_params(1 << 13, r0=0.03, seed=21, **kw))
+        s.iterate(3)
+        img = s.resolve().cpu().numpy()
+        torch_cuda.cuda.synchronize()
+        v = s.views()
+        out.append([img] + [v[k].cpu().numpy().copy() for k in ("N", "R2", "tau", "D", "M", "Phi")])
+        s.destroy()
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_flux_fixed_point_overflow_is_reported(torch_cuda):
     """A light so bright that each flux term at 2^52 fixed point passes 2^64:
     the range query flags it and pm_sppm_status reports PM_ERR_OVERFLOW
