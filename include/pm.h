@@ -184,8 +184,10 @@ typedef struct {
                            components (for incoherent batches; results are
                            unchanged and written to each ray's own slot).
                            Uses a library-owned scratch of 12 B per ray, kept
-                           for later calls (grown when a call has more rays;
-                           the growth waits for the stream). */
+                           with the BVH for later calls (grown when a call has
+                           more rays; the growth waits for the call's stream).
+                           Reordered calls on one BVH share that scratch, so
+                           they must not overlap on different streams. */
     int32_t block;      /* threads per workgroup of every kernel but the
                            persistent one: 64, 128 or 256 (0 = default) */
     int32_t tile_width; /* > 0: the rays are the pixels of an image this
