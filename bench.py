@@ -504,7 +504,10 @@ def main():
         del src, dst
     tb = traversal_bench(args, torch, api, scenes)
     out = {
-        "metric": "Mrays/s traversal (closest hit, MTBVH)",
+        "metric": "Mrays/s traversal + SPPM photons/s; fwd+adjoint vs fwd time at matched RMSE",
+        # value: the first part (closest-hit traversal, MTBVH); the other two are
+        # sppm.photons_per_s and adjoint.ratio_fwd_plus_adj_over_fwd below
+        "value_part": "Mrays/s traversal (closest hit, MTBVH)",
         "value": round(tb["n_rays"] / (tb["step_ms"] * 1e-3) / 1e6, 2),
         "unit": "Mrays/s",
         "n_gpus": 1,
