@@ -31,15 +31,28 @@ __device__ __forceinline__ int32_t lcg_step(int32_t s, int32_t a, int32_t q, int
     return t < 0 ? t + m : t;
 }
 
+// s / m rounded to nearest float, for a state 0 < s < m of one of the four
+// generators: the product with the rounded reciprocal, corrected once by its
+// exact fma residual (Markstein's division, IBM J. Res. Dev. 1990). For these
+// four moduli it equals the IEEE quotient for every state (checked
+// exhaustively on the host), in 3 instructions instead of the ~10 of a full
+// division.
+__device__ __forceinline__ float div_by_modulus(int32_t s, float m, float inv_m) {
+    float x = (float)s;
+    float q0 = x * inv_m;
+    float r = __builtin_fmaf(-q0, m, x);
+    return __builtin_fmaf(r, inv_m, q0);
+}
+
 __device__ __forceinline__ float rng_next(Rng &g) {
     g.s0 = lcg_step(g.s0, 3423, 1225, 1112, 4194287);
     g.s1 = lcg_step(g.s1, 2646, 1585, 367, 4194277);
     g.s2 = lcg_step(g.s2, 1707, 2457, 92, 4194191);
     g.s3 = lcg_step(g.s3, 1999, 2098, 265, 4194167);
-    float f0 = (float)g.s0 / 4194287.0f;
-    float f1 = (float)g.s1 / 4194277.0f;
-    float f2 = (float)g.s2 / 4194191.0f;
-    float f3 = (float)g.s3 / 4194167.0f;
+    float f0 = div_by_modulus(g.s0, 4194287.0f, 1.0f / 4194287.0f);
+    float f1 = div_by_modulus(g.s1, 4194277.0f, 1.0f / 4194277.0f);
+    float f2 = div_by_modulus(g.s2, 4194191.0f, 1.0f / 4194191.0f);
+    float f3 = div_by_modulus(g.s3, 4194167.0f, 1.0f / 4194167.0f);
     float x = ((f0 - f1) + f2) - f3;
     float u = x - floorf(x);
     return u >= 1.0f ? 0x1.fffffep-1f : u;
