@@ -466,7 +466,9 @@ int build_bvh_gpu(const float *verts_h, const uint32_t *mats_h, int64_t n_tri, i
     // 5-6. records
     const uint32_t n_nodes = (uint32_t)root_sz;
     PM_HIP(hipGetDevice(&b->device));
-    PM_HIP(hipMalloc(&b->d_nodes, sizeof(uint4) * kLinkSets * (size_t)n_nodes));
+    // zeroed pad nodes after the six arrays (a packet walk reads the node after the one it visits)
+    PM_HIP(hipMalloc(&b->d_nodes, sizeof(uint4) * (kLinkSets * (size_t)n_nodes + pm::kPadNodes)));
+    PM_HIP(hipMemsetAsync(b->d_nodes + kLinkSets * (size_t)n_nodes, 0, sizeof(uint4) * pm::kPadNodes, s));
     PM_HIP(hipMalloc(&b->d_tris, sizeof(float4) * 3 * (size_t)n));
     PM_HIP(hipMalloc(&b->d_next, 64));
     PM_HIP(hipMemsetAsync(stats, 0, sizeof(TreeStats), s));

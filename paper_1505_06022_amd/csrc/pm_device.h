@@ -175,7 +175,7 @@ __device__ __forceinline__ int link_set(V3 d) {
 }
 
 struct Bvh {
-    const uint4 *nodes;   // [6][n_nodes] 16-byte nodes
+    const uint4 *nodes;   // [6][n_nodes] 16-byte nodes, then a pad node
     const float4 *tris;   // [n_tri][3] float4
     uint32_t n_nodes;
     float qlo[3], qstep[3];  // node box grid: coordinate = qlo + q * qstep
@@ -361,20 +361,38 @@ struct Walker {
 // node index, the link words and so every branch are uniform across the wave,
 // and all lanes read the same node and triangle records.
 template <bool kStats>
+__device__ __forceinline__ uint32_t packet_visit(Walker &w, const uint4 &q, uint32_t i,
+                                                 const float4 *__restrict__ tris, TraceStats &st) {
+    const uint32_t link = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.w);
+    const bool hit = w.box_hit(q);
+    if (kStats) st.boxes++;
+    if ((link >> 31) != 0u) {
+        if (hit) w.leaf_tris<kStats>(tris, link, st);
+        return i + 1;
+    }
+    return __ballot(hit) != 0ull ? i + 1 : link;
+}
+
+// Nodes a packet walk requests at once (measured: 2 beats 1, 3, 4 and 5).
+constexpr int kPacketRun = 2;
+
+template <bool kStats>
 __device__ __forceinline__ void walk_packet(Walker &w, const uint4 *__restrict__ nodes, uint32_t n,
                                             const float4 *__restrict__ tris, TraceStats &st) {
+    constexpr int kRun = kPacketRun;
     uint32_t i = 0;
     while (i < n) {
-        const uint4 q = nodes[i];
-        const uint32_t link = (uint32_t)__builtin_amdgcn_readfirstlane((int)q.w);
-        const bool hit = w.box_hit(q);
-        if (kStats) st.boxes++;
-        if ((link >> 31) != 0u) {
-            if (hit) w.leaf_tris<kStats>(tris, link, st);
-            ++i;
-        } else {
-            i = __ballot(hit) != 0ull ? i + 1 : link;
-        }
+        // nodes i .. i + kRun - 1 come in one request: each is the next node
+        // after a hit or a leaf, which then costs no further round trip
+        const uint4 *p = nodes + i;  // in bounds: the node arrays end with kRun - 1 pad nodes
+        uint4 q[kRun];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) q[k] = p[k];
+        uint32_t cur = packet_visit<kStats>(w, q[0], i, tris, st);
+#pragma unroll
+        for (int k = 1; k < kRun; ++k)
+            if (cur == i + (uint32_t)k && cur < n) cur = packet_visit<kStats>(w, q[k], cur, tris, st);
+        i = cur;
     }
     w.i = n;
 }

@@ -24,6 +24,10 @@ int hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return pm::hip_fail(e_, #call); \
     } while (0)
 
+// Zeroed nodes after a BVH's six node arrays: a packet walk reads the node
+// after the one it visits.
+constexpr size_t kPadNodes = 1;
+
 }  // namespace pm
 
 struct pm_bvh {
@@ -32,7 +36,7 @@ struct pm_bvh {
     double sah_cost = 0.0, build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float qlo[3] = {0, 0, 0}, qstep[3] = {1, 1, 1};
-    uint4 *d_nodes = nullptr;   // [6][n_nodes] 16-byte nodes
+    uint4 *d_nodes = nullptr;   // [6][n_nodes] 16-byte nodes, then kPadNodes zeroed nodes
     float4 *d_tris = nullptr;   // [n_tri][3]
     uint32_t *d_next = nullptr; // work counter of the persistent traversal kernel
     uint32_t *d_perm = nullptr; // ray order of the reordering traversal (perm_cap entries)

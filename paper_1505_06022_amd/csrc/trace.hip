@@ -7,6 +7,8 @@
 
 namespace {
 
+static_assert(pmd::kPacketRun >= 1 && pmd::kPacketRun - 1 <= (int)pm::kPadNodes, "packet reads past the pad nodes");
+
 constexpr int kTraceBlock = 256;
 constexpr int kDefaultWalkBlock = 256;  // workgroup of the one-ray-per-lane kernels
 constexpr uint32_t kNoRay = 0xffffffffu;
@@ -296,7 +298,9 @@ int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b) {
     for (int64_t k = 0; k < h.n_tri; ++k) b->pos_of[h.tris[(size_t)k * kTriWords + 9]] = (int32_t)k;
     PM_HIP(hipGetDevice(&b->device));
     size_t nb = h.nodes.size() * sizeof(uint32_t), tb = h.tris.size() * sizeof(uint32_t);
-    PM_HIP(hipMalloc(&b->d_nodes, nb));
+    // zeroed pad nodes after the six arrays (a packet walk reads the node after the one it visits)
+    PM_HIP(hipMalloc(&b->d_nodes, nb + sizeof(uint4) * pm::kPadNodes));
+    PM_HIP(hipMemsetAsync((char *)b->d_nodes + nb, 0, sizeof(uint4) * pm::kPadNodes, s));
     PM_HIP(hipMalloc(&b->d_tris, tb));
     PM_HIP(hipMalloc(&b->d_next, 64));
     PM_HIP(hipMemcpyAsync(b->d_nodes, h.nodes.data(), nb, hipMemcpyHostToDevice, s));
