@@ -443,6 +443,30 @@ def achievable_bandwidth(torch):
     return {"copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1), "read_GBps": round(nb / (read_ms * 1e-3) / 1e9, 1)}
 
 
+def dependent_read_rate(torch, api, n_lanes, steps, log2_rows=24):
+    """Achievable rate of dependent random 16-byte reads (pm_probe_chase):
+    n_lanes chains of `steps` reads each over 2^log2_rows random rows (256 MiB
+    by default, about the size of the soup's BVH): the access pattern of the
+    incoherent walk without its arithmetic.  Best of 5."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    rows = torch.randint(-2**31, 2**31 - 1, (1 << log2_rows, 4), dtype=torch.int32, device="cuda", generator=g)
+    out = torch.empty(n_lanes, dtype=torch.int32, device="cuda")
+    api.probe_chase(rows, steps, n_lanes, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = 1e30
+    for _ in range(5):
+        e0.record()
+        api.probe_chase(rows, steps, n_lanes, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del rows, out
+    rate = n_lanes * steps / (best * 1e-3)
+    return {"rows_bytes": 16 << log2_rows, "lanes": n_lanes, "steps": steps, "ms": round(best, 4),
+            "reads_per_s": round(rate, 1), "GBps": round(16 * rate / 1e9, 1)}
+
+
 def cpu_baseline(tb, scenes):
     import oracle
     nth = _cpu_threads()
@@ -547,6 +571,18 @@ def main():
     ach = achievable_bandwidth(torch)
     best = max(ach["copy_GBps"], ach["read_GBps"])
     out["roofline"]["achievable"] = dict(ach, frac=round(tb["achieved"] / best, 4))
+    # the incoherent walk (node visits per second, bucketing included) against chains of dependent random
+    # reads of the same length per lane: over a BVH-sized buffer (reads served by the Infinity Cache and
+    # HBM) and over 4 MiB (one XCD's L2 holds it: the rate of a walk whose every node read hits L2)
+    vn_inc, _, n_inc = tb["per_batch"][1]
+    steps = max(1, int(round(vn_inc / n_inc)))
+    node_rate = vn_inc / (float(tb["kern_ms"][:, 1].mean()) * 1e-3)
+    far = dependent_read_rate(torch, api, n_inc, steps, log2_rows=24)
+    near = dependent_read_rate(torch, api, n_inc, steps, log2_rows=18)
+    out["roofline"]["achievable"]["dependent_reads"] = {
+        "incoherent_node_visits_per_s": round(node_rate, 1), "random_256MiB": far, "random_4MiB": near,
+        "frac_of_4MiB": round(node_rate / near["reads_per_s"], 4),
+        "ratio_to_256MiB": round(node_rate / far["reads_per_s"], 3)}
     if not args.no_sppm:
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),

@@ -415,6 +415,25 @@ PM_API int pm_batch_get_views(pm_batch *b, int32_t scene, pm_sppm_views *v);
 PM_API int pm_render_batch(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n_scenes,
                            int32_t K, float *const *images, const pm_batch_opts *opts, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Memory microbenchmark for the traversal's roofline: dependent random reads,
+ * the access pattern of an incoherent stackless walk (Sec. 3.1: each node
+ * visited decides the next) without its arithmetic.  rows: device buffer of
+ * 2^log2_rows rows of four uint32 (16 bytes, the size of a node record), any
+ * contents; random contents give random chains.  Lane l (0 <= l < n_lanes)
+ * starts at row (l * 0x9E3779B1) & mask, mask = 2^log2_rows - 1, and reads
+ * `steps` rows: after row (x, y, z, w) it moves to row (x ^ salt) & mask with
+ * salt = l * 0x85EBCA77 (uint32 arithmetic).  out (device, n_lanes uint32,
+ * caller-owned) gets, per lane, the XOR of every word it read.  One wavefront
+ * per workgroup.  Asynchronous on stream; nothing is allocated.
+ * PM_ERR_ARG: NULL rows or out, log2_rows outside [1, 28], n_lanes outside
+ * [1, 2^31), steps < 1. */
+PM_API int pm_probe_chase(const uint32_t *rows, int32_t log2_rows, int64_t n_lanes, int32_t steps, uint32_t *out,
+                          void *stream);
+
 #ifdef __cplusplus
 }
 #endif

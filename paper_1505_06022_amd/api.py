@@ -22,7 +22,7 @@ EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host
            "pm_bvh_get_info", "pm_bvh_download", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
            "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
-           "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch"]
+           "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch", "pm_probe_chase"]
 
 
 class PMError(RuntimeError):
@@ -133,6 +133,7 @@ def lib() -> C.CDLL:
         L.pm_batch_get_info.argtypes = [P, P]
         L.pm_batch_get_views.argtypes = [P, I32, P]
         L.pm_render_batch.argtypes = [P, P, I32, I32, P, P, P]
+        L.pm_probe_chase.argtypes = [P, I32, I64, I32, P, P]
         _lib = L
     return _lib
 
@@ -265,6 +266,21 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
         o.counters = None if counters is None else counters.data_ptr()
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t
+
+
+def probe_chase(rows, steps: int, n_lanes: int, out=None, stream=None):
+    """Dependent random 16-byte reads (memory microbenchmark).  rows: int32 or
+    uint32-valued cuda tensor of 2^k x 4 words; returns out (int32 [n_lanes]),
+    each lane's XOR of the words it read."""
+    import torch
+    assert rows.is_cuda and rows.is_contiguous() and rows.dtype == torch.int32 and rows.dim() == 2 \
+        and rows.shape[1] == 4
+    nr = rows.shape[0]
+    assert nr > 1 and nr & (nr - 1) == 0, "the row count must be a power of two"
+    if out is None:
+        out = torch.empty(n_lanes, dtype=torch.int32, device=rows.device)
+    _check(lib().pm_probe_chase(_ptr(rows), nr.bit_length() - 1, n_lanes, steps, _ptr(out), _stream(stream)))
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libpm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["capi.cpp", "bvh_build.cpp", "trace.hip", "sppm.hip", "batch.hip", "lbvh.hip"]
+SOURCES = ["capi.cpp", "bvh_build.cpp", "trace.hip", "sppm.hip", "batch.hip", "lbvh.hip", "probe.hip"]
 
 ARCH = "gfx950"
 

@@ -337,3 +337,15 @@ int pm_render_batch(const pm_scene_desc *const *descs, const pm_sppm_params *con
 }
 
 }  // extern "C"
+
+int pm_probe_chase(const uint32_t *rows, int32_t log2_rows, int64_t n_lanes, int32_t steps, uint32_t *out,
+                   void *stream) {
+    PM_GUARD({
+        if (!rows || !out) return pm::set_error("rows and out must not be NULL"), PM_ERR_ARG;
+        if (log2_rows < 1 || log2_rows > 28) return pm::set_error("log2_rows must be in [1, 28]"), PM_ERR_ARG;
+        if (n_lanes < 1 || n_lanes >= (int64_t(1) << 31))
+            return pm::set_error("n_lanes must be in [1, 2^31)"), PM_ERR_ARG;
+        if (steps < 1) return pm::set_error("steps must be at least 1"), PM_ERR_ARG;
+        return pm::launch_chase(rows, log2_rows, (uint32_t)n_lanes, (uint32_t)steps, out, (hipStream_t)stream);
+    })
+}

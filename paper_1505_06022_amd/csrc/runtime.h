@@ -52,6 +52,10 @@ struct Bvh;
 
 namespace pm {
 
+// Dependent random reads over 2^log2_rows 16-byte rows (memory microbenchmark).
+int launch_chase(const uint32_t *rows, int32_t log2_rows, uint32_t n_lanes, uint32_t steps, uint32_t *out,
+                 hipStream_t s);
+
 // Device view of a BVH handle (node/triangle pointers and the box grid).
 pmd::Bvh make_device_bvh(const pm_bvh *b);
 

@@ -93,6 +93,11 @@ def test_host_validation_errors_without_gpu():
     n = C.c_uint64(0)
     assert L.pm_sppm_save(None, None, C.byref(n), None) == api.PM_ERR_ARG
     assert L.pm_sppm_load(None, None, 0, None) == api.PM_ERR_ARG
+    one = C.c_void_p(16)  # never dereferenced: every call below fails validation first
+    assert L.pm_probe_chase(None, 4, 1, 1, one, None) == api.PM_ERR_ARG
+    assert L.pm_probe_chase(one, 4, 1, 1, None, None) == api.PM_ERR_ARG
+    for log2_rows, n_lanes, steps in ((0, 1, 1), (29, 1, 1), (4, 0, 1), (4, 1 << 31, 1), (4, 1, 0)):
+        assert L.pm_probe_chase(one, log2_rows, n_lanes, steps, one, None) == api.PM_ERR_ARG
 
 
 def _py_traverse(nodes, tris, info, ray, s):

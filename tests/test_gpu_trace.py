@@ -189,3 +189,24 @@ def test_trace_option_errors(torch_cuda):
             api.trace_rays(bvh, r, **kw)
         assert e.value.code == api.PM_ERR_ARG, kw
     bvh.destroy()
+
+
+def test_probe_chase_matches_host(torch_cuda):
+    """The memory microbenchmark walks the chains its header defines (host model, several tiles and a ragged tail)."""
+    _log("case: probe chase 2^10 rows, 1000 lanes, 37 steps")
+    rng = np.random.default_rng(5)
+    rows = rng.integers(-2**31, 2**31, size=(1 << 10, 4), dtype=np.int64).astype(np.int32)
+    n_lanes, steps = 1000, 37
+    got = api.probe_chase(torch_cuda.from_numpy(rows).cuda(), steps, n_lanes).cpu().numpy().view(np.uint32)
+    u = rows.view(np.uint32)
+    mask = np.uint32((1 << 10) - 1)
+    lane = np.arange(n_lanes, dtype=np.uint64)
+    r = ((lane * 0x9E3779B1) & 0xFFFFFFFF).astype(np.uint32) & mask
+    salt = ((lane * 0x85EBCA77) & 0xFFFFFFFF).astype(np.uint32)
+    acc = np.zeros(n_lanes, dtype=np.uint32)
+    for _ in range(steps):
+        q = u[r]
+        acc ^= (q[:, 0] ^ q[:, 1]) ^ (q[:, 2] ^ q[:, 3])
+        r = (q[:, 0] ^ salt) & mask
+    assert np.array_equal(got, acc)
+
