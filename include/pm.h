@@ -99,10 +99,10 @@ typedef struct {
     float grid_step[3];
 } pm_bvh_info;
 
-/* Build the BVH on the host (top-down binned SAH, Sec. 3.1 "standard top-down
- * sweeping algorithm ... based on SAH"), thread it six times with children
- * pre-sorted along +x,-x,+y,-y,+z,-z (the multiple-threaded BVH), and copy it
- * to the device on `stream`.
+/* Build the BVH on the host (top-down binned SAH; Sec. 3.1 builds top-down
+ * with the SAH on the CPU), thread it six times with children pre-sorted
+ * along +x,-x,+y,-y,+z,-z (the multiple-threaded BVH), and copy it to the
+ * device on `stream`.
  *   tri_verts  host, float32 [n_tri][3][3] vertex positions (finite)
  *   tri_mat    host, uint32 [n_tri] material ids (may be NULL: all 0)
  *   opts       may be NULL (defaults above)

@@ -318,8 +318,8 @@ __device__ __forceinline__ void photon_regen_range(const SppmDev &d, uint32_t k,
 // ---------------------------------------------------------------------------
 // Photon paths one bounce per pass (Sec. 3.3 as the paper schedules it): a
 // fixed pool of threads, each owning one slot; every launch (a pass) moves the
-// path of each slot by exactly one bounce, so a thread stores at most one
-// photon per pass.  A slot whose path was killed or left the scene takes the
+// path of each slot by exactly one bounce, so no thread deposits more than
+// a single photon in a pass.  A slot whose path was killed or left the scene takes the
 // next path index in the following pass and traces that path's first segment
 // there.  A slot's path state lives in memory between passes.
 // ---------------------------------------------------------------------------
