@@ -201,6 +201,34 @@ typedef struct {
 PM_API int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
                      const pm_trace_opts *opts, void *stream);
 
+/* One batch of rays for pm_trace_rays_multi: arguments as for
+ * pm_trace_rays_ex (opts may be NULL). */
+typedef struct {
+    uint32_t size;             /* sizeof(pm_trace_batch) */
+    const float *rays;         /* device, float32 [n][8] */
+    int64_t n;
+    int32_t *hit;              /* device, int32 [n] */
+    float *t;                  /* device, float32 [n] */
+    const pm_trace_opts *opts; /* may be NULL */
+} pm_trace_batch;
+
+#define PM_MAX_TRACE_BATCHES 8
+
+/* Several ray batches on one BVH (each as pm_trace_rays_ex would trace it),
+ * run concurrently: batch 0 on `stream`, batch k > 0 on a stream the BVH
+ * handle owns, which first waits for the work already enqueued on `stream`;
+ * `stream` then waits for every batch, so work enqueued on it after the call
+ * sees all results.  Kernels of different batches share the device (one
+ * batch's last wavefronts leave room for another's), so the call takes less
+ * time than the batches one after another; results are the same.  The
+ * batches' output arrays must not overlap.  At most one batch may use the
+ * handle's scratch (reorder != 0 or the persistent kernel).  Calls on one
+ * handle must be on the same stream or not overlap (the handle's streams are
+ * shared).  Errors: PM_ERR_ARG for n_batches outside [1, PM_MAX_TRACE_BATCHES],
+ * NULL bvh or batches, a batch that pm_trace_rays_ex would reject, or two
+ * batches using the scratch; all checked before anything is enqueued. */
+PM_API int pm_trace_rays_multi(const pm_bvh *bvh, int32_t n_batches, const pm_trace_batch *batches, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Stochastic progressive photon mapping (Sec. 2)                      */
 /* ------------------------------------------------------------------ */

@@ -22,7 +22,8 @@ EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host
            "pm_bvh_get_info", "pm_bvh_download", "pm_trace_rays", "pm_trace_rays_ex", "pm_sppm_create", "pm_sppm_destroy",
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
            "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
-           "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch", "pm_probe_chase"]
+           "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch", "pm_probe_chase",
+           "pm_trace_rays_multi"]
 
 
 class PMError(RuntimeError):
@@ -52,6 +53,12 @@ class TraceOpts(C.Structure):
 
 
 TRACE_AUTO, TRACE_PER_RAY, TRACE_PERSISTENT, TRACE_PAIRED, TRACE_POSTPONED, TRACE_TWO_RAYS, TRACE_PACKET = range(7)
+MAX_TRACE_BATCHES = 8
+
+
+class TraceBatch(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("rays", C.c_void_p), ("n", C.c_int64), ("hit", C.c_void_p), ("t", C.c_void_p),
+                ("opts", C.c_void_p)]
 
 
 class SceneDesc(C.Structure):
@@ -134,6 +141,7 @@ def lib() -> C.CDLL:
         L.pm_batch_get_views.argtypes = [P, I32, P]
         L.pm_render_batch.argtypes = [P, P, I32, I32, P, P, P]
         L.pm_probe_chase.argtypes = [P, I32, I64, I32, P, P]
+        L.pm_trace_rays_multi.argtypes = [P, I32, P, P]
         _lib = L
     return _lib
 
@@ -266,6 +274,39 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
         o.counters = None if counters is None else counters.data_ptr()
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t
+
+
+def _trace_opts(link_set=-1, counters=None, kernel=0, refill=0, reorder=0, block=0, tile_width=0) -> TraceOpts:
+    o = TraceOpts()
+    o.size, o.link_set, o.kernel, o.refill = C.sizeof(TraceOpts), link_set, kernel, refill
+    o.reorder, o.block, o.tile_width = int(reorder), int(block), int(tile_width)
+    o.counters = None if counters is None else counters.data_ptr()
+    return o
+
+
+def trace_rays_multi(bvh: Bvh, batches, stream=None):
+    """Several ray batches traced concurrently (pm_trace_rays_multi).  batches:
+    list of dicts with "rays" (float32 cuda [n, 8]), optional "hit" / "t"
+    outputs, and any pm_trace_opts field as in trace_rays.  Returns [(hit, t)]."""
+    import torch
+    keep, out = [], []
+    arr = (TraceBatch * len(batches))()
+    for k, bt in enumerate(batches):
+        bt = dict(bt)
+        rays = bt.pop("rays")
+        assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
+        n = rays.shape[0]
+        hit = bt.pop("hit", None)
+        t = bt.pop("t", None)
+        hit = torch.empty(n, dtype=torch.int32, device=rays.device) if hit is None else hit
+        t = torch.empty(n, dtype=torch.float32, device=rays.device) if t is None else t
+        o = _trace_opts(**bt)
+        keep.append(o)
+        arr[k].size, arr[k].rays, arr[k].n = C.sizeof(TraceBatch), _ptr(rays), n
+        arr[k].hit, arr[k].t, arr[k].opts = _ptr(hit), _ptr(t), C.cast(C.pointer(o), C.c_void_p)
+        out.append((hit, t))
+    _check(lib().pm_trace_rays_multi(bvh.h, len(batches), arr, _stream(stream)))
+    return out
 
 
 def probe_chase(rows, steps: int, n_lanes: int, out=None, stream=None):

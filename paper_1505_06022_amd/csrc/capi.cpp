@@ -186,46 +186,80 @@ int pm_bvh_get_info(const pm_bvh *b, pm_bvh_info *info) {
     })
 }
 
+// Host validation of one batch (pm_trace_rays_ex's rules); fills a.
+static int parse_trace(const float *rays, int64_t n, int32_t *hit, float *t, const pm_trace_opts *opts,
+                       pm::TraceArgs &a) {
+    if (n < 0) return pm::set_error("n must be >= 0"), PM_ERR_ARG;
+    if (n > 0 && (!rays || !hit || !t)) return pm::set_error("NULL ray or output pointer"), PM_ERR_ARG;
+    a = pm::TraceArgs{};
+    a.rays = rays;
+    a.n = n;
+    a.hit = hit;
+    a.t = t;
+    if (opts) {
+        if (opts->size < sizeof(pm_trace_opts)) return pm::set_error("pm_trace_opts.size too small"), PM_ERR_ARG;
+        if (opts->link_set < -1 || opts->link_set > 5) return pm::set_error("link_set must be in [-1,5]"), PM_ERR_ARG;
+        if (opts->kernel < 0 || opts->kernel > PM_TRACE_PACKET)
+            return pm::set_error("unknown traversal kernel"), PM_ERR_ARG;
+        if (opts->refill < 0 || opts->refill > 64) return pm::set_error("refill must be in [0,64]"), PM_ERR_ARG;
+        if (opts->kernel == PM_TRACE_POSTPONED && opts->refill > 63)
+            return pm::set_error("postponed kernel: refill (lanes still searching) must be in [0,63]"), PM_ERR_ARG;
+        if (opts->reorder < 0 || opts->reorder > 2) return pm::set_error("reorder must be 0, 1 or 2"), PM_ERR_ARG;
+        if (opts->block != 0 && opts->block != 64 && opts->block != 128 && opts->block != 256)
+            return pm::set_error("block must be 0, 64, 128 or 256"), PM_ERR_ARG;
+        if (opts->tile_width < 0) return pm::set_error("tile_width must be >= 0"), PM_ERR_ARG;
+        if (opts->tile_width > 0) {
+            if (n % opts->tile_width != 0)
+                return pm::set_error("tile_width must divide the number of rays"), PM_ERR_ARG;
+            if (opts->reorder != 0 || opts->kernel == PM_TRACE_PERSISTENT || opts->kernel == PM_TRACE_TWO_RAYS)
+                return pm::set_error("tile_width takes the rays in image order: no reorder, persistent or "
+                                     "two-ray kernel"),
+                       PM_ERR_ARG;
+        }
+        a.link_set = opts->link_set;
+        a.counters = opts->counters;
+        a.tile_w = opts->tile_width;
+        a.kernel = opts->kernel;
+        a.refill = opts->refill;
+        a.reorder = opts->reorder;
+        a.block = opts->block;
+    }
+    if (n >= (int64_t(1) << 31)) return pm::set_error("n must be below 2^31"), PM_ERR_ARG;
+    return PM_OK;
+}
+
 int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
                      const pm_trace_opts *opts, void *stream) {
     pm::TraceRange range_("pm_trace_rays_ex");
     PM_GUARD({
         if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
-        if (n < 0) return pm::set_error("n must be >= 0"), PM_ERR_ARG;
-        if (n > 0 && (!rays || !hit || !t)) return pm::set_error("NULL ray or output pointer"), PM_ERR_ARG;
-        int set = -1, kernel = PM_TRACE_AUTO, refill = 0, reorder = 0, block = 0, tile_w = 0;
-        uint32_t *counters = nullptr;
-        if (opts) {
-            if (opts->size < sizeof(pm_trace_opts)) return pm::set_error("pm_trace_opts.size too small"), PM_ERR_ARG;
-            if (opts->link_set < -1 || opts->link_set > 5) return pm::set_error("link_set must be in [-1,5]"), PM_ERR_ARG;
-            if (opts->kernel < 0 || opts->kernel > PM_TRACE_PACKET)
-                return pm::set_error("unknown traversal kernel"), PM_ERR_ARG;
-            if (opts->refill < 0 || opts->refill > 64) return pm::set_error("refill must be in [0,64]"), PM_ERR_ARG;
-            if (opts->kernel == PM_TRACE_POSTPONED && opts->refill > 63)
-                return pm::set_error("postponed kernel: refill (lanes still searching) must be in [0,63]"), PM_ERR_ARG;
-            if (opts->reorder < 0 || opts->reorder > 2) return pm::set_error("reorder must be 0, 1 or 2"), PM_ERR_ARG;
-            if (opts->block != 0 && opts->block != 64 && opts->block != 128 && opts->block != 256)
-                return pm::set_error("block must be 0, 64, 128 or 256"), PM_ERR_ARG;
-            if (opts->tile_width < 0) return pm::set_error("tile_width must be >= 0"), PM_ERR_ARG;
-            if (opts->tile_width > 0) {
-                if (n % opts->tile_width != 0)
-                    return pm::set_error("tile_width must divide the number of rays"), PM_ERR_ARG;
-                if (opts->reorder != 0 || opts->kernel == PM_TRACE_PERSISTENT || opts->kernel == PM_TRACE_TWO_RAYS)
-                    return pm::set_error("tile_width takes the rays in image order: no reorder, persistent or "
-                                         "two-ray kernel"),
-                           PM_ERR_ARG;
-            }
-            set = opts->link_set;
-            counters = opts->counters;
-            tile_w = opts->tile_width;
-            kernel = opts->kernel;
-            refill = opts->refill;
-            reorder = opts->reorder;
-            block = opts->block;
+        pm::TraceArgs a;
+        int rc = parse_trace(rays, n, hit, t, opts, a);
+        if (rc) return rc;
+        return pm::launch_trace(bvh, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill, a.reorder,
+                                a.block, a.tile_w, (hipStream_t)stream);
+    })
+}
+
+int pm_trace_rays_multi(const pm_bvh *bvh, int32_t n_batches, const pm_trace_batch *batches, void *stream) {
+    pm::TraceRange range_("pm_trace_rays_multi");
+    PM_GUARD({
+        if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
+        if (!batches) return pm::set_error("NULL batches"), PM_ERR_ARG;
+        if (n_batches < 1 || n_batches > PM_MAX_TRACE_BATCHES)
+            return pm::set_error("n_batches must be in [1, PM_MAX_TRACE_BATCHES]"), PM_ERR_ARG;
+        pm::TraceArgs args[PM_MAX_TRACE_BATCHES];
+        int scratch_users = 0;
+        for (int32_t k = 0; k < n_batches; ++k) {
+            const pm_trace_batch &bt = batches[k];
+            if (bt.size < sizeof(pm_trace_batch)) return pm::set_error("pm_trace_batch.size too small"), PM_ERR_ARG;
+            int rc = parse_trace(bt.rays, bt.n, bt.hit, bt.t, bt.opts, args[k]);
+            if (rc) return pm::set_error("batch " + std::to_string(k) + ": " + pm::last_error()), rc;
+            if (args[k].reorder != 0 || args[k].kernel == PM_TRACE_PERSISTENT) ++scratch_users;
         }
-        if (n >= (int64_t(1) << 31)) return pm::set_error("n must be below 2^31"), PM_ERR_ARG;
-        return pm::launch_trace(bvh, rays, n, hit, t, set, counters, kernel, refill, reorder, block, tile_w,
-                                (hipStream_t)stream);
+        if (scratch_users > 1)
+            return pm::set_error("at most one batch may reorder or use the persistent kernel"), PM_ERR_ARG;
+        return pm::launch_trace_multi(const_cast<pm_bvh *>(bvh), args, n_batches, (hipStream_t)stream);
     })
 }
 

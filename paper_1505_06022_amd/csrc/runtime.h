@@ -42,6 +42,11 @@ struct pm_bvh {
     uint32_t *d_perm = nullptr; // ray order of the reordering traversal (perm_cap entries)
     uint64_t perm_cap = 0;
     uint32_t *d_order = nullptr; // bucket counts / starts / cursors of the ray reordering
+    // streams of batches 1.. of pm_trace_rays_multi, and the events that fork
+    // them from and join them to the caller's stream (created on first use)
+    hipStream_t side[PM_MAX_TRACE_BATCHES] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[PM_MAX_TRACE_BATCHES] = {};
     int device = 0;
     std::vector<int32_t> pos_of;  // original triangle index -> position in d_tris
 };
@@ -73,5 +78,18 @@ void free_bvh(pm_bvh *b);
 // tile_w > 0: the rays are an image tile_w wide, taken in 8x8 tiles per wave.
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
                  uint32_t *counters, int kernel, int refill, int reorder, int block, int tile_w, hipStream_t s);
+
+// Validated arguments of one traced batch.
+struct TraceArgs {
+    const float *rays = nullptr;
+    int64_t n = 0;
+    int32_t *hit = nullptr;
+    float *t = nullptr;
+    int link_set = -1, kernel = PM_TRACE_AUTO, refill = 0, reorder = 0, block = 0, tile_w = 0;
+    uint32_t *counters = nullptr;
+};
+
+// Batches 1.. on the handle's own streams, forked from and joined to s.
+int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, hipStream_t s);
 
 }  // namespace pm

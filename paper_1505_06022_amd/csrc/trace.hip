@@ -316,6 +316,14 @@ void free_bvh(pm_bvh *b) {
     if (b->d_next) (void)hipFree(b->d_next);
     if (b->d_perm) (void)hipFree(b->d_perm);
     if (b->d_order) (void)hipFree(b->d_order);
+    for (int k = 0; k < PM_MAX_TRACE_BATCHES; ++k) {
+        if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+        if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+        b->side[k] = nullptr;
+        b->ev_join[k] = nullptr;
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    b->ev_fork = nullptr;
     b->d_perm = nullptr;
     b->d_order = nullptr;
     b->perm_cap = 0;
@@ -469,6 +477,29 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
                        link_set, counters, late, (uint32_t)tile_w);
     PM_HIP(hipGetLastError());
     return PM_OK;
+}
+
+int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, hipStream_t s) {
+    auto one = [&](const TraceArgs &a, hipStream_t st) {
+        return launch_trace(b, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill, a.reorder,
+                            a.block, a.tile_w, st);
+    };
+    if (n_batches == 1) return one(batches[0], s);
+    if (!b->ev_fork) PM_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    for (int32_t k = 1; k < n_batches; ++k) {
+        if (!b->side[k]) PM_HIP(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
+        if (!b->ev_join[k]) PM_HIP(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+    }
+    PM_HIP(hipEventRecord(b->ev_fork, s));
+    for (int32_t k = 1; k < n_batches; ++k) PM_HIP(hipStreamWaitEvent(b->side[k], b->ev_fork, 0));
+    int rc = PM_OK;
+    for (int32_t k = 0; k < n_batches && rc == PM_OK; ++k) rc = one(batches[k], k == 0 ? s : b->side[k]);
+    // join every side stream, also after a failed launch, so that s never runs ahead of them
+    for (int32_t k = 1; k < n_batches; ++k) {
+        PM_HIP(hipEventRecord(b->ev_join[k], b->side[k]));
+        PM_HIP(hipStreamWaitEvent(s, b->ev_join[k], 0));
+    }
+    return rc;
 }
 
 }  // namespace pm

@@ -98,6 +98,23 @@ def test_host_validation_errors_without_gpu():
     assert L.pm_probe_chase(one, 4, 1, 1, None, None) == api.PM_ERR_ARG
     for log2_rows, n_lanes, steps in ((0, 1, 1), (29, 1, 1), (4, 0, 1), (4, 1 << 31, 1), (4, 1, 0)):
         assert L.pm_probe_chase(one, log2_rows, n_lanes, steps, one, None) == api.PM_ERR_ARG
+    # pm_trace_rays_multi: every batch is checked before anything is enqueued (the handle is never touched here)
+    ok = api.TraceBatch(C.sizeof(api.TraceBatch), None, 0, None, None, None)
+    reo = api._trace_opts(reorder=1)
+    two = (api.TraceBatch * 2)(ok, ok)
+    assert L.pm_trace_rays_multi(None, 1, two, None) == api.PM_ERR_ARG
+    assert L.pm_trace_rays_multi(one, 1, None, None) == api.PM_ERR_ARG
+    assert L.pm_trace_rays_multi(one, 0, two, None) == api.PM_ERR_ARG
+    assert L.pm_trace_rays_multi(one, api.MAX_TRACE_BATCHES + 1, two, None) == api.PM_ERR_ARG
+    small = (api.TraceBatch * 2)(ok, api.TraceBatch(4, None, 0, None, None, None))
+    assert L.pm_trace_rays_multi(one, 2, small, None) == api.PM_ERR_ARG
+    neg = (api.TraceBatch * 2)(ok, api.TraceBatch(C.sizeof(api.TraceBatch), None, -1, None, None, None))
+    assert L.pm_trace_rays_multi(one, 2, neg, None) == api.PM_ERR_ARG
+    assert b"batch 1" in L.pm_last_error()
+    both = (api.TraceBatch * 2)(*[api.TraceBatch(C.sizeof(api.TraceBatch), None, 0, None, None,
+                                                 C.cast(C.pointer(reo), C.c_void_p)) for _ in range(2)])
+    assert L.pm_trace_rays_multi(one, 2, both, None) == api.PM_ERR_ARG
+    assert b"at most one batch" in L.pm_last_error()
 
 
 def _py_traverse(nodes, tris, info, ray, s):

@@ -210,3 +210,31 @@ def test_probe_chase_matches_host(torch_cuda):
         r = (q[:, 0] ^ salt) & mask
     assert np.array_equal(got, acc)
 
+
+def test_multi_batch_equals_single_calls(torch_cuda):
+    """pm_trace_rays_multi: batches traced concurrently give exactly the single-call results (three batches, two calls)."""
+    _log("case: multi-batch trace (packets + bucketed postponed + per-ray with counters), soup 2^14")
+    sc = scenes.soup_scene(1 << 14, 4)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    cam = scenes.pinhole_rays(scenes.Camera(pos=(0.5, 0.5, -1.5), look=(0.5, 0.5, 0.5), up=(0, 1, 0), tan_half_fov=0.4,
+                                            width=96, height=40))
+    inc = scenes.random_rays(5000, 9)
+    inc2 = scenes.random_rays(777, 10)
+    rc, ri, ri2 = (torch_cuda.from_numpy(np.ascontiguousarray(x)).cuda() for x in (cam, inc, inc2))
+    kc = dict(kernel=api.TRACE_PACKET, block=64, tile_width=96)
+    ki = dict(kernel=api.TRACE_POSTPONED, refill=32, reorder=1, block=64)
+    ref = [api.trace_rays(bvh, rc, **kc), api.trace_rays(bvh, ri, **ki)]
+    cnt_ref = torch_cuda.zeros((len(inc2), 2), dtype=torch_cuda.int32, device="cuda")
+    ref.append(api.trace_rays(bvh, ri2, counters=cnt_ref))
+    ref = [(h.cpu().numpy(), t.cpu().numpy()) for h, t in ref]
+    for call in range(2):
+        cnt = torch_cuda.zeros((len(inc2), 2), dtype=torch_cuda.int32, device="cuda")
+        got = api.trace_rays_multi(bvh, [dict(rays=ri, **ki), dict(rays=rc, **kc), dict(rays=ri2, counters=cnt)])
+        got = [got[1], got[0], got[2]]
+        for (h, t), (hr, tr) in zip(got, ref):
+            assert np.array_equal(h.cpu().numpy(), hr), call
+            assert np.array_equal(t.cpu().numpy(), tr), call
+        assert torch_cuda.equal(cnt, cnt_ref), call
+    assert (ref[0][0] >= 0).any() and (ref[1][0] >= 0).any()
+    bvh.destroy()
+
