@@ -157,6 +157,13 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
     # the incoherent batch as the bench times it: bucketed, postponed (late 32), 64-thread workgroups
     hb, tb = _gpu_trace(torch_cuda, bvh, inc, kernel=4, refill=32, reorder=1, block=64)
     assert np.array_equal(h[nc:], hb) and np.array_equal(t[nc:], tb)
+    # the bench's timed step: both batches side by side in one pm_trace_rays_multi call
+    ri, rc = (torch_cuda.from_numpy(np.ascontiguousarray(x)).cuda() for x in (inc, coh))
+    (hi_, ti_), (hc_, tc_) = api.trace_rays_multi(bvh, [dict(rays=ri, kernel=4, refill=32, reorder=1, block=64),
+                                                        dict(rays=rc, kernel=6, block=64, tile_width=1920)])
+    assert np.array_equal(h[nc:], hi_.cpu().numpy()) and np.array_equal(t[nc:], ti_.cpu().numpy())
+    assert np.array_equal(h[:nc], hc_.cpu().numpy()) and np.array_equal(t[:nc], tc_.cpu().numpy())
+    del ri, rc
     h5, t5 = _gpu_trace(torch_cuda, bvh, rays[:-1], kernel=5, reorder=1, block=64)   # odd count
     assert np.array_equal(h[:-1], h5) and np.array_equal(t[:-1], t5)
     for level in (1, 2):                                      # reordered: identical
