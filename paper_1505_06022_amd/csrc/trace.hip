@@ -264,6 +264,28 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const 
     trace_slot<kStats, kWalk, true>(bvh, rays, perm, lane, n, hit, tout, force_set, counters, late, 0u);
 }
 
+// Two batches in one launch: the first blocksA workgroups walk batch A in
+// the order of perm (postponed leaf tests); the rest take batch B, an image
+// tile_w wide, one 8x8 pixel tile per wavefront, as packets.  The dispatcher
+// hands out B's workgroups once all of A's are running, so B fills the
+// device as A's last wavefronts drain.
+template <bool kStats>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_perm_then_tiles(
+    pmd::Bvh bvh, uint32_t blocksA, const float4 *__restrict__ raysA, const uint32_t *__restrict__ perm, uint32_t nA,
+    int32_t *__restrict__ hitA, float *__restrict__ tA, int32_t setA, uint32_t *__restrict__ countersA, uint32_t late,
+    const float4 *__restrict__ raysB, int64_t nB, int32_t *__restrict__ hitB, float *__restrict__ tB, int32_t setB,
+    uint32_t *__restrict__ countersB, uint32_t tile_w) {
+    if (blockIdx.x < blocksA) {
+        const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, blocksA) * blockDim.x + threadIdx.x;
+        trace_slot<kStats, kWalkPostponed, true>(bvh, raysA, perm, lane, nA, hitA, tA, setA, countersA, late, 0u);
+    } else {
+        const uint64_t lane =
+            (uint64_t)pmd::xcd_block(blockIdx.x - blocksA, gridDim.x - blocksA) * blockDim.x + threadIdx.x;
+        trace_slot<kStats, kWalkPacket, false>(bvh, raysB, nullptr, lane, (uint64_t)nB, hitB, tB, setB, countersB, 0u,
+                                               tile_w);
+    }
+}
+
 }  // namespace
 
 namespace pm {
@@ -383,9 +405,8 @@ static int launch_persistent(const pm_bvh *b, const pmd::Bvh &bvh, const float *
     return PM_OK;
 }
 
-static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *rays, int64_t n, int32_t *hit,
-                                  float *t, int link_set, uint32_t *counters, int kernel, uint32_t late,
-                                  int reorder, uint32_t block, hipStream_t s) {
+// Bucket the rays (count, scan, scatter): b->d_perm receives the order.
+static int bucket_rays(pm_bvh *b, const float *rays, int64_t n, int link_set, int reorder, hipStream_t s) {
     if ((uint64_t)n > b->perm_cap) {
         if (b->d_perm) {
             PM_HIP(hipStreamSynchronize(s));
@@ -417,6 +438,16 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
     launch_bucket_scan(counts, start, fill, bsum, nbk, s);
     hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const uint2 *)key_rank, nn,
                        (const uint32_t *)start, b->d_perm);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
+static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *rays, int64_t n, int32_t *hit,
+                                  float *t, int link_set, uint32_t *counters, int kernel, uint32_t late,
+                                  int reorder, uint32_t block, hipStream_t s) {
+    int rc = bucket_rays(b, rays, n, link_set, reorder, s);
+    if (rc) return rc;
+    const uint32_t nn = (uint32_t)n;
     if (kernel == PM_TRACE_PERSISTENT)
         return launch_persistent(b, bvh, rays, nn, hit, t, link_set, counters, (int)late, b->d_perm, s);
     using Kern = void (*)(pmd::Bvh, const float4 *, const uint32_t *, uint32_t, int32_t *, float *, int32_t,
@@ -479,12 +510,40 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
     return PM_OK;
 }
 
+static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs &B, int block, hipStream_t s) {
+    int rc = bucket_rays(b, A.rays, A.n, A.link_set, A.reorder, s);
+    if (rc) return rc;
+    const pmd::Bvh bvh = make_device_bvh(b);
+    const uint32_t nA = (uint32_t)A.n;
+    const uint64_t blocksA = ((uint64_t)nA + block - 1) / block;
+    const int64_t tiles = (((int64_t)B.tile_w + 7) / 8) * ((B.n / B.tile_w + 7) / 8);
+    const uint64_t blocksB = ((uint64_t)tiles * 64 + block - 1) / block;
+    if (blocksA + blocksB > 0x7fffffffull) return set_error("too many rays for one launch"), PM_ERR_ARG;
+    hipLaunchKernelGGL(A.counters ? k_trace_perm_then_tiles<true> : k_trace_perm_then_tiles<false>,
+                       dim3((uint32_t)(blocksA + blocksB)), dim3(block), 0, s, bvh, (uint32_t)blocksA,
+                       (const float4 *)A.rays, (const uint32_t *)b->d_perm, nA, A.hit, A.t, A.link_set, A.counters,
+                       (uint32_t)A.refill, (const float4 *)B.rays, B.n, B.hit, B.t, B.link_set, B.counters,
+                       (uint32_t)B.tile_w);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
 int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, hipStream_t s) {
     auto one = [&](const TraceArgs &a, hipStream_t st) {
         return launch_trace(b, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill, a.reorder,
                             a.block, a.tile_w, st);
     };
     if (n_batches == 1) return one(batches[0], s);
+    if (n_batches == 2) {  // bucketed postponed walk + packets over image tiles: one launch for both
+        for (int k = 0; k < 2; ++k) {
+            const TraceArgs &A = batches[k], &B = batches[1 - k];
+            const int blk = A.block ? A.block : 256;
+            if (A.reorder != 0 && A.kernel == PM_TRACE_POSTPONED && A.n > 0 && B.kernel == PM_TRACE_PACKET &&
+                B.tile_w > 0 && B.reorder == 0 && B.n > 0 && (B.block ? B.block : 256) == blk &&
+                (A.counters == nullptr) == (B.counters == nullptr))
+                return launch_perm_then_tiles(b, A, B, blk, s);
+        }
+    }
     if (!b->ev_fork) PM_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     for (int32_t k = 1; k < n_batches; ++k) {
         if (!b->side[k]) PM_HIP(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));

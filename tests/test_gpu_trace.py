@@ -242,6 +242,22 @@ def test_multi_batch_equals_single_calls(torch_cuda):
             assert np.array_equal(h.cpu().numpy(), hr), call
             assert np.array_equal(t.cpu().numpy(), tr), call
         assert torch_cuda.equal(cnt, cnt_ref), call
+        # two batches, bucketed postponed walk + packets over image tiles: one fused launch
+        two = api.trace_rays_multi(bvh, [dict(rays=rc, **kc), dict(rays=ri, **ki)])
+        for (h, t), (hr, tr) in zip(two, ref[:2]):
+            assert np.array_equal(h.cpu().numpy(), hr) and np.array_equal(t.cpu().numpy(), tr), call
+    # the fused launch in statistics mode: the same hits, and per-ray counts from each walk
+    cc = torch_cuda.zeros((len(cam), 2), dtype=torch_cuda.int32, device="cuda")
+    ci = torch_cuda.zeros((len(inc), 2), dtype=torch_cuda.int32, device="cuda")
+    two = api.trace_rays_multi(bvh, [dict(rays=ri, counters=ci, **ki), dict(rays=rc, counters=cc, **kc)])
+    for (h, t), (hr, tr) in zip(two, [ref[1], ref[0]]):
+        assert np.array_equal(h.cpu().numpy(), hr) and np.array_equal(t.cpu().numpy(), tr)
+    cc1 = torch_cuda.zeros_like(cc)
+    ci1 = torch_cuda.zeros_like(ci)
+    api.trace_rays(bvh, rc, counters=cc1, **kc)
+    api.trace_rays(bvh, ri, counters=ci1, **ki)
+    assert torch_cuda.equal(cc, cc1)               # packets: the same walk either way
+    assert int(ci[:, 0].min()) >= 1 and int(ci1[:, 0].min()) >= 1
     assert (ref[0][0] >= 0).any() and (ref[1][0] >= 0).any()
     bvh.destroy()
 
