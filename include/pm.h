@@ -220,7 +220,13 @@ typedef struct {
  * `stream` then waits for every batch, so work enqueued on it after the call
  * sees all results.  Kernels of different batches share the device (one
  * batch's last wavefronts leave room for another's), so the call takes less
- * time than the batches one after another; results are the same.  The
+ * time than the batches one after another; results are the same.  Two
+ * batches of which one is bucketed (reorder) with the postponed kernel and
+ * the other is traced as packets over image tiles, with equal workgroup
+ * sizes and both with or without counters, go out on `stream` alone: the
+ * bucketing, then one launch whose first workgroups walk the bucketed batch
+ * and whose last ones take the tiles (dispatched as the walk's last
+ * wavefronts drain).  The
  * batches' output arrays must not overlap.  At most one batch may use the
  * handle's scratch (reorder != 0 or the persistent kernel).  Calls on one
  * handle must be on the same stream or not overlap (the handle's streams are
