@@ -537,9 +537,9 @@ int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, h
     if (n_batches == 2) {  // bucketed postponed walk + packets over image tiles: one launch for both
         for (int k = 0; k < 2; ++k) {
             const TraceArgs &A = batches[k], &B = batches[1 - k];
-            const int blk = A.block ? A.block : 256;
+            const int blk = A.block ? A.block : kDefaultWalkBlock;
             if (A.reorder != 0 && A.kernel == PM_TRACE_POSTPONED && A.n > 0 && B.kernel == PM_TRACE_PACKET &&
-                B.tile_w > 0 && B.reorder == 0 && B.n > 0 && (B.block ? B.block : 256) == blk &&
+                B.tile_w > 0 && B.reorder == 0 && B.n > 0 && (B.block ? B.block : kDefaultWalkBlock) == blk &&
                 (A.counters == nullptr) == (B.counters == nullptr))
                 return launch_perm_then_tiles(b, A, B, blk, s);
         }
