@@ -155,8 +155,8 @@ def traversal_bench(args, torch, api, scenes):
     # per ray: 32 B ray + 8 B result + 16 B per node visited + 48 B per triangle tested
     alg_bytes = sum(40.0 * n + 16.0 * vn + 48.0 * vt for vn, vt, n in per_batch)
 
-    # one step = one pm_trace_rays_multi call: the incoherent batch (bucketing, then the walk) on the
-    # caller's stream and the camera batch on a stream of the BVH handle, running side by side
+    # one step = one pm_trace_rays_multi call: the incoherent batch is bucketed, then one launch walks it
+    # and, in its last workgroups, the camera batch's 8x8 pixel tiles
     stream = torch.cuda.current_stream()
     multi = [dict(rays=batches[b], hit=outs[b][0], t=outs[b][1], **trace_kw[b]) for b in (1, 0)]
     for _ in range(args.warmup):
@@ -576,9 +576,9 @@ def main():
                             for vn, vt, n in tb["per_batch"]],
         "roofline": {"bound": "hbm", "achieved": round(tb["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(tb["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "pm_trace_rays_multi call, both batches side by side: k_ray_count + scan + "
-                               "k_ray_scatter + k_trace_perm with postponed leaf tests (incoherent batch) beside "
-                               "k_trace packets over 8x8 pixel tiles (camera batch)",
+                     "kernel": "pm_trace_rays_multi call: k_ray_count + scan + k_ray_scatter, then one launch of "
+                               "k_trace_perm_then_tiles (the incoherent batch's postponed walk, then the camera "
+                               "batch's packets over 8x8 pixel tiles)",
                      "bytes_per_launch": tb["per_launch_bytes"],
                      "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4),
                      "alone_ms_by_batch": [round(float(x), 4) for x in tb["batch_ms"]]},
