@@ -96,6 +96,9 @@ class State(C.Structure):
 def _declare(L):
     P = C.c_void_p
     L.orc_rng_seed.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, P]
+    L.orc_splitmix64.argtypes = [C.c_uint64, C.c_int64, P]
+    L.orc_xor128.argtypes = [P, C.c_int64, P]
+    L.orc_photon_emit.argtypes = [P, C.c_uint64, C.c_uint32, C.c_int64, P, P, P]
     L.orc_rng_step_component.argtypes = [C.c_int, P, P, C.c_int64]
     L.orc_rng_draw.argtypes = [P, P, C.c_int64]
     L.orc_rng_streams.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_int64, C.c_int64, P]
@@ -141,6 +144,21 @@ def rng_seed(seed: int, kind: int, k: int, index: int) -> np.ndarray:
     s = np.zeros(4, np.uint32)
     lib().orc_rng_seed(seed, kind, k, index, _p(s))
     return s
+
+
+def splitmix64(state: int, n: int) -> np.ndarray:
+    """n successive splitmix64 outputs starting from ``state``."""
+    out = np.zeros(n, np.uint64)
+    lib().orc_splitmix64(state, n, _p(out))
+    return out
+
+
+def xor128(seed_words, n: int) -> np.ndarray:
+    """n successive outputs of Marsaglia's xor128 from four seed words."""
+    sw = np.ascontiguousarray(seed_words, np.uint32)
+    out = np.zeros(n, np.uint32)
+    lib().orc_xor128(_p(sw), n, _p(out))
+    return out
 
 
 def rng_step_component(j: int, states: np.ndarray) -> np.ndarray:
@@ -299,6 +317,15 @@ def photon_pass(os_: OracleScene, seed: int, k: int, n_photons: int, paths: np.n
         raise OverflowError("oracle photon store capacity exceeded")
     pb.n = int(n)
     return pb
+
+
+def photon_emit(os_: OracleScene, seed: int, k: int, n: int):
+    """Emission of photon paths [0, n) of iteration k: (origin, direction, emitting triangle)."""
+    org = np.zeros((n, 3), np.float32)
+    dirs = np.zeros((n, 3), np.float32)
+    tri = np.zeros(n, np.int32)
+    lib().orc_photon_emit(os_.h, seed, k, n, _p(org), _p(dirs), _p(tri))
+    return org, dirs, tri
 
 
 def gather(hp: HitPointBuf, ph: PhotonBuf, R2: np.ndarray, shift=40, method=1, nthreads=None, want_double=False):

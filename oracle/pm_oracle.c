@@ -129,10 +129,26 @@ static inline uint64_t splitmix64(uint64_t *st) {
     return z ^ (z >> 31);
 }
 
+/* Marsaglia's xorshift generator "xor128" (Marsaglia 2003, J. Stat. Softw.
+ * 8(14)): four 32-bit words, one output (the new last word) per call. */
+static inline uint32_t xor128_next(uint32_t st[4]) {
+    uint32_t t = st[0] ^ (st[0] << 11);
+    st[0] = st[1];
+    st[1] = st[2];
+    st[2] = st[3];
+    st[3] = (st[3] ^ (st[3] >> 19)) ^ (t ^ (t >> 8));
+    return st[3];
+}
+
 /* Stream seeding.  The paper seeds each thread's four-word state on the CPU
- * with Marsaglia's xorshift (Sec. 3.2).  Here the xorshift128 seed itself is
+ * with Marsaglia's xorshift (Sec. 3.2).  Here the xorshift seed itself is
  * derived from a counter key (seed, kind, iteration, index) through
- * splitmix64, so any stream can be regenerated on its own. */
+ * splitmix64, so any stream can be regenerated on its own:
+ *   h1 = splitmix64 output of state seed,
+ *   h2 = splitmix64 output of state h1 ^ (kind << 32 | k),
+ *   w01, w23 = the next two splitmix64 outputs from state h2 ^ index,
+ *   xor128 seeded with (lo w01, hi w01, lo w23, hi w23) (all-zero -> x = 1),
+ *   s_j = 1 + (output 9 + j of xor128) mod (m_j - 1), j = 0..3. */
 static void rng_seed(uint64_t seed, uint32_t kind, uint32_t k, uint64_t index, uint32_t s[4]) {
     uint64_t st = seed;
     uint64_t h = splitmix64(&st);
@@ -141,20 +157,21 @@ static void rng_seed(uint64_t seed, uint32_t kind, uint32_t k, uint64_t index, u
     st = h ^ index;
     uint64_t w01 = splitmix64(&st);
     uint64_t w23 = splitmix64(&st);
-    uint32_t x = (uint32_t)w01, y = (uint32_t)(w01 >> 32);
-    uint32_t z = (uint32_t)w23, w = (uint32_t)(w23 >> 32);
-    if ((x | y | z | w) == 0u) x = 1u;
-    uint32_t out[4];
-    for (int i = 0; i < 12; ++i) {
-        /* Marsaglia 2003, "xor128" */
-        uint32_t t = x ^ (x << 11);
-        x = y;
-        y = z;
-        z = w;
-        w = (w ^ (w >> 19)) ^ (t ^ (t >> 8));
-        if (i >= 8) out[i - 8] = w;
-    }
-    for (int j = 0; j < 4; ++j) s[j] = 1u + out[j] % (RNG_M[j] - 1u);
+    uint32_t x[4] = {(uint32_t)w01, (uint32_t)(w01 >> 32), (uint32_t)w23, (uint32_t)(w23 >> 32)};
+    if ((x[0] | x[1] | x[2] | x[3]) == 0u) x[0] = 1u;
+    for (int i = 0; i < 8; ++i) (void)xor128_next(x); /* outputs 1..8 are discarded */
+    for (int j = 0; j < 4; ++j) s[j] = 1u + xor128_next(x) % (RNG_M[j] - 1u);
+}
+
+/* n successive splitmix64 outputs from the given state (known-answer hook). */
+ORC_EXPORT void orc_splitmix64(uint64_t state, int64_t n, uint64_t *out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = splitmix64(&state);
+}
+
+/* n successive xor128 outputs from the four seed words (known-answer hook). */
+ORC_EXPORT void orc_xor128(const uint32_t *seed, int64_t n, uint32_t *out) {
+    uint32_t st[4] = {seed[0], seed[1], seed[2], seed[3]};
+    for (int64_t i = 0; i < n; ++i) out[i] = xor128_next(st);
 }
 
 ORC_EXPORT void orc_rng_seed(uint64_t seed, uint32_t kind, uint32_t k, uint64_t index, uint32_t *s) {
@@ -774,15 +791,12 @@ typedef struct {
     int64_t cap;
 } orc_photons;
 
-/* Trace photon path n of iteration k.  Appends up to max_bounces photons to
- * buf (a local buffer), returns the number appended. */
-static int photon_path(const orc_scene *s, const orc_run_opts *op, uint32_t k, uint64_t n, float phi0,
-                       v3 *bx, v3 *bw, float *bphi, uint32_t *bb, int32_t *bmats) {
-    const orc_scene_desc *d = &s->d;
-    uint32_t st[4];
-    rng_seed(op->seed, KIND_PHOTON, k, n, st);
-    if (s->n_emit == 0) return 0;
-    /* emitter choice by power (area * Le) */
+/* Start of a photon path (Sec. 2: photons are traced from the light
+ * sources): an emitting triangle chosen with probability proportional to its
+ * power area * Le (one draw against the cumulative table), a uniform point on
+ * it (two draws, folded into the triangle when u1 + u2 > 1), and a cosine-
+ * distributed direction about its normal.  Returns the triangle's index. */
+static int32_t photon_emit(const orc_scene *s, uint32_t st[4], v3 *org, v3 *dir) {
     float u0 = rng_next(st);
     double target = (double)u0 * s->power;
     int64_t e = 0;
@@ -791,9 +805,40 @@ static int photon_path(const orc_scene *s, const orc_run_opts *op, uint32_t k, u
     const tri_t *tr = &s->T[et];
     float u1 = rng_next(st), u2 = rng_next(st);
     if (u1 + u2 > 1.0f) { u1 = 1.0f - u1; u2 = 1.0f - u2; }
-    v3 org = mk((tr->v0.x + u1 * tr->e1.x) + u2 * tr->e2.x, (tr->v0.y + u1 * tr->e1.y) + u2 * tr->e2.y,
-                (tr->v0.z + u1 * tr->e1.z) + u2 * tr->e2.z);
-    v3 dir = cosine_dir(tri_normal(tr), st);
+    *org = mk((tr->v0.x + u1 * tr->e1.x) + u2 * tr->e2.x, (tr->v0.y + u1 * tr->e1.y) + u2 * tr->e2.y,
+              (tr->v0.z + u1 * tr->e1.z) + u2 * tr->e2.z);
+    *dir = cosine_dir(tri_normal(tr), st);
+    return et;
+}
+
+/* Emission of photon paths [0, n) of iteration k: origin, direction and the
+ * emitting triangle of each (-1 and zeros when the scene has no emitter). */
+ORC_EXPORT void orc_photon_emit(const orc_scene *s, uint64_t seed, uint32_t k, int64_t n, float *org, float *dir,
+                                int32_t *tri) {
+    for (int64_t i = 0; i < n; ++i) {
+        v3 o = mk(0.0f, 0.0f, 0.0f), w = mk(0.0f, 0.0f, 0.0f);
+        int32_t et = -1;
+        if (s->n_emit > 0) {
+            uint32_t st[4];
+            rng_seed(seed, KIND_PHOTON, k, (uint64_t)i, st);
+            et = photon_emit(s, st, &o, &w);
+        }
+        org[3 * i] = o.x; org[3 * i + 1] = o.y; org[3 * i + 2] = o.z;
+        dir[3 * i] = w.x; dir[3 * i + 1] = w.y; dir[3 * i + 2] = w.z;
+        tri[i] = et;
+    }
+}
+
+/* Trace photon path n of iteration k.  Appends up to max_bounces photons to
+ * buf (a local buffer), returns the number appended. */
+static int photon_path(const orc_scene *s, const orc_run_opts *op, uint32_t k, uint64_t n, float phi0,
+                       v3 *bx, v3 *bw, float *bphi, uint32_t *bb, int32_t *bmats) {
+    const orc_scene_desc *d = &s->d;
+    uint32_t st[4];
+    rng_seed(op->seed, KIND_PHOTON, k, n, st);
+    if (s->n_emit == 0) return 0;
+    v3 org, dir;
+    int32_t et = photon_emit(s, st, &org, &dir);
     float phi = phi0;
     int32_t excl = et;
     int stored = 0;

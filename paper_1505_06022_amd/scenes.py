@@ -300,6 +300,92 @@ def polygon_light_scene(rho=0.5, Le=1.0, half=0.25, height=1.0, floor_half=40.0,
     return b.finish(cam, "polygon_light", params=[mf])
 
 
+def two_light_scene(Le=(10.0, 10.0), half=(0.1, 0.05), width=16, height=16) -> Scene:
+    """Two square emitters facing down over a diffuse floor, with their own
+    materials: light i has side 2*half[i] and radiance Le[i].  Emission by
+    power picks light i with probability A_i Le_i / sum_j A_j Le_j."""
+    b = _Builder()
+    mf = b.material(DIFFUSE, 0.5)
+    f = 4.0
+    b.quad((-f, 0, -f), (-f, 0, f), (f, 0, f), (f, 0, -f), mf)   # +y
+    _ceiling_light(b, Le[0], y=1.0, x=(-0.5 - half[0], -0.5 + half[0]), z=(-half[0], half[0]))
+    _ceiling_light(b, Le[1], y=1.0, x=(0.5 - half[1], 0.5 + half[1]), z=(-half[1], half[1]))
+    cam = Camera((0.0, 0.9, -1.4), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 0.5, width, height)
+    return b.finish(cam, "two_lights", params=[mf])
+
+
+def mirror_floor_scene(width=24, height=16, rho=0.5) -> Scene:
+    """A diffuse floor (y = 0, z <= 2) in front of a vertical mirror (z = 2,
+    facing -z, spanning y in [0.3, 4]); the camera looks at the mirror, so
+    most eye paths reflect once and end on the floor in front of it.  A
+    square light hangs above the floor, facing down."""
+    b = _Builder()
+    mf = b.material(DIFFUSE, rho)
+    mm = b.material(MIRROR, 0.0)
+    b.quad((-6, 0, -6), (-6, 0, 2), (6, 0, 2), (6, 0, -6), mf)       # floor (+y)
+    b.quad((-6, 0.3, 2), (-6, 4, 2), (6, 4, 2), (6, 0.3, 2), mm)     # mirror (-z)
+    _ceiling_light(b, 5.0, y=3.0, x=(-0.3, 0.3), z=(0.2, 0.8))
+    cam = Camera((0.1, 1.0, 0.0), (0.0, 0.6, 2.0), (0.0, 1.0, 0.0), 0.35, width, height)
+    return b.finish(cam, "mirror_floor", params=[mf])
+
+
+def mirror_corridor_scene(width=32, height=32, length=50.0) -> Scene:
+    """A corridor between two parallel mirrors (x = -0.5 facing +x, x = +0.5
+    facing -x, 100 high) over a diffuse floor (y = 0), closed by a diffuse end
+    wall at z = length; the top is open.  Eye rays bounce between the mirrors
+    on their way to the floor or the end wall, up to a few dozen times."""
+    b = _Builder()
+    mf = b.material(DIFFUSE, 0.5)
+    me = b.material(DIFFUSE, 0.7)
+    mm = b.material(MIRROR, 0.0)
+    L, Hh = length, 100.0
+    b.quad((-0.5, 0, -1), (-0.5, 0, L), (0.5, 0, L), (0.5, 0, -1), mf)          # floor (+y)
+    b.quad((-0.5, 0, L), (-0.5, Hh, L), (0.5, Hh, L), (0.5, 0, L), me)          # end wall (-z)
+    b.quad((-0.5, 0, -1), (-0.5, Hh, -1), (-0.5, Hh, L), (-0.5, 0, L), mm)      # left mirror (+x)
+    b.quad((0.5, 0, -1), (0.5, 0, L), (0.5, Hh, L), (0.5, Hh, -1), mm)          # right mirror (-x)
+    _ceiling_light(b, 1.0, y=0.99 * Hh, x=(-0.4, 0.4), z=(0.0, 0.8))
+    cam = Camera((0.1, 1.0, 0.0), (0.3, 0.75, 5.0), (0.0, 1.0, 0.0), 0.5, width, height)
+    return b.finish(cam, "mirror_corridor", params=[mf, me])
+
+
+def specular_furnace_scene(rho=0.5, Le=1.0, width=16, height=16, glass_level=3) -> Scene:
+    """The closed furnace cube (every face diffuse with albedo rho, emitting Le
+    inward) holding a floating mirror box and a glass sphere (IOR 1.5).
+    Lossless specular surfaces leave the uniform radiance Le / (1 - rho)
+    unchanged, so every hit point still sees it."""
+    b = _Builder()
+    m = b.material(DIFFUSE, rho, Le=Le)
+    mm = b.material(MIRROR, 0.0)
+    mg = b.material(GLASS, 0.0, ior=1.5)
+    tris = _box((0, 0, 0), (1, 1, 1))[:, [0, 2, 1]]   # inward normals
+    b.add(tris, m)
+    b.add(_box((0.2, 0.3, 0.55), (0.4, 0.5, 0.75)), mm)
+    b.add(np.asarray((0.66, 0.5, 0.65)) + 0.16 * _icosphere(glass_level), mg)
+    cam = Camera((0.5, 0.5, 0.05), (0.5, 0.5, 1.0), (0.0, 1.0, 0.0), 0.6, width, height)
+    return b.finish(cam, "specular_furnace", params=[m])
+
+
+def polygon_light_mirror_scene(rho=0.5, Le=1.0, half=0.25, height=1.0, mirror_x=0.4, floor_half=40.0,
+                               width=32, height_px=24) -> Scene:
+    """The polygon-light scene cut by a large vertical mirror at x = mirror_x
+    (facing -x): the floor (x < mirror_x) is lit by the square light and by
+    its mirror image.  The floor's Russian-roulette survival is 0, so only
+    first-bounce photons are stored and the floor radiance is
+    (rho/pi) (E(light) + E(image of the light))."""
+    b = _Builder()
+    mf = b.material(DIFFUSE, rho)
+    mm = b.material(MIRROR, 0.0)
+    f, xm = floor_half, mirror_x
+    b.quad((-f, 0, -f), (-f, 0, f), (xm, 0, f), (xm, 0, -f), mf)        # floor (+y)
+    b.quad((xm, 0, -f), (xm, 0, f), (xm, f, f), (xm, f, -f), mm)        # mirror (-x)
+    _ceiling_light(b, Le, y=height, x=(-half, half), z=(-half, half))
+    cam = Camera((-0.6, 0.9, -0.9), (-0.2, 0.0, 0.0), (0.0, 1.0, 0.0), 0.3, width, height_px)
+    s = b.finish(cam, "polygon_light_mirror", params=[mf])
+    s.mat_q = s.mat_q.copy()
+    s.mat_q[mf] = 0.0
+    return s
+
+
 def soup_scene(n_tri=1 << 20, seed=2) -> Scene:
     """Random triangle soup: centroids uniform in the unit cube, vertex offsets
     of lognormal(-5, 0.5) length along uniform directions."""

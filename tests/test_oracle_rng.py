@@ -8,7 +8,10 @@ These tests pin it to things other than itself:
     root, so every component has full period m-1;
   * the output formula against an exact rational evaluation of
     frac(s0/m0 - s1/m1 + s2/m2 - s3/m3) on the *advanced* state;
-  * statistical uniformity (the paper's caveat on quality).
+  * statistical uniformity (the paper's caveat on quality);
+  * stream seeding: the two published generators it is built from
+    (splitmix64 and Marsaglia's xor128) against their published known
+    answers, and the seeding rule composed from those two pinned pieces.
 """
 from fractions import Fraction
 
@@ -136,3 +139,50 @@ def test_streams_are_random_access(oracle_lib):
     full = oracle_lib.rng_streams(3, 1, 2, 0, 64, 10)
     part = oracle_lib.rng_streams(3, 1, 2, 40, 4, 10)
     assert np.array_equal(full[40:44], part)
+
+
+# splitmix64 (Steele, Lea and Flood 2014; Vigna's reference implementation):
+# the first outputs from state 0 and from state 1234567 are published test
+# values of the generator.
+SPLITMIX64_FROM_0 = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+SPLITMIX64_FROM_1234567 = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                           4593380528125082431, 16408922859458223821]
+# Marsaglia (2003), "Xorshift RNGs": xor128 with its published default seed
+# x, y, z, w = 123456789, 362436069, 521288629, 88675123.
+XOR128_SEED = [123456789, 362436069, 521288629, 88675123]
+XOR128_OUT = [3701687786, 458299110, 2500872618, 3633119408, 516391518]
+
+
+def test_splitmix64_known_answers(oracle_lib):
+    assert [int(x) for x in oracle_lib.splitmix64(0, 4)] == SPLITMIX64_FROM_0
+    assert [int(x) for x in oracle_lib.splitmix64(1234567, 5)] == SPLITMIX64_FROM_1234567
+
+
+def test_xor128_known_answers(oracle_lib):
+    assert [int(x) for x in oracle_lib.xor128(XOR128_SEED, 5)] == XOR128_OUT
+
+
+def _seed_from_pinned_parts(oracle_lib, seed, kind, k, index):
+    """The stream-seeding rule, composed from the two pinned generators:
+    h1 = splitmix64(seed); h2 = splitmix64(h1 ^ (kind << 32 | k));
+    w01, w23 = the two splitmix64 outputs from state h2 ^ index; xor128 seeded
+    with their 32-bit halves (low first); s_j = 1 + (output 9 + j) mod (m_j - 1)."""
+    mask = (1 << 64) - 1
+    h1 = int(oracle_lib.splitmix64(seed, 1)[0])
+    h2 = int(oracle_lib.splitmix64(h1 ^ ((kind << 32) | k), 1)[0])
+    w01, w23 = (int(x) for x in oracle_lib.splitmix64((h2 ^ index) & mask, 2))
+    words = [w01 & 0xFFFFFFFF, w01 >> 32, w23 & 0xFFFFFFFF, w23 >> 32]
+    if not any(words):
+        words[0] = 1
+    out = [int(x) for x in oracle_lib.xor128(words, 12)]
+    return [1 + out[8 + j] % (M[j] - 1) for j in range(4)]
+
+
+def test_stream_seeding_is_the_composition_of_the_pinned_generators(oracle_lib):
+    keys = [(0, 1, 0, 0), (1, 2, 0, 5), (5, 2, 3, 7), (2 ** 63 + 11, 1, 63, 2 ** 40 + 3),
+            (3, 3, 7, 123456), (2 ** 64 - 1, 2, 2 ** 32 - 1, 2 ** 64 - 1)]
+    rng = np.random.default_rng(7)
+    keys += [(int(rng.integers(0, 2 ** 63)), int(rng.integers(1, 4)), int(rng.integers(0, 64)),
+              int(rng.integers(0, 2 ** 40))) for _ in range(200)]
+    for key in keys:
+        assert [int(x) for x in oracle_lib.rng_seed(*key)] == _seed_from_pinned_parts(oracle_lib, *key), key
