@@ -246,7 +246,8 @@ typedef struct {
     const int32_t *mat_type;  /* host [n_mat] PM_MAT_* */
     const float *mat_rho;     /* host [n_mat] diffuse albedo in [0,1) */
     const float *mat_q;       /* host [n_mat] Russian-roulette survival
-                                 probability (nominal albedo, held fixed) */
+                                 probability in [0,1] (nominal albedo, held
+                                 fixed); 0 stores a photon and ends the path */
     const float *mat_Le;      /* host [n_mat] emitted radiance, >= 0 */
     const float *mat_ior;     /* host [n_mat] index of refraction (glass) */
     int32_t n_mat;
@@ -270,8 +271,10 @@ typedef struct {
     int32_t store_factor;     /* photon store capacity = n_photons * factor (8) */
     int32_t record_iterations; /* > 0: record what pm_sppm_adjoint needs for
                                   up to this many iterations (8 B per pixel
-                                  per iteration, plus 9 B x n_photons x
-                                  max_photon_bounces of replay scratch) */
+                                  per iteration, plus 10 B x n_photons x
+                                  max_photon_bounces of replay scratch);
+                                  needs gather_mode 0, at most 256 materials
+                                  and fewer than 2^24 pixels */
     int32_t photon_kernel;    /* PM_PHOTON_*: 0 = default (regeneration) */
     int32_t refill;           /* regeneration: idle lanes of a wave that
                                  trigger taking new paths (1..64; 0 = 32) */
@@ -377,7 +380,11 @@ PM_API int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, in
  *                 when the scene has no or several emitting materials)
  * Sampling is held fixed (Russian roulette uses the nominal q), so every path,
  * hit point and radius is replayed from its counter-keyed random stream and
- * only the flux terms are differentiated.  Asynchronous on `stream`.
+ * only the flux terms are differentiated.  Every sum is an integer sum of
+ * terms rounded one by one (a per-iteration power-of-two scale keeps each
+ * term below 2^39 units), so the gradient is bit-reproducible: it does not
+ * depend on the order of atomics or of photons in their buckets.
+ * Asynchronous on `stream`.
  * Errors: PM_ERR_STATE if nothing was recorded; PM_ERR_ARG for bad ids. */
 PM_API int pm_sppm_adjoint(pm_sppm *s, const float *dloss_dimage, const int32_t *param_mats, int32_t n_par,
                            double *grad, void *stream);

@@ -505,16 +505,22 @@ def _render_function():
             s.iterate(K, stream=stream)
             img = s.resolve(stream=stream)
             ctx.s, ctx.param_mats, ctx.stream = s, np.asarray(param_mats, np.int32), stream
-            ctx.dtypes = (albedos.dtype, Le.dtype if hasattr(Le, "dtype") else torch.float32)
-            ctx.devices = (albedos.device, Le.device if hasattr(Le, "device") else albedos.device)
+            ctx.le_is_tensor = isinstance(Le, torch.Tensor)
+            ctx.dtypes = (albedos.dtype, Le.dtype if ctx.le_is_tensor else torch.float32)
+            ctx.devices = (albedos.device, Le.device if ctx.le_is_tensor else albedos.device)
             return img
 
         @staticmethod
         def backward(ctx, g):
+            need_rho, need_le = ctx.needs_input_grad[0], ctx.needs_input_grad[1] and ctx.le_is_tensor
+            if not (need_rho or need_le):
+                return None, None, None, None, None, None, None
             grad = ctx.s.adjoint(g, ctx.param_mats, stream=ctx.stream)
             n = len(ctx.param_mats)
-            return (grad[:n].to(device=ctx.devices[0], dtype=ctx.dtypes[0]),
-                    grad[n].to(device=ctx.devices[1], dtype=ctx.dtypes[1]), None, None, None, None, None)
+            g_rho = grad[:n].to(device=ctx.devices[0], dtype=ctx.dtypes[0]) if need_rho else None
+            # a plain-number Le is a constant: its gradient position stays None
+            g_le = grad[n].to(device=ctx.devices[1], dtype=ctx.dtypes[1]) if need_le else None
+            return g_rho, g_le, None, None, None, None, None
 
     return SPPMRender
 

@@ -22,8 +22,8 @@ __global__ __launch_bounds__(kBlock) void k_eye(SppmDev d, uint32_t k, int32_t a
 }
 
 template <bool kRecord>
-__global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint8_t *__restrict__ mat_tab,
-                                                   double *__restrict__ adj_tab) {
+__global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint16_t *__restrict__ mat_tab,
+                                                   long long *__restrict__ adj_tab) {
     uint32_t n = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (n < d.n_paths) photon_elem<kRecord>(d, k, n, mat_tab, adj_tab);
 }
@@ -32,8 +32,8 @@ __global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint8_
 __global__ __launch_bounds__(kBlock) void k_photon_regen(SppmDev d, uint32_t k) { photon_regen_loop(d, k, d.refill); }
 
 // The same, recording each path's stored-photon materials for the adjoint.
-__global__ __launch_bounds__(kBlock) void k_photon_regen_rec(SppmDev d, uint32_t k, uint8_t *__restrict__ mat_tab,
-                                                             double *__restrict__ adj_tab) {
+__global__ __launch_bounds__(kBlock) void k_photon_regen_rec(SppmDev d, uint32_t k, uint16_t *__restrict__ mat_tab,
+                                                             long long *__restrict__ adj_tab) {
     photon_regen_loop<true>(d, k, d.refill, mat_tab, adj_tab);
 }
 
@@ -159,71 +159,190 @@ __global__ __launch_bounds__(kBlock) void k_init_state(SppmDev d, double r0sq) {
 // contribution c = W rho_h / pi * phi_j, where phi_j carries rho_m / q_m for
 // every earlier diffuse bounce on m.  Per iteration the replayed gather adds
 // G_h = g_h / (pi R2_{h,k} K) times c to the photon's (path, bounce) entry and
-// the hit point's own albedo term G_h * sum c / rho_h; a per-path suffix sum
-// then gives the earlier-bounce terms.  Material sums are reduced in LDS.
+// to the hit point's own material; a per-path suffix sum then gives the
+// earlier-bounce terms.  Dividing by rho_m is left to the end of the iteration.
+//
+// Every sum is an integer sum, so the gradient does not depend on the order of
+// the atomics or of the photons in their buckets.  Each term G_h c is rounded
+// on its own to a fixed point whose scale is a power of two chosen per
+// iteration from two maxima (of |G_h| wk_h over hit points, of the flux over
+// stored photons), so that no term exceeds 2^39 units.  A (path, bounce) entry
+// is a signed 64-bit sum (fewer than 2^24 hit points reach one photon); the
+// per-material sums are 96-bit (two 64-bit words: the low 32 bits of each
+// addend, and the rest), and each iteration's are converted to double once
+// and added to the gradient in iteration order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lds_flush(double *lds, int n_mat, double *__restrict__ grad_mat) {
+constexpr int kAdjTermBits = 39;
+
+using i128 = __int128;
+
+__device__ __forceinline__ void wide_add(unsigned long long *lo, unsigned long long *hi, i128 v) {
+    atomicAdd(lo, (unsigned long long)(uint32_t)(uint64_t)v);
+    atomicAdd(hi, (unsigned long long)(long long)(v >> 32));
+}
+
+// Per-material 96-bit sums: accumulate in LDS, then add each workgroup's sums
+// to the global pair with the carry of the low word moved into the high one.
+struct WideLds {
+    unsigned long long lo[kMaxAdjMat], hi[kMaxAdjMat];
+};
+
+__device__ __forceinline__ void wide_clear(WideLds &w, int n_mat) {
+    for (int m = threadIdx.x; m < n_mat; m += kBlock) {
+        w.lo[m] = 0ull;
+        w.hi[m] = 0ull;
+    }
     __syncthreads();
-    for (int m = threadIdx.x; m < n_mat; m += kBlock)
-        if (lds[m] != 0.0) unsafeAtomicAdd(&grad_mat[m], lds[m]);
+}
+
+__device__ __forceinline__ void wide_flush(WideLds &w, int n_mat, unsigned long long *__restrict__ glob) {
+    __syncthreads();
+    for (int m = threadIdx.x; m < n_mat; m += kBlock) {
+        const unsigned long long lo = w.lo[m], hi = w.hi[m];
+        if (lo | hi) {
+            atomicAdd(&glob[m], lo & 0xffffffffull);
+            atomicAdd(&glob[n_mat + m], hi + (lo >> 32));
+        }
+    }
+}
+
+__device__ __forceinline__ double adj_G(const float *__restrict__ g, int64_t p, double r2, double K) {
+    return (double)g[p] / ((kPiD * r2) * K);
+}
+
+// Clears the iteration's maxima and per-material sums.
+__global__ void k_adj_begin(unsigned long long *__restrict__ adj_max, unsigned long long *__restrict__ wide,
+                            int32_t n_mat) {
+    for (int i = threadIdx.x; i < 2 * n_mat; i += blockDim.x) wide[i] = 0ull;
+    if (threadIdx.x < 2) adj_max[threadIdx.x] = 0ull;
+}
+
+// max over valid hit points of |G_h| wk_h (non-negative doubles order like
+// their bit patterns, so the maximum is an integer maximum)
+__global__ __launch_bounds__(kBlock) void k_adj_gmax(SppmDev d, const double *__restrict__ R2k,
+                                                     const float *__restrict__ g, double K,
+                                                     unsigned long long *__restrict__ adj_max) {
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long v = 0ull;
+    if (p < d.P) {
+        float4 hn = d.hp_nrm[p];
+        if (__float_as_int(hn.w) >= 0) {
+            double a = fabs(adj_G(g, p, R2k[p], K)) * (double)d.hp_pos[p].w;
+            v = (unsigned long long)__double_as_longlong(a);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicMax(&adj_max[0], v);
+}
+
+// max flux over the stored photons
+__global__ __launch_bounds__(kBlock) void k_adj_phimax(SppmDev d, unsigned long long *__restrict__ adj_max) {
+    const uint32_t n = min(d.counters[0], d.cap);
+    unsigned long long v = 0ull;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        unsigned long long b = (unsigned long long)__double_as_longlong((double)d.store[2 * (size_t)i].w);
+        v = b > v ? b : v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0 && v) atomicMax(&adj_max[1], v);
+}
+
+// Scale 2^(39 - e) with 2^e above the product of the two maxima, so
+// |G_h wk_h phi_j| * scale < 2^39 for every pair (0: nothing to add).
+__global__ void k_adj_scale(const unsigned long long *__restrict__ adj_max, double *__restrict__ scale) {
+    if (threadIdx.x == 0) {
+        const double bound = __longlong_as_double((long long)adj_max[0]) * __longlong_as_double((long long)adj_max[1]);
+        double sc = 0.0;
+        if (bound > 0.0 && bound < 1e300) {
+            int e;
+            (void)frexp(bound, &e);  // bound < 2^e
+            sc = ldexp(1.0, kAdjTermBits - e);
+        }
+        *scale = sc;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_adj(SppmDev d, const double *__restrict__ R2k,
                                                        const uint32_t *__restrict__ start,
                                                        const float4 *__restrict__ sorted, const float *__restrict__ g,
-                                                       double K, double *__restrict__ adj_tab, int32_t n_mat,
-                                                       double *__restrict__ grad_mat) {
-    __shared__ double lds[kMaxAdjMat];
-    for (int m = threadIdx.x; m < n_mat; m += kBlock) lds[m] = 0.0;
-    __syncthreads();
+                                                       double K, const double *__restrict__ scale_p,
+                                                       long long *__restrict__ adj_tab, int32_t n_mat,
+                                                       unsigned long long *__restrict__ wide) {
+    __shared__ WideLds lds;
+    wide_clear(lds, n_mat);
+    const double scale = *scale_p;
     int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     float4 hn = p < d.P ? d.hp_nrm[p] : make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
-    if (__float_as_int(hn.w) >= 0 && g[p] != 0.0f) {
+    if (__float_as_int(hn.w) >= 0 && g[p] != 0.0f && scale > 0.0) {
         float4 hx = d.hp_pos[p];
         double r2 = R2k[p];
-        double G = (double)g[p] / ((kPiD * r2) * K);
+        double G = adj_G(g, p, r2, K);
         Grid gr = make_grid(d);
-        double wk = (double)hx.w, csum = 0.0;
+        double wk = (double)hx.w;
+        i128 own = 0;
         const int32_t mb = d.max_bounces;
         for_each_photon_in_disc(d, gr, hx, hn, r2, start, sorted, [&](const float4 &a, const float4 &b) {
             double cc = wk * (double)a.w;
+            long long q = __double2ll_rn((G * cc) * scale);
             uint32_t meta = __float_as_uint(b.w);
-            unsafeAtomicAdd(&adj_tab[(size_t)(meta >> 5) * mb + (meta & 31u)], G * cc);
-            csum += cc;
+            if (q) atomicAdd((unsigned long long *)&adj_tab[(size_t)(meta >> 5) * mb + (meta & 31u)],
+                             (unsigned long long)q);
+            own += q;
         });
-        uint32_t m = __float_as_uint(hn.w);
-        if (csum != 0.0) atomicAdd(&lds[m], G * csum / (double)d.sc.mat_rho[m]);
+        if (own != 0) wide_add(&lds.lo[__float_as_uint(hn.w)], &lds.hi[__float_as_uint(hn.w)], own);
     }
-    lds_flush(lds, n_mat, grad_mat);
+    wide_flush(lds, n_mat, wide);
 }
 
-__global__ __launch_bounds__(kBlock) void k_path_adj(const uint8_t *__restrict__ mat_tab,
-                                                     const double *__restrict__ adj_tab, uint32_t n_paths,
-                                                     int32_t max_bounces, const float *__restrict__ mat_rho,
-                                                     int32_t n_mat, double *__restrict__ grad_mat) {
-    __shared__ double lds[kMaxAdjMat];
-    for (int m = threadIdx.x; m < n_mat; m += kBlock) lds[m] = 0.0;
-    __syncthreads();
+__global__ __launch_bounds__(kBlock) void k_path_adj(const uint16_t *__restrict__ mat_tab,
+                                                     const long long *__restrict__ adj_tab, uint32_t n_paths,
+                                                     int32_t max_bounces, int32_t n_mat,
+                                                     unsigned long long *__restrict__ wide) {
+    __shared__ WideLds lds;
+    wide_clear(lds, n_mat);
     uint32_t n = blockIdx.x * kBlock + threadIdx.x;
     if (n < n_paths) {
-        const uint8_t *row = mat_tab + (size_t)n * max_bounces;
-        const double *arow = adj_tab + (size_t)n * max_bounces;
+        const uint16_t *row = mat_tab + (size_t)n * max_bounces;
+        const long long *arow = adj_tab + (size_t)n * max_bounces;
         int end = 0;
-        while (end < max_bounces && row[end] != 0xfeu) end++;
-        double S = 0.0;  // sensitivity of the photons stored after bounce b
+        while (end < max_bounces && row[end] != kMatEnd) end++;
+        i128 S = 0;  // sensitivity of the photons stored after bounce b
         for (int b = end - 1; b >= 0; --b) {
             uint32_t m = row[b];
-            if (m == 0xffu) continue;
-            if (S != 0.0) atomicAdd(&lds[m], S / (double)mat_rho[m]);
+            if (m == kMatNone) continue;
+            if (S != 0) wide_add(&lds.lo[m], &lds.hi[m], S);
             S += arow[b];
         }
     }
-    lds_flush(lds, n_mat, grad_mat);
+    wide_flush(lds, n_mat, wide);
 }
 
-// sum_p g_p L_p (every term of L_p is proportional to the emitted radiance)
+// grad_mat[m] += (iteration's integer sum for m) / scale / rho_m, one
+// iteration after another (the order of these additions is fixed).
+__global__ void k_adj_fold(const unsigned long long *__restrict__ wide, int32_t n_mat,
+                           const double *__restrict__ scale_p, const float *__restrict__ mat_rho,
+                           double *__restrict__ grad_mat) {
+    const double scale = *scale_p;
+    for (int m = threadIdx.x; m < n_mat; m += blockDim.x) {
+        const unsigned long long lo = wide[m];
+        const long long hi = (long long)(wide[n_mat + m] + (lo >> 32));
+        if (scale > 0.0 && (hi != 0 || (lo & 0xffffffffull) != 0ull) && mat_rho[m] > 0.0f) {
+            const double v = (double)hi * 4294967296.0 + (double)(lo & 0xffffffffull);
+            grad_mat[m] += (v / scale) / (double)mat_rho[m];
+        }
+    }
+}
+
+// Per-workgroup partial sums of g_p L_p (every term of L_p is proportional to
+// the emitted radiance); k_collect_grad adds them in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_le_grad(SppmDev d, double K, const float *__restrict__ g,
-                                                    double *__restrict__ out) {
+                                                    double *__restrict__ part) {
     __shared__ double lds[kBlock / 64];
     int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double v = 0.0;
@@ -234,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_le_grad(SppmDev d, double K, const f
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) t += lds[w];
-        unsafeAtomicAdd(out, t);
+        part[blockIdx.x] = t;
     }
 }
 
@@ -247,11 +366,23 @@ struct ParamMats {
     uint8_t m[kMaxAdjMat];
 };
 
-__global__ void k_collect_grad(const double *__restrict__ grad_mat, ParamMats pm, int32_t n_par,
-                               const double *__restrict__ le_sum, double inv_Le, double *__restrict__ out) {
-    int i = threadIdx.x;
+// One workgroup of kMaxAdjMat threads: parameter gradients, and the emission
+// gradient as a fixed-order sum of the partial sums of g L.
+__global__ __launch_bounds__(kMaxAdjMat) void k_collect_grad(const double *__restrict__ grad_mat, ParamMats pm,
+                                                             int32_t n_par, const double *__restrict__ le_part,
+                                                             int32_t n_part, double inv_Le, double *__restrict__ out) {
+    __shared__ double lds[kMaxAdjMat];
+    const int i = threadIdx.x;
+    double t = 0.0;
+    for (int j = i; j < n_part; j += kMaxAdjMat) t += le_part[j];
+    lds[i] = t;
+    __syncthreads();
+    for (int w = kMaxAdjMat / 2; w > 0; w >>= 1) {
+        if (i < w) lds[i] += lds[i + w];
+        __syncthreads();
+    }
     if (i < n_par) out[i] = grad_mat[pm.m[i]];
-    if (i == n_par) out[i] = *le_sum * inv_Le;
+    if (i == n_par) out[i] = lds[0] * inv_Le;
 }
 
 inline uint32_t blocks_for(int64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
@@ -278,7 +409,7 @@ void sppm_free(pm_sppm *s) {
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
                     s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
-                    s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
+                    s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
@@ -305,8 +436,6 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
         if (t < 0 || t > 2) return set_error("unknown material type"), PM_ERR_ARG;
         if (!(d->mat_rho[m] >= 0.0f && d->mat_rho[m] < 1.0f)) return set_error("albedo must be in [0,1)"), PM_ERR_ARG;
         if (!(d->mat_q[m] >= 0.0f && d->mat_q[m] <= 1.0f)) return set_error("RR probability must be in [0,1]"), PM_ERR_ARG;
-        if (d->mat_rho[m] > 0.0f && !(d->mat_q[m] > 0.0f))
-            return set_error("RR probability must be > 0 where albedo > 0"), PM_ERR_ARG;
         if (!(d->mat_Le[m] >= 0.0f) || !std::isfinite(d->mat_Le[m])) return set_error("Le must be finite and >= 0"), PM_ERR_ARG;
         if (t == PM_MAT_GLASS && !(d->mat_ior[m] > 0.0f)) return set_error("glass ior must be > 0"), PM_ERR_ARG;
     }
@@ -338,6 +467,9 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
         return set_error("record_iterations must be in [0, 100000]"), PM_ERR_ARG;
     if (p->record_iterations > 0 && d->n_mat > kMaxAdjMat)
         return set_error("the adjoint supports at most 256 materials"), PM_ERR_ARG;
+    // a photon's (path, bounce) entry sums at most one term of 2^39 units per pixel
+    if (p->record_iterations > 0 && (int64_t)d->width * d->height >= (int64_t(1) << 24))
+        return set_error("the adjoint supports images below 2^24 pixels"), PM_ERR_ARG;
     return PM_OK;
 }
 
@@ -449,9 +581,13 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     s->rec_iters = p->record_iterations;
     if (s->rec_iters > 0) {
         PM_HIPF(hipMalloc(&s->R2_hist, sizeof(double) * (size_t)s->rec_iters * s->P));
-        PM_HIPF(hipMalloc(&s->adj_tab, sizeof(double) * (size_t)p->n_photons * p->max_photon_bounces));
-        PM_HIPF(hipMalloc(&s->mat_tab, (size_t)p->n_photons * p->max_photon_bounces));
+        PM_HIPF(hipMalloc(&s->adj_tab, sizeof(long long) * (size_t)p->n_photons * p->max_photon_bounces));
+        PM_HIPF(hipMalloc(&s->mat_tab, sizeof(uint16_t) * (size_t)p->n_photons * p->max_photon_bounces));
         PM_HIPF(hipMalloc(&s->grad_mat, sizeof(double) * (nm + 1)));
+        PM_HIPF(hipMalloc(&s->adj_wide, sizeof(unsigned long long) * 2 * nm));
+        PM_HIPF(hipMalloc(&s->adj_max, sizeof(unsigned long long) * 2));
+        PM_HIPF(hipMalloc(&s->adj_scale, sizeof(double)));
+        PM_HIPF(hipMalloc(&s->le_part, sizeof(double) * blocks_for(s->P)));
     }
     {
         int n_emit_mat = 0;
@@ -614,8 +750,8 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
             hipLaunchKernelGGL(k_pass_tally, dim3(1), dim3(64), 0, st, d);
             hipLaunchKernelGGL(k_photon_drain, dim3(blocks_for(ps.S)), dim3(kBlock), 0, st, d, k, ps);
         } else
-            hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint8_t *)nullptr,
-                               (double *)nullptr);
+            hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint16_t *)nullptr,
+                               (long long *)nullptr);
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         if (d.gather_mode == PM_GATHER_STOCHASTIC) {
             hipLaunchKernelGGL(k_sh_clear, dim3(std::min<uint32_t>(blocks_for(T), 4096u)), dim3(kBlock), 0, st, d, T);
@@ -684,30 +820,40 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
     for (int32_t k = 0; k < s->K; ++k) {
         const double *R2k = s->R2_hist + (size_t)k * s->P;
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, d);
+        hipLaunchKernelGGL(k_adj_begin, dim3(1), dim3(kBlock), 0, st, s->adj_max, s->adj_wide, s->n_mat);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
-        // replayed eye pass and R_max beside the replayed photon pass, as in the forward iteration
+        // replayed eye pass, R_max and max |G| wk beside the replayed photon pass, as in the forward iteration
         PM_HIP(hipEventRecord(s->ev_fork, st));
         PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
         hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, (uint32_t)k, 0);
         hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d, R2k);
+        hipLaunchKernelGGL(k_adj_gmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, R2k, g, K, s->adj_max);
         PM_HIP(hipEventRecord(s->ev_join, s->side));
         hipLaunchKernelGGL(k_photon_regen_rec, dim3(s->regen_grid_rec), dim3(kBlock), 0, st, d, (uint32_t)k,
                            s->mat_tab, s->adj_tab);
+        hipLaunchKernelGGL(k_adj_phimax, dim3(std::min<uint32_t>(ph_blocks, 1024u)), dim3(kBlock), 0, st, d,
+                           s->adj_max);
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+        hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(64), 0, st, (const unsigned long long *)s->adj_max,
+                           s->adj_scale);
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
         launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
         hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, (const uint32_t *)s->cell_start,
-                               s->sorted);
+                           s->sorted);
         hipLaunchKernelGGL(k_gather_adj, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, R2k,
-                           (const uint32_t *)s->cell_start, (const float4 *)s->sorted, g, K, s->adj_tab, s->n_mat,
-                           s->grad_mat);
-        hipLaunchKernelGGL(k_path_adj, dim3(blocks_for(np)), dim3(kBlock), 0, st, s->mat_tab, s->adj_tab, np, mb,
-                           d.sc.mat_rho, s->n_mat, s->grad_mat);
+                           (const uint32_t *)s->cell_start, (const float4 *)s->sorted, g, K,
+                           (const double *)s->adj_scale, s->adj_tab, s->n_mat, s->adj_wide);
+        hipLaunchKernelGGL(k_path_adj, dim3(blocks_for(np)), dim3(kBlock), 0, st, (const uint16_t *)s->mat_tab,
+                           (const long long *)s->adj_tab, np, mb, s->n_mat, s->adj_wide);
+        hipLaunchKernelGGL(k_adj_fold, dim3(1), dim3(kMaxAdjMat), 0, st, (const unsigned long long *)s->adj_wide,
+                           s->n_mat, (const double *)s->adj_scale, d.sc.mat_rho, s->grad_mat);
         PM_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_le_grad, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, K, g, s->grad_mat + s->n_mat);
+    const uint32_t n_part = blocks_for(s->P);
+    hipLaunchKernelGGL(k_le_grad, dim3(n_part), dim3(kBlock), 0, st, d, K, g, s->le_part);
     hipLaunchKernelGGL(k_collect_grad, dim3(1), dim3(kMaxAdjMat), 0, st, s->grad_mat, pms, n_par,
-                       s->grad_mat + s->n_mat, s->le_single > 0.0 ? 1.0 / s->le_single : 0.0, grad);
+                       (const double *)s->le_part, (int32_t)n_part, s->le_single > 0.0 ? 1.0 / s->le_single : 0.0,
+                       grad);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }

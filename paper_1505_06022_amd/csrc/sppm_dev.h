@@ -10,6 +10,9 @@ constexpr int kBlock = 256;
 constexpr int kScanItems = 16;                  // per thread
 constexpr int kScanTile = kBlock * kScanItems;  // buckets per scan tile
 constexpr int kMaxAdjMat = 256;
+// markers of the adjoint's per-path material table (entries are uint16)
+constexpr uint16_t kMatNone = 0xffffu;  // no photon stored at this bounce
+constexpr uint16_t kMatEnd = 0xfffeu;   // the path ended before this bounce
 
 struct SceneDev {
     Bvh bvh;
@@ -181,11 +184,12 @@ __device__ __forceinline__ bool photon_emit(const SppmDev &d, uint32_t k, uint32
 
 // One bounce of a live path; returns true while the path continues.
 // kRecord (adjoint replay): row n of mat_tab gets, per bounce, the material of
-// a stored photon (0xff: none at that bounce), and the matching entries of
-// adj_tab are cleared for the adjoint gather; photon_finish marks the end.
+// a stored photon (kMatNone: none at that bounce), and the matching entries of
+// adj_tab are cleared for the adjoint gather; photon_finish marks the end
+// (kMatEnd).  Material ids are below kMaxAdjMat, so neither marker is a material.
 template <bool kRecord>
-__device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, uint8_t *__restrict__ mat_tab,
-                                              double *__restrict__ adj_tab) {
+__device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, uint16_t *__restrict__ mat_tab,
+                                              long long *__restrict__ adj_tab) {
     const SceneDev &sc = d.sc;
     const int32_t mb = d.max_bounces;
     const int b = P.b;
@@ -200,17 +204,17 @@ __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, u
     V3 nrm = tri_normal(tr);
     uint32_t m = tr.mat;
     int type = sc.mat_type[m];
-    uint8_t *row = kRecord ? mat_tab + (size_t)P.n * mb : nullptr;
+    uint16_t *row = kRecord ? mat_tab + (size_t)P.n * mb : nullptr;
     if (kRecord) {
-        row[b] = 0xffu;
+        row[b] = kMatNone;
         P.last = b;
     }
     if (type == PM_MAT_DIFFUSE) {
         float rho = sc.mat_rho[m];
         if (!(rho > 0.0f)) return false;
         if (kRecord) {
-            row[b] = (uint8_t)m;
-            adj_tab[(size_t)P.n * mb + b] = 0.0;
+            row[b] = (uint16_t)m;
+            adj_tab[(size_t)P.n * mb + b] = 0;
         }
         uint32_t slot = wave_append(&d.counters[0]);
         if (slot < d.cap) {
@@ -237,14 +241,14 @@ __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, u
 }
 
 template <bool kRecord>
-__device__ __forceinline__ void photon_finish(const SppmDev &d, const PhotonPath &P, uint8_t *__restrict__ mat_tab) {
-    if (kRecord && P.last + 1 < d.max_bounces) mat_tab[(size_t)P.n * d.max_bounces + P.last + 1] = 0xfeu;
+__device__ __forceinline__ void photon_finish(const SppmDev &d, const PhotonPath &P, uint16_t *__restrict__ mat_tab) {
+    if (kRecord && P.last + 1 < d.max_bounces) mat_tab[(size_t)P.n * d.max_bounces + P.last + 1] = kMatEnd;
 }
 
 // Photon path n traced to its end by one lane.
 template <bool kRecord>
-__device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32_t n, uint8_t *__restrict__ mat_tab,
-                                            double *__restrict__ adj_tab) {
+__device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32_t n, uint16_t *__restrict__ mat_tab,
+                                            long long *__restrict__ adj_tab) {
     PhotonPath P;
     if (photon_emit(d, k, n, P))
         while (photon_bounce<kRecord>(d, P, mat_tab, adj_tab)) {
@@ -262,8 +266,8 @@ __device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32
 // as in photon_elem.
 template <bool kRecord = false>
 __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, uint32_t refill,
-                                                  uint8_t *__restrict__ mat_tab = nullptr,
-                                                  double *__restrict__ adj_tab = nullptr) {
+                                                  uint16_t *__restrict__ mat_tab = nullptr,
+                                                  long long *__restrict__ adj_tab = nullptr) {
     PhotonPath P;
     bool live = false, exhausted = false;
     for (;;) {

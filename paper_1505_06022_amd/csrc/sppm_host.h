@@ -41,9 +41,13 @@ struct pm_sppm {
     std::vector<float> rho_host;  // albedos (validation of adjoint parameters)
     double le_single = 0.0;  // Le of the single emitting material, 0 if not exactly one
     double *R2_hist = nullptr;    // [rec_iters][P] radius used in each iteration
-    double *adj_tab = nullptr;    // [n_photons][max_bounces] photon sensitivities
-    uint8_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
-    double *grad_mat = nullptr;   // [n_mat + 1]; last entry: sum g L
+    long long *adj_tab = nullptr;  // [n_photons][max_bounces] photon sensitivities (fixed point, see adj_*)
+    uint16_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
+    double *grad_mat = nullptr;    // [n_mat + 1]; last entry: sum g L
+    unsigned long long *adj_wide = nullptr;  // [2][n_mat] per-material integer sums of one iteration (lo | hi)
+    unsigned long long *adj_max = nullptr;   // [2] max |G| wk over hit points, max flux over photons (double bits)
+    double *adj_scale = nullptr;             // [1] fixed-point scale of the current iteration
+    double *le_part = nullptr;               // [blocks over pixels] partial sums of g L
     uint64_t scene_hash = 0;      // fingerprint of the scene description (checkpoint matching)
     // the eye pass runs beside the photon pass on a second stream (default
     // priority), forked from and joined back to the caller's stream by events
