@@ -201,6 +201,28 @@ typedef struct {
 PM_API int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
                      const pm_trace_opts *opts, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * bucketed trace of pm_trace_rays_ex (reorder 1 or 2; 0 or NULL opts mean 1)
+ * with its scratch in a static per-device array of the library instead of
+ * the BVH handle's growable buffer.  The call allocates and frees nothing.
+ *   rays, hit, t  device buffers as for pm_trace_rays (caller-owned)
+ *   n             0 .. PM_NOALLOC_MAX_RAYS
+ * The array (12 B per ray of PM_NOALLOC_MAX_RAYS plus 9.4 MB of bucket
+ * arrays, about 60 MB) is set aside on every device the library's code is
+ * loaded on and held until the process ends; its address is looked up on the
+ * first call on each device.  Every call on one device shares it and it keeps
+ * the last call's contents (the bucket counters are cleared by a kernel at
+ * the start of each call): calls that overlap on one device, on different
+ * streams or host threads, race and give wrong results.  Results equal those
+ * of pm_trace_rays_ex with the same options.  The BVH must live on the current
+ * device.  Asynchronous on `stream`.
+ * Errors: PM_ERR_ARG for n above PM_NOALLOC_MAX_RAYS, reorder other than
+ * 0..2, tile_width, another device or the rules of pm_trace_rays_ex. */
+#define PM_NOALLOC_MAX_RAYS (1 << 22)
+PM_API int pm_trace_rays_noalloc(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
+                                 const pm_trace_opts *opts, void *stream);
+
 /* One batch of rays for pm_trace_rays_multi: arguments as for
  * pm_trace_rays_ex (opts may be NULL). */
 typedef struct {

@@ -23,7 +23,7 @@ EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
            "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
            "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch", "pm_probe_chase",
-           "pm_trace_rays_multi"]
+           "pm_trace_rays_multi", "pm_trace_rays_noalloc"]
 
 
 class PMError(RuntimeError):
@@ -122,6 +122,7 @@ def lib() -> C.CDLL:
         L.pm_bvh_download.argtypes = [P, P, P, P]
         L.pm_trace_rays.argtypes = [P, P, I64, P, P, P]
         L.pm_trace_rays_ex.argtypes = [P, P, I64, P, P, P, P]
+        L.pm_trace_rays_noalloc.argtypes = [P, P, I64, P, P, P, P]
         L.pm_sppm_create.argtypes = [P, P, P, P]
         L.pm_sppm_destroy.argtypes = [P]
         L.pm_sppm_iterate.argtypes = [P, I32, P]
@@ -273,6 +274,22 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
         o.tile_width = int(tile_width)
         o.counters = None if counters is None else counters.data_ptr()
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
+    return hit, t
+
+
+NOALLOC_MAX_RAYS = 1 << 22
+
+
+def trace_rays_noalloc(bvh: Bvh, rays, hit, t, link_set: int = -1, counters=None, kernel: int = 0, refill: int = 0,
+                       reorder: int = 1, block: int = 0, stream=None):
+    """The bucketed trace on the library's static scratch (pm_trace_rays_noalloc):
+    the caller passes the outputs hit (int32 cuda [n]) and t (float32 cuda [n])."""
+    import torch
+    assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
+    n = rays.shape[0]
+    assert hit.dtype == torch.int32 and t.dtype == torch.float32 and hit.numel() >= n and t.numel() >= n
+    o = _trace_opts(link_set, counters, kernel, refill, reorder, block, 0)
+    _check(lib().pm_trace_rays_noalloc(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t
 
 

@@ -241,6 +241,25 @@ int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *h
     })
 }
 
+int pm_trace_rays_noalloc(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *hit, float *t,
+                          const pm_trace_opts *opts, void *stream) {
+    pm::TraceRange range_("pm_trace_rays_noalloc");
+    PM_GUARD({
+        if (n > (int64_t)PM_NOALLOC_MAX_RAYS)
+            return pm::set_error("n = " + std::to_string(n) + " exceeds PM_NOALLOC_MAX_RAYS = " +
+                                 std::to_string((int64_t)PM_NOALLOC_MAX_RAYS)),
+                   PM_ERR_ARG;
+        if (!bvh) return pm::set_error("NULL bvh"), PM_ERR_ARG;
+        pm::TraceArgs a;
+        int rc = parse_trace(rays, n, hit, t, opts, a);
+        if (rc) return rc;
+        if (a.reorder == 0) a.reorder = 1;
+        if (a.tile_w != 0) return pm::set_error("tile_width does not apply to the bucketed trace"), PM_ERR_ARG;
+        return pm::launch_trace_noalloc(bvh, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill,
+                                        a.reorder, a.block, (hipStream_t)stream);
+    })
+}
+
 int pm_trace_rays_multi(const pm_bvh *bvh, int32_t n_batches, const pm_trace_batch *batches, void *stream) {
     pm::TraceRange range_("pm_trace_rays_multi");
     PM_GUARD({

@@ -79,6 +79,12 @@ void free_bvh(pm_bvh *b);
 int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
                  uint32_t *counters, int kernel, int refill, int reorder, int block, int tile_w, hipStream_t s);
 
+// The bucketed trace (reorder 1 or 2) on the library's static per-device
+// scratch: no allocation; n <= PM_NOALLOC_MAX_RAYS; b must be on the current
+// device.
+int launch_trace_noalloc(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
+                         uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s);
+
 // Validated arguments of one traced batch.
 struct TraceArgs {
     const float *rays = nullptr;

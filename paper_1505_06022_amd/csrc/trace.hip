@@ -1,5 +1,6 @@
 // Closest-hit ray traversal of the multiple-threaded BVH (Sec. 3.1).
 #include <algorithm>
+#include <mutex>
 
 #include "pm_device.h"
 #include "runtime.h"
@@ -405,22 +406,39 @@ static int launch_persistent(const pm_bvh *b, const pmd::Bvh &bvh, const float *
     return PM_OK;
 }
 
-// Bucket the rays (count, scan, scatter): b->d_perm receives the order.
-static int bucket_rays(pm_bvh *b, const float *rays, int64_t n, int link_set, int reorder, hipStream_t s) {
+// Scratch of the bucketed trace: the ray order [perm_cap] followed, at an
+// 8-byte aligned offset, by each ray's (bucket, rank) [perm_cap]; and the
+// bucket arrays (counts, starts, fill cursors, scan block sums).
+struct BucketScratch {
+    uint32_t *perm;
+    uint64_t perm_cap;
+    uint32_t *order;
+};
+constexpr size_t kOrderWords = (3 * (size_t)kOrderBucketsFine + 1 + kOrderBucketsFine / 4096 + 1 + 63) & ~size_t(63);
+
+constexpr size_t perm_words(uint64_t cap) { return 3 * (size_t)cap + 2; }
+
+// The BVH handle's own scratch, grown (after the stream's work) for more rays.
+static int bvh_scratch(pm_bvh *b, int64_t n, hipStream_t s, BucketScratch &sc) {
     if ((uint64_t)n > b->perm_cap) {
         if (b->d_perm) {
             PM_HIP(hipStreamSynchronize(s));
             PM_HIP(hipFree(b->d_perm));
             b->d_perm = nullptr;
         }
-        // ray order, then each ray's (bucket, rank) pair at an 8-byte aligned offset
-        PM_HIP(hipMalloc(&b->d_perm, sizeof(uint32_t) * (3 * (size_t)n + 2)));
+        PM_HIP(hipMalloc(&b->d_perm, sizeof(uint32_t) * perm_words((uint64_t)n)));
         b->perm_cap = (uint64_t)n;
     }
+    if (!b->d_order) PM_HIP(hipMalloc(&b->d_order, sizeof(uint32_t) * kOrderWords));
+    sc = BucketScratch{b->d_perm, b->perm_cap, b->d_order};
+    return PM_OK;
+}
+
+// Bucket the rays (count, scan, scatter) into sc.perm: kernels only, no allocation.
+static int bucket_rays(const pm_bvh *b, const BucketScratch &sc, const float *rays, int64_t n, int link_set,
+                       int reorder, hipStream_t s) {
     const uint32_t nbk = reorder == 2 ? kOrderBucketsFine : kOrderBucketsCoarse;
-    if (!b->d_order)
-        PM_HIP(hipMalloc(&b->d_order, sizeof(uint32_t) * (3 * kOrderBucketsFine + 1 + kOrderBucketsFine / 4096 + 1)));
-    uint32_t *counts = b->d_order, *start = counts + nbk, *fill = start + nbk + 1;
+    uint32_t *counts = sc.order, *start = counts + nbk, *fill = start + nbk + 1;
     uint32_t *bsum = fill + nbk;
     OrderBox ob;
     ob.cells = reorder == 2 ? 32u : 16u;
@@ -432,24 +450,24 @@ static int bucket_rays(pm_bvh *b, const float *rays, int64_t n, int link_set, in
     }
     const uint32_t nn = (uint32_t)n, blocks = (uint32_t)((n + kTraceBlock - 1) / kTraceBlock);
     hipLaunchKernelGGL(k_fill_u32, dim3((nbk + 255) / 256), dim3(256), 0, s, counts, nbk, 0u);
-    uint2 *key_rank = (uint2 *)(b->d_perm + ((b->perm_cap + 1) & ~uint64_t(1)));
+    uint2 *key_rank = (uint2 *)(sc.perm + ((sc.perm_cap + 1) & ~uint64_t(1)));
     hipLaunchKernelGGL(k_ray_count, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
                        counts, key_rank);
     launch_bucket_scan(counts, start, fill, bsum, nbk, s);
     hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const uint2 *)key_rank, nn,
-                       (const uint32_t *)start, b->d_perm);
+                       (const uint32_t *)start, sc.perm);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }
 
-static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *rays, int64_t n, int32_t *hit,
-                                  float *t, int link_set, uint32_t *counters, int kernel, uint32_t late,
-                                  int reorder, uint32_t block, hipStream_t s) {
-    int rc = bucket_rays(b, rays, n, link_set, reorder, s);
+static int launch_trace_reordered(const pm_bvh *b, const BucketScratch &sc, const pmd::Bvh &bvh, const float *rays,
+                                  int64_t n, int32_t *hit, float *t, int link_set, uint32_t *counters, int kernel,
+                                  uint32_t late, int reorder, uint32_t block, hipStream_t s) {
+    int rc = bucket_rays(b, sc, rays, n, link_set, reorder, s);
     if (rc) return rc;
     const uint32_t nn = (uint32_t)n;
     if (kernel == PM_TRACE_PERSISTENT)
-        return launch_persistent(b, bvh, rays, nn, hit, t, link_set, counters, (int)late, b->d_perm, s);
+        return launch_persistent(b, bvh, rays, nn, hit, t, link_set, counters, (int)late, sc.perm, s);
     using Kern = void (*)(pmd::Bvh, const float4 *, const uint32_t *, uint32_t, int32_t *, float *, int32_t,
                           uint32_t *, uint32_t);
     const int wk = walk_of(kernel);
@@ -461,8 +479,36 @@ static int launch_trace_reordered(pm_bvh *b, const pmd::Bvh &bvh, const float *r
                                            k_trace_perm<false, kWalkPacket>);
     const uint32_t lanes = wk == kWalkTwo ? (nn + 1) / 2 : nn;
     hipLaunchKernelGGL(kern, dim3((lanes + block - 1) / block), dim3(block), 0, s, bvh, (const float4 *)rays,
-                       (const uint32_t *)b->d_perm, nn, hit, t, link_set, counters, late);
+                       (const uint32_t *)sc.perm, nn, hit, t, link_set, counters, late);
     PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
+// Scratch of the allocation-free bucketed trace: one array per device, set
+// aside when the library's code is loaded on that device and kept until the
+// process ends.  Host code must not pass `scratch` itself to a kernel (its
+// host-side name is not a device address): it uses the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint32_t scratch[kOrderWords + perm_words(PM_NOALLOC_MAX_RAYS)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int noalloc_scratch(int device, BucketScratch &sc) {
+    if (device < 0 || device >= kMaxDevices) return set_error("device index out of range"), PM_ERR_ARG;
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            // the first call on this device (which is current): look the array up once
+            PM_HIP(hipGetSymbolAddress(&g_scratch_ptr[device], HIP_SYMBOL(scratch)));
+            if (!g_scratch_ptr[device]) return set_error("scratch array has no device address"), PM_ERR_HIP;
+        }
+        ptr = g_scratch_ptr[device];
+    }
+    uint32_t *base = (uint32_t *)ptr;
+    sc = BucketScratch{base + kOrderWords, (uint64_t)PM_NOALLOC_MAX_RAYS, base};
     return PM_OK;
 }
 
@@ -474,9 +520,13 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
     // the postponed walk reads its threshold from the refill option (and the
     // persistent one its refill count)
     const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT ? (uint32_t)refill : 0u;
-    if (reorder)
-        return launch_trace_reordered(const_cast<pm_bvh *>(b), bvh, rays, n, hit, t, link_set, counters, kernel,
-                                      late, reorder, (uint32_t)block, s);
+    if (reorder) {
+        BucketScratch sc;
+        int rc = bvh_scratch(const_cast<pm_bvh *>(b), n, s, sc);
+        if (rc) return rc;
+        return launch_trace_reordered(b, sc, bvh, rays, n, hit, t, link_set, counters, kernel, late, reorder,
+                                      (uint32_t)block, s);
+    }
     if (kernel == 0) kernel = PM_TRACE_PER_RAY;
     if (kernel == PM_TRACE_PERSISTENT) {
         if (n >= (int64_t(1) << 31)) {
@@ -511,7 +561,10 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
 }
 
 static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs &B, int block, hipStream_t s) {
-    int rc = bucket_rays(b, A.rays, A.n, A.link_set, A.reorder, s);
+    BucketScratch sc;
+    int rc = bvh_scratch(b, A.n, s, sc);
+    if (rc) return rc;
+    rc = bucket_rays(b, sc, A.rays, A.n, A.link_set, A.reorder, s);
     if (rc) return rc;
     const pmd::Bvh bvh = make_device_bvh(b);
     const uint32_t nA = (uint32_t)A.n;
@@ -521,7 +574,7 @@ static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs
     if (blocksA + blocksB > 0x7fffffffull) return set_error("too many rays for one launch"), PM_ERR_ARG;
     hipLaunchKernelGGL(A.counters ? k_trace_perm_then_tiles<true> : k_trace_perm_then_tiles<false>,
                        dim3((uint32_t)(blocksA + blocksB)), dim3(block), 0, s, bvh, (uint32_t)blocksA,
-                       (const float4 *)A.rays, (const uint32_t *)b->d_perm, nA, A.hit, A.t, A.link_set, A.counters,
+                       (const float4 *)A.rays, (const uint32_t *)sc.perm, nA, A.hit, A.t, A.link_set, A.counters,
                        (uint32_t)A.refill, (const float4 *)B.rays, B.n, B.hit, B.t, B.link_set, B.counters,
                        (uint32_t)B.tile_w);
     PM_HIP(hipGetLastError());
@@ -559,6 +612,23 @@ int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, h
         PM_HIP(hipStreamWaitEvent(s, b->ev_join[k], 0));
     }
     return rc;
+}
+
+int launch_trace_noalloc(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
+                         uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s) {
+    if (n > (int64_t)PM_NOALLOC_MAX_RAYS) return set_error("n exceeds PM_NOALLOC_MAX_RAYS"), PM_ERR_ARG;
+    if (reorder != 1 && reorder != 2) return set_error("the allocation-free trace buckets the rays: reorder 1 or 2"), PM_ERR_ARG;
+    int dev = -1;
+    PM_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return set_error("the BVH lives on another device than the current one"), PM_ERR_ARG;
+    BucketScratch sc;
+    int rc = noalloc_scratch(dev, sc);
+    if (rc) return rc;
+    if (n == 0) return PM_OK;
+    if (block == 0) block = kDefaultWalkBlock;
+    const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT ? (uint32_t)refill : 0u;
+    return launch_trace_reordered(b, sc, make_device_bvh(b), rays, n, hit, t, link_set, counters, kernel, late, reorder,
+                                  (uint32_t)block, s);
 }
 
 }  // namespace pm
