@@ -1,5 +1,6 @@
 // Closest-hit ray traversal of the multiple-threaded BVH (Sec. 3.1).
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include "pm_device.h"
@@ -355,20 +356,20 @@ void free_bvh(pm_bvh *b) {
     b->d_next = nullptr;
 }
 
-static int persistent_grid(hipStream_t s, int device, uint32_t &grid) {
-    static int cached_dev = -1;
-    static uint32_t cached = 0;
-    if (cached_dev == device) {
-        grid = cached;
-        return PM_OK;
-    }
+// Workgroups of the persistent kernel that fill a device, cached per device
+// (0: not computed yet); any host thread may call this.
+constexpr int kMaxDevices = 64;
+static std::atomic<uint32_t> g_persistent_grid[kMaxDevices];
+
+static int persistent_grid(int device, uint32_t &grid) {
+    if (device < 0 || device >= kMaxDevices) return set_error("device index out of range"), PM_ERR_ARG;
+    grid = g_persistent_grid[device].load(std::memory_order_relaxed);
+    if (grid != 0) return PM_OK;
     int cus = 0, per_cu = 0;
     PM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     PM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_trace_persistent<false>, kTraceBlock, 0));
-    cached = (uint32_t)std::max(1, cus * std::max(1, per_cu));
-    cached_dev = device;
-    grid = cached;
-    (void)s;
+    grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+    g_persistent_grid[device].store(grid, std::memory_order_relaxed);  // racing threads store the same value
     return PM_OK;
 }
 
@@ -395,7 +396,7 @@ static int launch_persistent(const pm_bvh *b, const pmd::Bvh &bvh, const float *
                              float *t, int link_set, uint32_t *counters, int refill, const uint32_t *perm,
                              hipStream_t s) {
     uint32_t grid = 0;
-    int rc = persistent_grid(s, b->device, grid);
+    int rc = persistent_grid(b->device, grid);
     if (rc) return rc;
     uint32_t rf = refill > 0 ? (uint32_t)refill : 16u;
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->d_next);
@@ -491,7 +492,6 @@ static int launch_trace_reordered(const pm_bvh *b, const BucketScratch &sc, cons
 // hipGetSymbolAddress returns for the current device.
 static __device__ __align__(256) uint32_t scratch[kOrderWords + perm_words(PM_NOALLOC_MAX_RAYS)];
 
-constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mu;
 static void *g_scratch_ptr[kMaxDevices];
 
