@@ -116,16 +116,44 @@ def _parse():
     ap.add_argument("--incoherent", default="postponed_late32_reorder1_block64", choices=names,
                     help="traversal options of the incoherent batch")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="first run a plain 1 GiB device-to-device copy (calibrates HBM byte counters)")
+                    help="first run the library's 1 GiB stream copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
 def _cpu_threads() -> int:
+    """Host threads for the oracle: the cores this process may run on, capped by
+    OMP_NUM_THREADS where the machine sets it (a GPU host's share per GPU)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def _host_info() -> dict:
+    """nproc, the cores this process may use, and the CPU model (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        model = next((ln.split(":", 1)[1].strip() for ln in out.splitlines() if ln.startswith("Model name")), None)
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+        except OSError:
+            pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"nproc": os.cpu_count(), "affinity_cores": aff, "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": model}
 
 
 def traversal_bench(args, torch, api, scenes):
@@ -305,6 +333,17 @@ def sppm_bench(args, torch, api, scenes):
     s.status()
     n_stored = int(s.views()["photon_count"][0].item())
     s.destroy()
+    # the whole configuration: 64 iterations and the resolve, from a fresh handle (creation not timed)
+    full = api.Sppm(sc, p, bvh=bvh)
+    torch.cuda.synchronize()
+    e0.record(st)
+    full.iterate(64)
+    full.resolve()
+    e1.record(st)
+    torch.cuda.synchronize()
+    full.status()
+    full.destroy()
+    full_ms = e0.elapsed_time(e1)
     variants, tbvh = {}, {}
     runs = [("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
             ("regen_refill16", dict(photon_kernel=2, refill=16)), ("regen_refill32", dict(photon_kernel=2, refill=32))]
@@ -351,41 +390,82 @@ def sppm_bench(args, torch, api, scenes):
         sv.destroy()
     bvh.destroy()
     return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
+                full_render={"iterations": 64, "ms": round(full_ms, 2),
+                             "photons_per_s": round(64 * Np / (full_ms * 1e-3), 1)},
                 tbvh=tbvh, stochastic_hashing=sh, pass_schedule=schedule,
                 workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
 def adjoint_bench(args, torch, api, scenes):
-    """Forward K iterations + resolve, then the replay adjoint of an L2 image
-    loss, on the 250k-triangle scene at full size (same K and photon count for
-    both, so the forward image and its RMSE are identical by construction)."""
+    """The adjoint workload on the 250k-triangle scene at full size: 16 diffuse
+    albedos and Le as parameters, L2 image loss against a target rendered at
+    albedos perturbed by U[-0.1, 0.1] (same seed and K), gradient through the
+    torch.autograd.Function.  Forward and forward+adjoint use the same K and
+    photon count with common random numbers, so the forward image and its RMSE
+    are identical by construction.  Two ratios: the autograd route end to end
+    (its forward also creates the handle), and the device work of direct calls
+    (K iterations + resolve against the replay adjoint)."""
     sc = scenes.procedural_scene()
     v = sc.verts.reshape(-1, 3)
     diag = float(np.linalg.norm(v.max(0) - v.min(0)))
     Np, K = 1 << 20, args.adjoint_iters
-    p = api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, record_iterations=K)
-    s = api.Sppm(sc, p)
+    r0 = 0.05 * diag * 64 / 1280
+    p = api.sppm_params(Np, alpha=0.7, r0=r0, seed=3)
+    pm = sc.albedo_params
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    rng = np.random.default_rng(11)
+    rho_t = sc.mat_rho.copy()
+    rho_t[pm] = np.clip(rho_t[pm] + rng.uniform(-0.1, 0.1, len(pm)).astype(np.float32), 0.01, 0.99)
+    target = api.render(sc.with_rho(rho_t), p, K, bvh=bvh).double()
+    light = int(np.nonzero(sc.mat_Le > 0)[0][0])
     st = torch.cuda.current_stream()
-    target = torch.zeros((720, 1280), dtype=torch.float32, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    g = 2.0 * (target - target) / target.numel()     # loads the loss kernels outside the timing
+
+    def autograd_step():
+        rho = torch.tensor(sc.mat_rho[pm].astype(np.float64), requires_grad=True)
+        Le = torch.tensor(float(sc.mat_Le[light]), dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        ev[0].record(st)
+        img = api.sppm_render_diff(rho, Le, sc, pm, p, K, bvh=bvh)
+        loss = ((img.double() - target) ** 2).mean()
+        ev[1].record(st)
+        ev[2].record(st)
+        loss.backward()
+        ev[3].record(st)
+        torch.cuda.synchronize()
+        return (ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), img.detach(),
+                np.concatenate([rho.grad.cpu().numpy(), [Le.grad.item()]]), float(loss.item()))
+
+    autograd_step()                      # loads every kernel outside the timing
+    f_ms, b_ms, img, grad, loss = autograd_step()
+    # the device work alone, direct calls on one handle
+    s = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=r0, seed=3, record_iterations=K), bvh=bvh)
+    g = (2.0 * (img.double() - target) / img.numel()).float()
     torch.cuda.synchronize()
     ev[0].record(st)
     s.iterate(K)
-    img = s.resolve()
+    img2 = s.resolve()
     ev[1].record(st)
-    g = 2.0 * (img - target) / img.numel()
     ev[2].record(st)
-    grad = s.adjoint(g, sc.albedo_params)
+    direct = s.adjoint(g, pm)
     ev[3].record(st)
     torch.cuda.synchronize()
     t_fwd, t_adj = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
     s.status()
+    same_image = bool(torch.equal(img2, img))
+    same_grad = bool(np.array_equal(direct.cpu().numpy(), grad))
     s.destroy()
+    bvh.destroy()
     return {"fwd_ms": round(t_fwd, 2), "adjoint_ms": round(t_adj, 2),
-            "ratio_fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 3), "iterations": K,
-            "n_params": len(sc.albedo_params) + 1, "grad_finite": bool(torch.isfinite(grad).all().item()),
-            "workload": "procedural 250,094 triangles, 1280x720, 2^20 photons/iteration, L2 loss"}
+            "ratio_fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 3),
+            "autograd": {"forward_ms": round(f_ms, 2), "backward_ms": round(b_ms, 2),
+                         "ratio_fwd_plus_bwd_over_fwd": round((f_ms + b_ms) / f_ms, 3),
+                         "note": "forward includes creating the handle (device buffers, upload)"},
+            "iterations": K, "n_params": len(pm) + 1, "loss": loss,
+            "grad_finite": bool(np.all(np.isfinite(grad))), "autograd_equals_direct_call": same_grad,
+            "forward_image_identical": same_image,
+            "workload": "procedural 250,094 triangles, 1280x720, 2^20 photons/iteration, 16 albedos + Le, "
+                        "L2 loss against a render at albedos perturbed by U[-0.1, 0.1]"}
 
 
 def batch_bench(args, torch, api, scenes):
@@ -431,15 +511,18 @@ def batch_bench(args, torch, api, scenes):
             "setup_s": round(t_setup, 2)}
 
 
-def achievable_bandwidth(torch):
-    """Measured streaming bandwidth of the device: a 1 GiB device-to-device
-    copy (read + write bytes) and a reduction that reads 1 GiB (the traversal's
-    bytes are almost all reads).  Each is the best of 5."""
+def achievable_bandwidth(torch, api):
+    """Measured streaming bandwidth of the device with the library's own stream
+    kernel (pm_probe_stream): a 1 GiB copy (read + write bytes) and a 1 GiB
+    read (the traversal's bytes are almost all reads); best of 5 each.  torch's
+    copy_ of the same buffer is listed for comparison."""
     src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    out = torch.zeros(1, dtype=torch.int32, device="cuda")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def best_ms(fn):
+        fn()
         best = 1e30
         for _ in range(5):
             e0.record()
@@ -449,11 +532,15 @@ def achievable_bandwidth(torch):
             best = min(best, e0.elapsed_time(e1))
         return best
 
-    copy_ms = best_ms(lambda: dst.copy_(src))
-    read_ms = best_ms(lambda: src.sum())
+    copy_ms = best_ms(lambda: api.probe_stream(src, dst))
+    assert torch.equal(dst, src)
+    read_ms = best_ms(lambda: api.probe_stream(src, out=out))
+    torch_copy_ms = best_ms(lambda: dst.copy_(src))
     nb = src.numel() * 4
     del src, dst
-    return {"copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1), "read_GBps": round(nb / (read_ms * 1e-3) / 1e9, 1)}
+    return {"kernel": "pm_probe_stream", "bytes": nb, "copy_GBps": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
+            "read_GBps": round(nb / (read_ms * 1e-3) / 1e9, 1),
+            "torch_copy_GBps": round(2 * nb / (torch_copy_ms * 1e-3) / 1e9, 1)}
 
 
 def dependent_read_rate(torch, api, n_lanes, steps, log2_rows=24):
@@ -515,7 +602,7 @@ def cpu_baseline(tb, scenes):
     sppm["procedural_1280x720_2^20_photons"] = {"s_per_iteration": round(dt_proc, 3),
                                                 "photons_per_s": round((1 << 20) / dt_proc, 1),
                                                 "note": "2 of the configuration's 64 iterations"}
-    return {"value": len(sample) / dt / 1e6, "unit": "Mrays/s", "cores": nth, "kind": "oracle",
+    return {"value": len(sample) / dt / 1e6, "unit": "Mrays/s", "cores": nth, "kind": "oracle", "host": _host_info(),
             "sample": (f"oracle median-split BVH over the same 2^20-triangle soup, 2^18 coherent + 2^18 "
                        f"incoherent rays sampled from the workload (build {t_build:.2f} s not counted); "
                        f"brute force over all triangles: {len(bf) / dt_bf:.1f} rays/s on 512 of them"),
@@ -532,11 +619,11 @@ def main():
     import torch
     from paper_1505_06022_amd import api, scenes
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.copy_probe:
+    if args.copy_probe:   # the library's stream copy of 1 GiB, three times (calibrates HBM byte counters)
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            api.probe_stream(src, dst)
         torch.cuda.synchronize()
         del src, dst
     tb = traversal_bench(args, torch, api, scenes)
@@ -583,7 +670,7 @@ def main():
                      "avg_launch_ms": round(float(tb["kern_ms"].mean()), 4),
                      "alone_ms_by_batch": [round(float(x), 4) for x in tb["batch_ms"]]},
     }
-    ach = achievable_bandwidth(torch)
+    ach = achievable_bandwidth(torch, api)
     best = max(ach["copy_GBps"], ach["read_GBps"])
     out["roofline"]["achievable"] = dict(ach, frac=round(tb["achieved"] / best, 4))
     # the incoherent walk (node visits per second, bucketing included) against chains of dependent random
@@ -601,6 +688,7 @@ def main():
     if not args.no_sppm:
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
+                       "full_render_64_iterations": sp["full_render"],
                        "stored_photons": sp["n_stored"], "workload": sp["workload"],
                        "iteration_ms_by_photon_kernel": sp["variants"],
                        "one_bounce_per_pass_schedule": sp["pass_schedule"],

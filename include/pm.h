@@ -497,6 +497,17 @@ PM_API int pm_render_batch(const pm_scene_desc *const *descs, const pm_sppm_para
 PM_API int pm_probe_chase(const uint32_t *rows, int32_t log2_rows, int64_t n_lanes, int32_t steps, uint32_t *out,
                           void *stream);
 
+/* Memory microbenchmark for the achievable HBM bandwidth of the streaming
+ * stages (the measured ceiling beside the datasheet's 8 TB/s): n_bytes
+ * (a positive multiple of 64) read from src with 16-byte vector loads,
+ * contiguous per wavefront, four loads in flight per thread.  mode 0 copies
+ * them to dst (n_bytes written); mode 1 only reads them and XORs every
+ * 32-bit word into *out (device uint32, caller-owned; the caller clears it).
+ * src and dst are caller-owned device buffers, 16-byte aligned.
+ * Asynchronous on stream; nothing is allocated.
+ * PM_ERR_ARG: bad mode, NULL or misaligned pointers, bad n_bytes. */
+PM_API int pm_probe_stream(const void *src, void *dst, uint64_t n_bytes, int32_t mode, uint32_t *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,7 @@ EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
            "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
            "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch", "pm_probe_chase",
-           "pm_trace_rays_multi", "pm_trace_rays_noalloc"]
+           "pm_trace_rays_multi", "pm_trace_rays_noalloc", "pm_probe_stream"]
 
 
 class PMError(RuntimeError):
@@ -142,6 +142,7 @@ def lib() -> C.CDLL:
         L.pm_batch_get_views.argtypes = [P, I32, P]
         L.pm_render_batch.argtypes = [P, P, I32, I32, P, P, P]
         L.pm_probe_chase.argtypes = [P, I32, I64, I32, P, P]
+        L.pm_probe_stream.argtypes = [P, P, C.c_uint64, I32, P, P]
         L.pm_trace_rays_multi.argtypes = [P, I32, P, P]
         _lib = L
     return _lib
@@ -326,6 +327,17 @@ def trace_rays_multi(bvh: Bvh, batches, stream=None):
     return out
 
 
+def probe_stream(src, dst=None, out=None, stream=None):
+    """Streaming copy of src into dst (dst given) or read of src with the XOR of
+    its words into out (a cuda int32 tensor of one element), pm_probe_stream."""
+    n = src.numel() * src.element_size()
+    if dst is not None:
+        assert dst.numel() * dst.element_size() >= n
+        _check(lib().pm_probe_stream(_ptr(src), _ptr(dst), n, 0, None, _stream(stream)))
+    else:
+        _check(lib().pm_probe_stream(_ptr(src), None, n, 1, _ptr(out), _stream(stream)))
+
+
 def probe_chase(rows, steps: int, n_lanes: int, out=None, stream=None):
     """Dependent random 16-byte reads (memory microbenchmark).  rows: int32 or
     uint32-valued cuda tensor of 2^k x 4 words; returns out (int32 [n_lanes]),
@@ -507,7 +519,7 @@ def _render_function():
         """
 
         @staticmethod
-        def forward(ctx, albedos, Le, scene, param_mats, params, K, stream=None):
+        def forward(ctx, albedos, Le, scene, param_mats, params, K, stream=None, bvh=None):
             sc = scene.with_rho(scene.mat_rho.copy())
             rho = sc.mat_rho
             rho[np.asarray(param_mats, np.int64)] = albedos.detach().cpu().numpy().astype(np.float32)
@@ -518,7 +530,7 @@ def _render_function():
             sc.mat_Le[em[0]] = np.float32(float(Le))
             p = SppmParams.from_buffer_copy(params)
             p.record_iterations = max(int(params.record_iterations), int(K))
-            s = Sppm(sc, p, stream=stream)
+            s = Sppm(sc, p, bvh=bvh, stream=stream)
             s.iterate(K, stream=stream)
             img = s.resolve(stream=stream)
             ctx.s, ctx.param_mats, ctx.stream = s, np.asarray(param_mats, np.int32), stream
@@ -531,13 +543,13 @@ def _render_function():
         def backward(ctx, g):
             need_rho, need_le = ctx.needs_input_grad[0], ctx.needs_input_grad[1] and ctx.le_is_tensor
             if not (need_rho or need_le):
-                return None, None, None, None, None, None, None
+                return None, None, None, None, None, None, None, None
             grad = ctx.s.adjoint(g, ctx.param_mats, stream=ctx.stream)
             n = len(ctx.param_mats)
             g_rho = grad[:n].to(device=ctx.devices[0], dtype=ctx.dtypes[0]) if need_rho else None
             # a plain-number Le is a constant: its gradient position stays None
             g_le = grad[n].to(device=ctx.devices[1], dtype=ctx.dtypes[1]) if need_le else None
-            return g_rho, g_le, None, None, None, None, None
+            return g_rho, g_le, None, None, None, None, None, None
 
     return SPPMRender
 
@@ -545,12 +557,13 @@ def _render_function():
 _SPPMRender = None
 
 
-def sppm_render_diff(albedos, Le, scene, param_mats, params: SppmParams, K: int, stream=None):
-    """Differentiable render (torch.autograd): returns the [H, W] image."""
+def sppm_render_diff(albedos, Le, scene, param_mats, params: SppmParams, K: int, stream=None, bvh: Bvh | None = None):
+    """Differentiable render (torch.autograd): returns the [H, W] image.  bvh:
+    optional BVH already built over the scene's triangles."""
     global _SPPMRender
     if _SPPMRender is None:
         _SPPMRender = _render_function()
-    return _SPPMRender.apply(albedos, Le, scene, param_mats, params, K, stream)
+    return _SPPMRender.apply(albedos, Le, scene, param_mats, params, K, stream, bvh)
 
 
 # ---------------------------------------------------------------------------

@@ -402,3 +402,14 @@ int pm_probe_chase(const uint32_t *rows, int32_t log2_rows, int64_t n_lanes, int
         return pm::launch_chase(rows, log2_rows, (uint32_t)n_lanes, (uint32_t)steps, out, (hipStream_t)stream);
     })
 }
+
+int pm_probe_stream(const void *src, void *dst, uint64_t n_bytes, int32_t mode, uint32_t *out, void *stream) {
+    PM_GUARD({
+        if (mode != 0 && mode != 1) return pm::set_error("mode must be 0 (copy) or 1 (read)"), PM_ERR_ARG;
+        if (!src || (mode == 0 && !dst) || (mode == 1 && !out))
+            return pm::set_error("src, and dst (copy) or out (read), must not be NULL"), PM_ERR_ARG;
+        if (n_bytes == 0 || n_bytes % 64 != 0) return pm::set_error("n_bytes must be a positive multiple of 64"), PM_ERR_ARG;
+        if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return pm::set_error("src and dst must be 16-byte aligned"), PM_ERR_ARG;
+        return pm::launch_stream(src, dst, n_bytes, mode, out, (hipStream_t)stream);
+    })
+}

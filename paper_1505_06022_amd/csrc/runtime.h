@@ -58,6 +58,8 @@ struct Bvh;
 namespace pm {
 
 // Dependent random reads over 2^log2_rows 16-byte rows (memory microbenchmark).
+// Streaming copy (mode 0) or read with an XOR of every word into *out (mode 1).
+int launch_stream(const void *src, void *dst, uint64_t n_bytes, int32_t mode, uint32_t *out, hipStream_t s);
 int launch_chase(const uint32_t *rows, int32_t log2_rows, uint32_t n_lanes, uint32_t steps, uint32_t *out,
                  hipStream_t s);
 

@@ -122,3 +122,45 @@ def test_batched_workload_sample_matches_single(torch_cuda):
     for i, (sc, Np, r0) in enumerate(work):
         ref, _ = _single(torch_cuda, sc, Np, r0, 11 + i, 2)
         assert np.array_equal(imgs[i].cpu().numpy(), ref)
+
+
+def test_full_batched_workload_autotuned_equals_single_and_oracle(torch_cuda, oracle_lib, tmp_path):
+    """The batched workload as the benchmark runs it: all 32 uneven scenes,
+    16 iterations, chunk and block picked by the autotuner, one graph per
+    iteration.  Every scene's image and state equal its own single-handle
+    render bit for bit, and the three scenes with the fewest photons also
+    equal the oracle."""
+    _log("case: batched workload, 32 scenes, K = 16, autotuned")
+    os.environ["PM_AUTOTUNE_CACHE"] = str(tmp_path / "tune.txt")
+    try:
+        work = scenes.batch_workload()
+        assert len(work) == 32
+        K = 16
+        prm = [api.sppm_params(Np, alpha=0.7, r0=r0, seed=100 + i) for i, (_, Np, r0) in enumerate(work)]
+        b = api.Batch([w[0] for w in work], prm, autotune=True)
+        info = b.info()
+        _log(f"  autotuned chunk {info['chunk']} block {info['block']}")
+        b.iterate(K)
+        imgs = [im.cpu().numpy() for im in b.resolve()]
+        b.status()
+        states = [{k: v.cpu().numpy() for k, v in b.views(i).items() if k in ("N", "R2", "tau", "D")}
+                  for i in range(len(work))]
+        b.destroy()
+    finally:
+        del os.environ["PM_AUTOTUNE_CACHE"]
+    for i, (sc, Np, r0) in enumerate(work):
+        s = api.Sppm(sc, prm[i])
+        s.iterate(K)
+        ref = s.resolve().cpu().numpy()
+        s.status()
+        v = s.views()
+        assert np.array_equal(imgs[i], ref), i
+        for k in ("N", "R2", "tau", "D"):
+            assert np.array_equal(states[i][k], v[k].cpu().numpy()), (i, k)
+        s.destroy()
+    _log("  32 scenes equal their single renders; oracle on the three smallest")
+    smallest = sorted(range(len(work)), key=lambda i: (work[i][1], work[i][0].n_tri))[:3]
+    for i in smallest:
+        sc, Np, r0 = work[i]
+        ref = oracle_lib.sppm_run(oracle_lib.OracleScene(sc), 100 + i, Np, K, alpha=0.7, r0=r0).image
+        assert np.array_equal(imgs[i].ravel(), ref), i

@@ -261,3 +261,24 @@ def test_multi_batch_equals_single_calls(torch_cuda):
     assert (ref[0][0] >= 0).any() and (ref[1][0] >= 0).any()
     bvh.destroy()
 
+
+
+def test_probe_stream_copy_and_read(torch_cuda):
+    """pm_probe_stream: the copy reproduces the source exactly; the read mode's
+    XOR of every word equals the host's; bad arguments are refused."""
+    _log("case: stream probe")
+    torch = torch_cuda
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    for n_words in (16, 4096 + 48, (1 << 22) + 16 * 7):
+        src = torch.randint(-2**31, 2**31 - 1, (n_words,), dtype=torch.int32, device="cuda", generator=g)
+        dst = torch.zeros_like(src)
+        api.probe_stream(src, dst)
+        out = torch.zeros(1, dtype=torch.int32, device="cuda")
+        api.probe_stream(src, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+        h = src.cpu().numpy().view(np.uint32)
+        assert int(out.cpu().numpy().view(np.uint32)[0]) == int(np.bitwise_xor.reduce(h))
+    with pytest.raises(api.PMError):
+        api.probe_stream(src[:3], dst)            # 12 bytes: not a multiple of 64
