@@ -109,7 +109,10 @@ def _parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--batch-iters", type=int, default=16)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the comparison of traversal kernels")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the comparisons of traversal kernels and of SPPM schedules")
+    ap.add_argument("--only-sppm", action="store_true",
+                    help="run only the SPPM iteration leg and print it (profiling runs of its kernels)")
     names = [k for k, _ in KERNEL_VARIANTS]
     ap.add_argument("--coherent", default="packet_tiles_block64", choices=names,
                     help="traversal options of the camera batch")
@@ -313,6 +316,76 @@ def traversal_bench(args, torch, api, scenes):
     )
 
 
+def sppm_roofline(api, sc, p_kw, bvh, iters=4):
+    """Per-stage algorithmic-bytes roofline of the SPPM iteration.  One handle
+    counts the work (PM_PROFILE_COUNT: rays, box and triangle tests, stored
+    photons, buckets and photons of the range query), another times the stages
+    with HIP events on the streams they run on (PM_PROFILE_TIME); both run
+    `iters` iterations after two warm-up ones.  Bytes per unit:
+      eye pass + R_max  per eye ray 32 B ray + 8 B result + 16 B per box test
+                        + 48 B per triangle test; per pixel 32 B hit point
+                        written, 16 B of D read and written, 12 B for R_max
+      photon pass       the same per photon ray, + 32 B per stored photon
+      hashed grid       per stored photon: count 16 B read + 4 B atomic + 8 B
+                        (bucket, rank) written; scatter 8 + 32 + 4 B read and
+                        32 B written; per bucket 8 B (scan)
+      range query       per pixel 16 B hit-point normal read + 12 B (M, flux)
+                        written; per hit point 16 B position + 8 B radius; 8 B
+                        per bucket visited; 16 B per photon examined and 16 B
+                        more per photon accepted (a lower bound: a photon inside
+                        the disc that faces away is read but not counted)
+      update            per pixel 8 B (M, hit-point flag); per hit point 32 B
+                        read and 24 B written (an upper bound: hit points with
+                        M = 0 are skipped)"""
+    res = {}
+    for flag in (api.PROFILE_COUNT, api.PROFILE_TIME):
+        h = api.Sppm(sc, api.sppm_params(profile=flag, **p_kw), bvh=bvh)
+        h.iterate(2)
+        h.stats(reset=True)
+        h.iterate(iters)
+        h.status()
+        res[flag] = h.stats()
+        h.destroy()
+    c, t = res[api.PROFILE_COUNT], res[api.PROFILE_TIME]
+    nc, nt = float(c["counted_iterations"]), float(t["timed_iterations"])
+    P = sc.camera.width * sc.camera.height
+    bits = 12
+    while bits < 24 and (1 << bits) < 4 * p_kw["n_photons"]:
+        bits += 1
+    T = 1 << bits
+    q = {k: v / nc for k, v in c.items() if k not in ("counted_iterations", "timed_iterations") and not k.startswith("ms_")}
+
+    def rays(prefix):
+        return 40.0 * q[prefix + "_rays"] + 16.0 * q[prefix + "_box_tests"] + 48.0 * q[prefix + "_tri_tests"]
+
+    stages = {
+        "eye": (rays("eye") + 60.0 * P, t["ms_eye"] / nt),
+        "photon": (rays("photon") + 32.0 * q["photons_stored"], t["ms_photon"] / nt),
+        "grid": (104.0 * q["photons_stored"] + 8.0 * T, t["ms_grid"] / nt),
+        "gather": (28.0 * P + 24.0 * q["gather_hit_points"] + 8.0 * q["gather_buckets"] +
+                   16.0 * q["gather_examined"] + 16.0 * q["gather_accepted"], t["ms_gather"] / nt),
+        "update": (8.0 * P + 56.0 * q["gather_hit_points"], t["ms_update"] / nt),
+    }
+    out = {}
+    for name, (b, ms) in stages.items():
+        gbs = b / (ms * 1e-3) / 1e9
+        out[name] = {"bytes": round(b), "ms": round(ms, 4), "GBps": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    counts = {k: round(v, 1) for k, v in q.items()}
+    per_unit = {"eye_rays_per_pixel": round(q["eye_rays"] / P, 3),
+                "boxes_per_photon_ray": round(q["photon_box_tests"] / q["photon_rays"], 2),
+                "tris_per_photon_ray": round(q["photon_tri_tests"] / q["photon_rays"], 2),
+                "rays_per_photon_path": round(q["photon_rays"] / q["photon_paths"], 3),
+                "stored_per_photon_path": round(q["photons_stored"] / q["photon_paths"], 3),
+                "examined_per_hit_point": round(q["gather_examined"] / q["gather_hit_points"], 1),
+                "accepted_per_hit_point": round(q["gather_accepted"] / q["gather_hit_points"], 1),
+                "buckets_per_hit_point": round(q["gather_buckets"] / q["gather_hit_points"], 2)}
+    return {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s", "stages": out, "counts_per_iteration": counts,
+            "per_unit": per_unit, "iteration_ms_timed": round(t["ms_iteration"] / nt, 4),
+            "note": "stage times with a host wait after each iteration (PM_PROFILE_TIME); the eye pass runs beside "
+                    "the photon pass on a second stream, so its time includes sharing the device"}
+
+
 def sppm_bench(args, torch, api, scenes):
     sc = scenes.procedural_scene()
     v = sc.verts.reshape(-1, 3)
@@ -344,9 +417,18 @@ def sppm_bench(args, torch, api, scenes):
     full.status()
     full.destroy()
     full_ms = e0.elapsed_time(e1)
-    variants, tbvh = {}, {}
+    roof = sppm_roofline(api, sc, dict(n_photons=Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3), bvh)
+    variants, tbvh, schedule, sh = {}, {}, {}, {}
+    if args.no_variants:
+        bvh.destroy()
+        return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
+                    full_render={"iterations": 64, "ms": round(full_ms, 2),
+                                 "photons_per_s": round(64 * Np / (full_ms * 1e-3), 1)},
+                    roofline=roof, tbvh=tbvh, stochastic_hashing=sh, pass_schedule=schedule,
+                    workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
     runs = [("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
             ("regen_refill16", dict(photon_kernel=2, refill=16)), ("regen_refill32", dict(photon_kernel=2, refill=32))]
+    runs += [(f"ray_regen_refill{r}", dict(photon_kernel=4, refill=r)) for r in (4, 8, 16, 24, 32, 48)]
     # the paper's own schedule: one bounce per thread per launch (threads = pixels, then fixed pools)
     P = sc.camera.width * sc.camera.height
     runs += [("passes_threads_per_pixel", dict(photon_kernel=3)),
@@ -354,7 +436,6 @@ def sppm_bench(args, torch, api, scenes):
              ("passes_threads_2^20_passes_24", dict(photon_kernel=3, pass_threads=1 << 20, passes=24))]
     # the paper's TBVH comparison: every ray walks one link set (a single threaded BVH)
     runs += [(f"single_link_set_{k}", dict(single_link_set=k + 1)) for k in range(6)]
-    schedule = {}
     for name, kw in runs:
         sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=0.05 * diag * 64 / 1280, seed=3, **kw), bvh=bvh)
         sv.iterate(1)
@@ -376,7 +457,6 @@ def sppm_bench(args, torch, api, scenes):
     ref.iterate(64)
     ref_img = ref.resolve().double()
     ref.destroy()
-    sh = {}
     for name, mode in (("exact", 0), ("stochastic", 1)):
         sv = api.Sppm(sc, api.sppm_params(Np, alpha=0.7, r0=r0, seed=3, gather_mode=mode), bvh=bvh)
         torch.cuda.synchronize()
@@ -392,7 +472,7 @@ def sppm_bench(args, torch, api, scenes):
     return dict(iteration_ms=it_ms, photons_per_s=Np / (it_ms * 1e-3), n_stored=n_stored, variants=variants,
                 full_render={"iterations": 64, "ms": round(full_ms, 2),
                              "photons_per_s": round(64 * Np / (full_ms * 1e-3), 1)},
-                tbvh=tbvh, stochastic_hashing=sh, pass_schedule=schedule,
+                roofline=roof, tbvh=tbvh, stochastic_hashing=sh, pass_schedule=schedule,
                 workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
 
 
@@ -626,6 +706,13 @@ def main():
             api.probe_stream(src, dst)
         torch.cuda.synchronize()
         del src, dst
+    if args.only_sppm:
+        sp = sppm_bench(args, torch, api, scenes)
+        print(json.dumps({"sppm_only": True, "photons_per_s": round(sp["photons_per_s"], 1),
+                          "iteration_ms": round(sp["iteration_ms"], 3), "stored_photons": sp["n_stored"],
+                          "full_render_64_iterations": sp["full_render"], "roofline": sp["roofline"],
+                          "workload": sp["workload"]}), flush=True)
+        return
     tb = traversal_bench(args, torch, api, scenes)
     out = {
         "metric": "Mrays/s traversal + SPPM photons/s; fwd+adjoint vs fwd time at matched RMSE",
@@ -688,14 +775,15 @@ def main():
     if not args.no_sppm:
         sp = sppm_bench(args, torch, api, scenes)
         out["sppm"] = {"photons_per_s": round(sp["photons_per_s"], 1), "iteration_ms": round(sp["iteration_ms"], 3),
-                       "full_render_64_iterations": sp["full_render"],
+                       "full_render_64_iterations": sp["full_render"], "roofline": sp["roofline"],
                        "stored_photons": sp["n_stored"], "workload": sp["workload"],
                        "iteration_ms_by_photon_kernel": sp["variants"],
                        "one_bounce_per_pass_schedule": sp["pass_schedule"],
                        "gather_exact_vs_stochastic_hashing": sp["stochastic_hashing"],
-                       "tbvh_ablation": {"iteration_ms_single_link_set": sp["tbvh"],
-                                         "mean_ratio_tbvh_over_mtbvh": round(
-                                             float(np.mean(list(sp["tbvh"].values()))) / sp["iteration_ms"], 3)}}
+                       "tbvh_ablation": ({"iteration_ms_single_link_set": sp["tbvh"],
+                                          "mean_ratio_tbvh_over_mtbvh": round(
+                                              float(np.mean(list(sp["tbvh"].values()))) / sp["iteration_ms"], 3)}
+                                         if sp["tbvh"] else None)}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, torch, api, scenes)
     if not args.no_batch:

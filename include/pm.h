@@ -314,7 +314,18 @@ typedef struct {
                                  iteration, 1..1024; 0 = ceil(n_photons /
                                  threads) + 8.  Must be 0 for the other
                                  photon kernels. */
+    int32_t profile;          /* PM_PROFILE_* flags (single-scene handles;
+                                 0 for a batch member); see pm_sppm_get_stats */
 } pm_sppm_params;
+
+/* Profiling of the iterations (pm_sppm_params.profile), read with
+ * pm_sppm_get_stats.  Results are unchanged by either flag.
+ * COUNT: the eye pass, the regenerating photon pass and the exact range query
+ *   run instrumented variants that count their work (slower; needs the
+ *   default photon kernel and gather_mode EXACT).
+ * TIME: HIP events around each stage; every iteration then waits for its end
+ *   on the host, so iterations no longer queue behind each other. */
+enum { PM_PROFILE_COUNT = 1, PM_PROFILE_TIME = 2 };
 
 /* Range query.  EXACT: every photon inside a hit point's disc, found through
  * a hashed grid with cell edge R_max (1 + 2^-5) (2 R_max (1 + 2^-10) when the
@@ -340,8 +351,12 @@ enum { PM_GATHER_EXACT = 0, PM_GATHER_STOCHASTIC = 1 };
  * pass.  Path state stays in device memory between passes (56 B per thread).
  * The passes are enqueued without any host synchronisation, so their number
  * is fixed in advance (`passes`); one last launch finishes whatever paths the
- * passes left (views: photon_count[3] counts them). */
-enum { PM_PHOTON_AUTO = 0, PM_PHOTON_PER_PATH = 1, PM_PHOTON_REGEN = 2, PM_PHOTON_PASSES = 3 };
+ * passes left (views: photon_count[3] counts them).  RAY_REGEN: regeneration
+ * at ray granularity: persistent lanes each walk their own ray, and once
+ * `refill` lanes of a wavefront wait, those lanes shade their hits and start
+ * the next ray of their path (or a new path) while the others keep walking,
+ * so a wavefront does not wait for its longest walk at every bounce. */
+enum { PM_PHOTON_AUTO = 0, PM_PHOTON_PER_PATH = 1, PM_PHOTON_REGEN = 2, PM_PHOTON_PASSES = 3, PM_PHOTON_RAY_REGEN = 4 };
 
 /* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)
  * and allocates the per-pixel state (N = 0, R^2 = r0^2, tau = 0, D = 0).
@@ -391,6 +406,31 @@ PM_API int pm_sppm_load(pm_sppm *s, const void *buf, uint64_t size, void *stream
 
 /* create -> K x iterate -> resolve -> status -> destroy. */
 PM_API int pm_render(const pm_scene_desc *desc, const pm_sppm_params *params, int32_t K, float *image, void *stream);
+
+/* Work counts and stage times of the profiled iterations (sums since the
+ * handle was created or last reset), the per-unit counts of the stages'
+ * algorithmic-bytes rooflines. */
+typedef struct {
+    uint32_t size;                 /* sizeof(pm_sppm_stats) */
+    int64_t counted_iterations;    /* iterations run with PM_PROFILE_COUNT */
+    uint64_t eye_paths, eye_rays, eye_box_tests, eye_tri_tests;
+    uint64_t photon_paths, photon_rays, photon_box_tests, photon_tri_tests, photons_stored;
+    uint64_t gather_hit_points;    /* valid hit points queried */
+    uint64_t gather_buckets;       /* distinct buckets visited */
+    uint64_t gather_examined;      /* photons in those buckets */
+    uint64_t gather_accepted;      /* photons inside a disc from the eye's side (sum of M) */
+    int64_t timed_iterations;      /* iterations run with PM_PROFILE_TIME */
+    double ms_eye;                 /* eye pass + R_max (on the side stream, beside the photon pass) */
+    double ms_photon;              /* photon pass */
+    double ms_grid;                /* hashed grid: count, scan, scatter (after the eye pass joins) */
+    double ms_gather;              /* range query */
+    double ms_update;              /* progressive update */
+    double ms_iteration;           /* whole iteration */
+} pm_sppm_stats;
+
+/* Copies the counts and times into *out (synchronises `stream`); reset != 0
+ * then clears them.  PM_ERR_ARG: NULL pointers, out->size too small. */
+PM_API int pm_sppm_get_stats(pm_sppm *s, pm_sppm_stats *out, int32_t reset, void *stream);
 
 /* Gradient of a scalar image loss by replay (the adjoint of the K iterations
  * run so far; requires params.record_iterations >= K).

@@ -23,7 +23,7 @@ EXPORTS = ["pm_abi_version", "pm_last_error", "pm_build_bvh", "pm_build_bvh_host
            "pm_sppm_iterate", "pm_sppm_resolve", "pm_sppm_status", "pm_render", "pm_sppm_get_views",
            "pm_sppm_adjoint", "pm_sppm_save", "pm_sppm_load", "pm_batch_create", "pm_batch_destroy", "pm_batch_iterate", "pm_batch_resolve",
            "pm_batch_status", "pm_batch_get_info", "pm_batch_get_views", "pm_render_batch", "pm_probe_chase",
-           "pm_trace_rays_multi", "pm_trace_rays_noalloc", "pm_probe_stream"]
+           "pm_trace_rays_multi", "pm_trace_rays_noalloc", "pm_probe_stream", "pm_sppm_get_stats"]
 
 
 class PMError(RuntimeError):
@@ -75,10 +75,23 @@ class SppmParams(C.Structure):
                 ("seed", C.c_uint64), ("max_eye_depth", C.c_int32), ("max_photon_bounces", C.c_int32),
                 ("fixed_shift", C.c_int32), ("store_factor", C.c_int32), ("record_iterations", C.c_int32),
                 ("photon_kernel", C.c_int32), ("refill", C.c_int32), ("single_link_set", C.c_int32),
-                ("gather_mode", C.c_int32), ("pass_threads", C.c_int32), ("passes", C.c_int32)]
+                ("gather_mode", C.c_int32), ("pass_threads", C.c_int32), ("passes", C.c_int32),
+                ("profile", C.c_int32)]
 
 
-PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN, PHOTON_PASSES = 0, 1, 2, 3
+PROFILE_COUNT, PROFILE_TIME = 1, 2
+
+
+class SppmStats(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("counted_iterations", C.c_int64)] + \
+               [(n, C.c_uint64) for n in ("eye_paths", "eye_rays", "eye_box_tests", "eye_tri_tests", "photon_paths",
+                                          "photon_rays", "photon_box_tests", "photon_tri_tests", "photons_stored", "gather_hit_points",
+                                          "gather_buckets", "gather_examined", "gather_accepted")] + \
+               [("timed_iterations", C.c_int64)] + \
+               [(n, C.c_double) for n in ("ms_eye", "ms_photon", "ms_grid", "ms_gather", "ms_update", "ms_iteration")]
+
+
+PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN, PHOTON_PASSES, PHOTON_RAY_REGEN = 0, 1, 2, 3, 4
 GATHER_EXACT, GATHER_STOCHASTIC = 0, 1
 
 
@@ -143,6 +156,7 @@ def lib() -> C.CDLL:
         L.pm_render_batch.argtypes = [P, P, I32, I32, P, P, P]
         L.pm_probe_chase.argtypes = [P, I32, I64, I32, P, P]
         L.pm_probe_stream.argtypes = [P, P, C.c_uint64, I32, P, P]
+        L.pm_sppm_get_stats.argtypes = [P, P, I32, P]
         L.pm_trace_rays_multi.argtypes = [P, I32, P, P]
         _lib = L
     return _lib
@@ -358,7 +372,7 @@ def probe_chase(rows, steps: int, n_lanes: int, out=None, stream=None):
 # ---------------------------------------------------------------------------
 def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, max_photon_bounces=32,
                 fixed_shift=40, store_factor=8, record_iterations=0, photon_kernel=0, refill=0,
-                single_link_set=0, gather_mode=0, pass_threads=0, passes=0) -> SppmParams:
+                single_link_set=0, gather_mode=0, pass_threads=0, passes=0, profile=0) -> SppmParams:
     p = SppmParams()
     p.size = C.sizeof(SppmParams)
     p.n_photons, p.alpha, p.r0, p.seed = n_photons, alpha, float(r0), seed
@@ -369,6 +383,7 @@ def sppm_params(n_photons: int, alpha=0.7, r0=0.05, seed=1, max_eye_depth=16, ma
     p.single_link_set = single_link_set
     p.gather_mode = gather_mode
     p.pass_threads, p.passes = pass_threads, passes
+    p.profile = profile
     return p
 
 
@@ -468,6 +483,13 @@ class Sppm:
         """Continue from a checkpoint taken from a handle with the same scene and parameters."""
         buf = C.create_string_buffer(bytes(checkpoint), len(checkpoint))
         _check(lib().pm_sppm_load(self.h, buf, len(checkpoint), _stream(stream)))
+
+    def stats(self, reset: bool = False, stream=None) -> dict:
+        """Profiling counts and stage times (pm_sppm_get_stats)."""
+        st = SppmStats()
+        st.size = C.sizeof(SppmStats)
+        _check(lib().pm_sppm_get_stats(self.h, C.byref(st), int(reset), _stream(stream)))
+        return {n: getattr(st, n) for n, _ in SppmStats._fields_ if n != "size"}
 
     def adjoint(self, dloss_dimage, param_mats, grad=None, stream=None):
         """dLoss/drho for each material in param_mats, then dLoss/dLe (float64 cuda tensor)."""

@@ -465,6 +465,8 @@ int batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const 
             return set_error("scene " + std::to_string(i) + ": a batch uses the exact gather"), PM_ERR_ARG;
         if (params[i]->photon_kernel == PM_PHOTON_PASSES)
             return set_error("scene " + std::to_string(i) + ": a batch schedules its own photon stage"), PM_ERR_ARG;
+        if (params[i]->profile != 0)
+            return set_error("scene " + std::to_string(i) + ": profiling applies to single-scene handles"), PM_ERR_ARG;
     }
     pm_batch *b = new pm_batch();
     auto fail = [&](int code) {

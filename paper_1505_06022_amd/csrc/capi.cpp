@@ -311,6 +311,10 @@ int pm_sppm_status(pm_sppm *s, void *stream) { PM_GUARD({ return pm::sppm_status
 
 int pm_sppm_get_views(pm_sppm *s, pm_sppm_views *v) { PM_GUARD({ return pm::sppm_views(s, v); }) }
 
+int pm_sppm_get_stats(pm_sppm *s, pm_sppm_stats *out, int32_t reset, void *stream) {
+    PM_GUARD({ return pm::sppm_get_stats(s, out, reset, (hipStream_t)stream); })
+}
+
 int pm_sppm_adjoint(pm_sppm *s, const float *dloss_dimage, const int32_t *param_mats, int32_t n_par, double *grad,
                     void *stream) {
     pm::TraceRange range_("pm_sppm_adjoint");

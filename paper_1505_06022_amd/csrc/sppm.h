@@ -15,6 +15,7 @@ int sppm_status(pm_sppm *s, hipStream_t st);
 int sppm_views(pm_sppm *s, pm_sppm_views *v);
 int sppm_save(pm_sppm *s, void *buf, uint64_t *size, hipStream_t st);
 int sppm_load(pm_sppm *s, const void *buf, uint64_t size, hipStream_t st);
+int sppm_get_stats(pm_sppm *s, pm_sppm_stats *out, int32_t reset, hipStream_t st);
 int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par, double *grad, hipStream_t st);
 
 int batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const *params, int32_t n,

@@ -21,6 +21,16 @@ __global__ __launch_bounds__(kBlock) void k_eye(SppmDev d, uint32_t k, int32_t a
     if (p < d.P) eye_elem(d, k, p, accumulate_D != 0);
 }
 
+// The statistics variants (PM_PROFILE_COUNT): the same work, plus counts of
+// paths, rays, box and triangle tests, and of the range query's buckets and
+// photons, added to d.stats once per wavefront.
+__global__ __launch_bounds__(kBlock) void k_eye_stats(SppmDev d, uint32_t k, int32_t accumulate_D) {
+    int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    LaneStats ls;
+    if (p < d.P) eye_elem<true>(d, k, p, accumulate_D != 0, &ls);
+    wave_stats_flush(d.stats + kStatEyePaths, ls);
+}
+
 template <bool kRecord>
 __global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint16_t *__restrict__ mat_tab,
                                                    long long *__restrict__ adj_tab) {
@@ -30,6 +40,19 @@ __global__ __launch_bounds__(kBlock) void k_photon(SppmDev d, uint32_t k, uint16
 
 // Persistent photon lanes with path regeneration.
 __global__ __launch_bounds__(kBlock) void k_photon_regen(SppmDev d, uint32_t k) { photon_regen_loop(d, k, d.refill); }
+
+__global__ __launch_bounds__(kBlock) void k_photon_regen_stats(SppmDev d, uint32_t k) {
+    photon_regen_loop<false, true>(d, k, d.refill);
+}
+
+// Regeneration at ray granularity (PM_PHOTON_RAY_REGEN).
+__global__ __launch_bounds__(kBlock) void k_photon_stream(SppmDev d, uint32_t k) {
+    photon_stream_loop(d, k, d.refill);
+}
+
+__global__ __launch_bounds__(kBlock) void k_photon_stream_stats(SppmDev d, uint32_t k) {
+    photon_stream_loop<true>(d, k, d.refill);
+}
 
 // The same, recording each path's stored-photon materials for the adjoint.
 __global__ __launch_bounds__(kBlock) void k_photon_regen_rec(SppmDev d, uint32_t k, uint16_t *__restrict__ mat_tab,
@@ -50,6 +73,19 @@ __global__ void k_pass_tally(SppmDev d) {
 
 __global__ __launch_bounds__(kBlock) void k_photon_drain(SppmDev d, uint32_t k, PassSlots ps) {
     photon_drain_elem(d, k, ps, xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x);
+}
+
+// Start of a photon pass: clear its store's photon count and the path counter.
+__global__ void k_photon_begin(SppmDev d) {
+    if (threadIdx.x == 0) {
+        d.counters[0] = 0u;
+        d.counters[2] = 0u;
+    }
+}
+
+// Start of an eye pass: clear the R_max accumulator.
+__global__ void k_rmax_clear(SppmDev d) {
+    if (threadIdx.x == 0) *d.r2max = 0ull;
 }
 
 // Frame setup: clear the photon and path counters and the R_max accumulator.
@@ -105,6 +141,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(SppmDev d, const uint32_t *__
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     Grid gr = make_grid(d);
     gather_wave(d, gr, p, start, sorted);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_stats(SppmDev d, const uint32_t *__restrict__ start,
+                                                         const float4 *__restrict__ sorted) {
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    Grid gr = make_grid(d);
+    gather_wave<true>(d, gr, p, start, sorted);
 }
 
 // Stochastic spatial hashing: clear the keys, insert every stored photon
@@ -407,11 +450,18 @@ void sppm_free(pm_sppm *s) {
     // kernels of this handle may still be in flight on the caller's stream
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
-                    s->hp_nrm, s->store, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
+                    s->hp_nrm, s->store, s->store2, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
                     s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
-                    s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
+                    s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->stats, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    for (hipEvent_t e : s->prof_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (int i = 0; i < 2; ++i) {
+        if (s->ev_ph[i]) (void)hipEventDestroy(s->ev_ph[i]);
+        if (s->ev_scat[i]) (void)hipEventDestroy(s->ev_scat[i]);
+    }
+    if (s->phs) (void)hipStreamDestroy(s->phs);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     if (s->side) (void)hipStreamDestroy(s->side);
@@ -451,8 +501,8 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->store_factor < 1 || p->n_photons * p->store_factor > (int64_t(1) << 30))
         return set_error("store_factor must be >= 1 and the store below 2^30 photons"), PM_ERR_ARG;
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
-    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_PASSES || p->refill < 0 || p->refill > 64)
-        return set_error("photon_kernel must be 0..3 and refill 0..64"), PM_ERR_ARG;
+    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_RAY_REGEN || p->refill < 0 || p->refill > 64)
+        return set_error("photon_kernel must be 0..4 and refill 0..64"), PM_ERR_ARG;
     if (p->pass_threads < 0 || p->pass_threads > (1 << 26) || p->passes < 0 || p->passes > 1024)
         return set_error("pass_threads must be in [0, 2^26] and passes in [0, 1024]"), PM_ERR_ARG;
     if (p->photon_kernel != PM_PHOTON_PASSES && (p->pass_threads != 0 || p->passes != 0))
@@ -461,6 +511,11 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
         return set_error("gather_mode must be PM_GATHER_EXACT or PM_GATHER_STOCHASTIC"), PM_ERR_ARG;
     if (p->gather_mode == PM_GATHER_STOCHASTIC && p->record_iterations > 0)
         return set_error("the adjoint needs the exact gather (gather_mode 0)"), PM_ERR_ARG;
+    if (p->profile < 0 || p->profile > (PM_PROFILE_COUNT | PM_PROFILE_TIME))
+        return set_error("profile must be a combination of PM_PROFILE_COUNT and PM_PROFILE_TIME"), PM_ERR_ARG;
+    if ((p->profile & PM_PROFILE_COUNT) &&
+        (p->gather_mode != PM_GATHER_EXACT || p->photon_kernel == PM_PHOTON_PER_PATH || p->photon_kernel == PM_PHOTON_PASSES))
+        return set_error("PM_PROFILE_COUNT counts the regenerating photon kernels and the exact gather"), PM_ERR_ARG;
     if (p->single_link_set < 0 || p->single_link_set > 6)
         return set_error("single_link_set must be 0 (by direction) or 1..6"), PM_ERR_ARG;
     if (p->record_iterations < 0 || p->record_iterations > 100000)
@@ -542,8 +597,17 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     PM_HIPF(hipMalloc(&s->hp_pos, sizeof(float4) * s->P));
     PM_HIPF(hipMalloc(&s->hp_nrm, sizeof(float4) * s->P));
     PM_HIPF(hipMalloc(&s->store, sizeof(float4) * 2 * (size_t)cap64));
-    PM_HIPF(hipMalloc(&s->counters, sizeof(uint32_t) * 4));
+    PM_HIPF(hipMalloc(&s->counters, sizeof(uint32_t) * 8));
     PM_HIPF(hipMalloc(&s->r2max, sizeof(unsigned long long)));
+    if (own_grid && !(p->profile & PM_PROFILE_TIME)) {
+        // a second photon store and a photon stream: consecutive iterations overlap
+        PM_HIPF(hipMalloc(&s->store2, sizeof(float4) * 2 * (size_t)cap64));
+        PM_HIPF(hipStreamCreateWithFlags(&s->phs, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            PM_HIPF(hipEventCreateWithFlags(&s->ev_ph[i], hipEventDisableTiming));
+            PM_HIPF(hipEventCreateWithFlags(&s->ev_scat[i], hipEventDisableTiming));
+        }
+    }
     if (own_grid) {
         PM_HIPF(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
         PM_HIPF(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
@@ -576,6 +640,12 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         const int64_t auto_pass = (p->n_photons + S - 1) / S + 8;
         s->n_pass = p->passes > 0 ? p->passes : (int32_t)std::min<int64_t>(auto_pass, 1024);
     }
+    if (p->profile & PM_PROFILE_COUNT) {
+        PM_HIPF(hipMalloc(&s->stats, sizeof(unsigned long long) * kStatCount));
+        PM_HIPF(hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * kStatCount, st));
+    }
+    if (p->profile & PM_PROFILE_TIME)
+        for (hipEvent_t &e : s->prof_ev) PM_HIPF(hipEventCreate(&e));
     s->n_mat = nm;
     s->rho_host.assign(d->mat_rho, d->mat_rho + nm);
     s->rec_iters = p->record_iterations;
@@ -613,7 +683,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         PM_HIPF(hipMemcpyAsync(s->emit_pos, epos.data(), sizeof(uint32_t) * epos.size(), hipMemcpyHostToDevice, st));
         PM_HIPF(hipMemcpyAsync(s->emit_cdf, ecdf.data(), sizeof(double) * ecdf.size(), hipMemcpyHostToDevice, st));
     }
-    PM_HIPF(hipMemsetAsync(s->counters, 0, sizeof(uint32_t) * 4, st));
+    PM_HIPF(hipMemsetAsync(s->counters, 0, sizeof(uint32_t) * 8, st));
     PM_HIPF(hipMemsetAsync(s->hp_nrm, 0xff, sizeof(float4) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->M, 0, sizeof(uint32_t) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->Phi, 0, sizeof(unsigned long long) * s->P, st));
@@ -660,9 +730,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.P = s->P;
     dv.mask = T - 1u;
     dv.table_off = 0;
-    dv.photon_kernel = (p->photon_kernel == PM_PHOTON_PER_PATH || p->photon_kernel == PM_PHOTON_PASSES)
-                           ? p->photon_kernel
-                           : PM_PHOTON_REGEN;
+    dv.photon_kernel = p->photon_kernel == PM_PHOTON_AUTO ? PM_PHOTON_REGEN : p->photon_kernel;
     dv.refill = p->refill > 0 ? (uint32_t)p->refill : 32u;
     dv.force_set = p->single_link_set - 1;
     // Paired node requests pay off on one large scene (2.65 -> 2.55 ms per
@@ -680,6 +748,8 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         s->regen_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
         PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_regen_rec, kBlock, 0));
         s->regen_grid_rec = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_stream, kBlock, 0));
+        s->stream_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
     }
     dv.hp_pos = s->hp_pos;
     dv.hp_nrm = s->hp_nrm;
@@ -693,6 +763,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.r2max = s->r2max;
     dv.M = s->M;
     dv.Phi = s->Phi;
+    dv.stats = s->stats;
     hipLaunchKernelGGL(k_init_state, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dv, p->r0 * p->r0);
     PM_HIPF(hipGetLastError());
     // host staging vectors go out of scope: finish the copies first
@@ -719,58 +790,193 @@ int sppm_reset(pm_sppm *s, hipStream_t st) {
     return PM_OK;
 }
 
+// Device view of iteration k: a pipelined handle alternates two photon stores
+// (each with its block of four counters) between consecutive iterations.
+static SppmDev iteration_view(const pm_sppm *s, uint32_t k) {
+    SppmDev dk = s->dev;
+    const uint32_t par = s->store2 ? (k & 1u) : 0u;
+    dk.store = par ? s->store2 : s->store;
+    dk.counters = s->counters + 4 * par;
+    return dk;
+}
+
+// The photon pass of iteration k (its counters cleared first) on stream q.
+static int enqueue_photon(pm_sppm *s, const SppmDev &dk, uint32_t k, bool count, hipStream_t q) {
+    const uint32_t np = (uint32_t)s->prm.n_photons;
+    hipLaunchKernelGGL(k_photon_begin, dim3(1), dim3(64), 0, q, dk);
+    if (dk.photon_kernel == PM_PHOTON_RAY_REGEN) {
+        if (count)
+            hipLaunchKernelGGL(k_photon_stream_stats, dim3(s->stream_grid), dim3(kBlock), 0, q, dk, k);
+        else
+            hipLaunchKernelGGL(k_photon_stream, dim3(s->stream_grid), dim3(kBlock), 0, q, dk, k);
+    } else if (dk.photon_kernel == PM_PHOTON_REGEN) {
+        if (count)
+            hipLaunchKernelGGL(k_photon_regen_stats, dim3(s->regen_grid), dim3(kBlock), 0, q, dk, k);
+        else
+            hipLaunchKernelGGL(k_photon_regen, dim3(s->regen_grid), dim3(kBlock), 0, q, dk, k);
+    } else if (dk.photon_kernel == PM_PHOTON_PASSES) {
+        const PassSlots &ps = s->slots;
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)ps.S)), dim3(kBlock), 0, q, (uint32_t *)ps.nb,
+                           2u * ps.S, kSlotIdle);
+        for (int32_t j = 0; j < s->n_pass; ++j)
+            hipLaunchKernelGGL(k_photon_pass, dim3(blocks_for(ps.S)), dim3(kBlock), 0, q, dk, k, ps);
+        hipLaunchKernelGGL(k_pass_tally, dim3(1), dim3(64), 0, q, dk);
+        hipLaunchKernelGGL(k_photon_drain, dim3(blocks_for(ps.S)), dim3(kBlock), 0, q, dk, k, ps);
+    } else {
+        hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, q, dk, k, (uint16_t *)nullptr,
+                           (long long *)nullptr);
+    }
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
+// One call runs n_iter iterations.  Per iteration k: the eye pass and R_max
+// on the side stream, the photon pass, then on the caller's stream the hashed
+// grid, the range query and the update.  A pipelined handle (two photon
+// stores) runs its photon passes on a third stream, one after another: the
+// pass of iteration k + 1 needs nothing of iteration k except a free store,
+// so it overlaps iteration k's grid, range query and update and keeps the
+// device full while the photon pass drains.  Events order the rest: the
+// photon pass of k + 1 waits for the scatter of k - 1 (the last reader of its
+// store), the eye pass of k for the update of k - 1 (it overwrites the hit
+// points and R_max that k - 1 read), and the grid of k for the eye pass and
+// photon pass of k.  At the end of the call the caller's stream has waited
+// for every stream.  Results are those of the serial order.
 int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
     if (!s || n_iter < 0) return set_error("invalid handle or iteration count"), PM_ERR_ARG;
     if (!s->cell_count) return set_error("handle belongs to a batch: iterate the batch"), PM_ERR_STATE;
+    if (n_iter == 0) return PM_OK;
     const uint32_t T = 1u << s->table_bits;
-    const uint32_t np = (uint32_t)s->prm.n_photons;
     const uint32_t ph_blocks = std::min<uint32_t>(blocks_for(s->cap), 256u * 64u);
+    const bool count = (s->prm.profile & PM_PROFILE_COUNT) != 0, timed = (s->prm.profile & PM_PROFILE_TIME) != 0;
+    const bool pipe = s->store2 != nullptr;
+    hipEvent_t *ev = s->prof_ev;
+    const uint32_t k0 = (uint32_t)s->K;
+    int rc;
+    if (pipe) {
+        PM_HIP(hipEventRecord(s->ev_fork, st));
+        PM_HIP(hipStreamWaitEvent(s->phs, s->ev_fork, 0));
+        if ((rc = enqueue_photon(s, iteration_view(s, k0), k0, count, s->phs))) return rc;
+        PM_HIP(hipEventRecord(s->ev_ph[k0 & 1u], s->phs));
+    }
     for (int32_t it = 0; it < n_iter; ++it) {
-        uint32_t k = (uint32_t)s->K;
-        const SppmDev &d = s->dev;
-        hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, d);
-        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
-        // eye pass and R_max on the side stream, photon pass on the caller's:
-        // they share no data, and the eye pass's long specular paths would
+        const uint32_t k = k0 + (uint32_t)it;
+        const SppmDev dk = iteration_view(s, k);
+        if (pipe && it + 1 < n_iter) {
+            // the next photon pass refills the store that the scatter of k - 1 read
+            if (it >= 1) PM_HIP(hipStreamWaitEvent(s->phs, s->ev_scat[(k + 1u) & 1u], 0));
+            if ((rc = enqueue_photon(s, iteration_view(s, k + 1u), k + 1u, count, s->phs))) return rc;
+            PM_HIP(hipEventRecord(s->ev_ph[(k + 1u) & 1u], s->phs));
+        }
+        if (timed) PM_HIP(hipEventRecord(ev[0], st));
+        // eye pass and R_max on the side stream, beside the photon pass: they
+        // share no data, and the eye pass's long specular paths would
         // otherwise leave the device idle at its end
         PM_HIP(hipEventRecord(s->ev_fork, st));
         PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
-        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, k, 1);
-        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d,
+        if (timed) PM_HIP(hipEventRecord(ev[1], s->side));
+        hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, s->side, dk);
+        if (count)
+            hipLaunchKernelGGL(k_eye_stats, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 1);
+        else
+            hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 1);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, dk,
                            (const double *)s->R2);
+        if (timed) PM_HIP(hipEventRecord(ev[2], s->side));
         PM_HIP(hipEventRecord(s->ev_join, s->side));
-        if (d.photon_kernel == PM_PHOTON_REGEN) {
-            hipLaunchKernelGGL(k_photon_regen, dim3(s->regen_grid), dim3(kBlock), 0, st, d, k);
-        } else if (d.photon_kernel == PM_PHOTON_PASSES) {
-            const PassSlots &ps = s->slots;
-            hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(2 * (int64_t)ps.S)), dim3(kBlock), 0, st,
-                               (uint32_t *)ps.nb, 2u * ps.S, kSlotIdle);
-            for (int32_t j = 0; j < s->n_pass; ++j)
-                hipLaunchKernelGGL(k_photon_pass, dim3(blocks_for(ps.S)), dim3(kBlock), 0, st, d, k, ps);
-            hipLaunchKernelGGL(k_pass_tally, dim3(1), dim3(64), 0, st, d);
-            hipLaunchKernelGGL(k_photon_drain, dim3(blocks_for(ps.S)), dim3(kBlock), 0, st, d, k, ps);
-        } else
-            hipLaunchKernelGGL(k_photon<false>, dim3(blocks_for(np)), dim3(kBlock), 0, st, d, k, (uint16_t *)nullptr,
-                               (long long *)nullptr);
+        if (!pipe) {
+            if (timed) PM_HIP(hipEventRecord(ev[3], st));
+            if ((rc = enqueue_photon(s, dk, k, count, st))) return rc;
+            if (timed) PM_HIP(hipEventRecord(ev[4], st));
+        }
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
-        if (d.gather_mode == PM_GATHER_STOCHASTIC) {
-            hipLaunchKernelGGL(k_sh_clear, dim3(std::min<uint32_t>(blocks_for(T), 4096u)), dim3(kBlock), 0, st, d, T);
-            hipLaunchKernelGGL(k_sh_insert, dim3(ph_blocks), dim3(kBlock), 0, st, d, k, s->cell_count);
-            hipLaunchKernelGGL(k_sh_pick, dim3(ph_blocks), dim3(kBlock), 0, st, d, k);
-            hipLaunchKernelGGL(k_sh_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d,
+        if (pipe) PM_HIP(hipStreamWaitEvent(st, s->ev_ph[k & 1u], 0));
+        if (timed) PM_HIP(hipEventRecord(ev[5], st));
+        if (dk.gather_mode == PM_GATHER_STOCHASTIC) {
+            hipLaunchKernelGGL(k_sh_clear, dim3(std::min<uint32_t>(blocks_for(T), 4096u)), dim3(kBlock), 0, st, dk, T);
+            hipLaunchKernelGGL(k_sh_insert, dim3(ph_blocks), dim3(kBlock), 0, st, dk, k, s->cell_count);
+            hipLaunchKernelGGL(k_sh_pick, dim3(ph_blocks), dim3(kBlock), 0, st, dk, k);
+            if (pipe) PM_HIP(hipEventRecord(s->ev_scat[k & 1u], st));
+            if (timed) PM_HIP(hipEventRecord(ev[6], st));
+            hipLaunchKernelGGL(k_sh_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk,
                                (const uint32_t *)s->cell_count);
         } else {
-            hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, d, s->cell_count);
+            hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, dk, s->cell_count);
             launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
-            hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, d, (const uint32_t *)s->cell_start,
+            hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, dk, (const uint32_t *)s->cell_start,
                                s->sorted);
-            hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d,
-                               (const uint32_t *)s->cell_start, (const float4 *)s->sorted);
+            if (pipe) PM_HIP(hipEventRecord(s->ev_scat[k & 1u], st));
+            if (timed) PM_HIP(hipEventRecord(ev[6], st));
+            if (count)
+                hipLaunchKernelGGL(k_gather_stats, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk,
+                                   (const uint32_t *)s->cell_start, (const float4 *)s->sorted);
+            else
+                hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk,
+                                   (const uint32_t *)s->cell_start, (const float4 *)s->sorted);
         }
+        if (timed) PM_HIP(hipEventRecord(ev[7], st));
         double *hist = (int32_t)k < s->rec_iters ? s->R2_hist + (size_t)k * s->P : nullptr;
-        hipLaunchKernelGGL(k_update, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, d, hist);
+        hipLaunchKernelGGL(k_update, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk, hist);
         PM_HIP(hipGetLastError());
+        if (timed) {  // wait for the iteration and add its stage times
+            PM_HIP(hipEventRecord(ev[8], st));
+            PM_HIP(hipEventSynchronize(ev[8]));
+            float ms[kProfTimes];
+            PM_HIP(hipEventElapsedTime(&ms[0], ev[1], ev[2]));  // eye pass + R_max (side stream)
+            PM_HIP(hipEventElapsedTime(&ms[1], ev[3], ev[4]));  // photon pass
+            PM_HIP(hipEventElapsedTime(&ms[2], ev[5], ev[6]));  // hashed grid
+            PM_HIP(hipEventElapsedTime(&ms[3], ev[6], ev[7]));  // range query
+            PM_HIP(hipEventElapsedTime(&ms[4], ev[7], ev[8]));  // update
+            PM_HIP(hipEventElapsedTime(&ms[5], ev[0], ev[8]));  // whole iteration
+            for (int i = 0; i < kProfTimes; ++i) s->prof_ms[i] += ms[i];
+            s->prof_timed_iters++;
+        }
+        if (count) s->prof_counted_iters++;
         s->K++;
+    }
+    return PM_OK;
+}
+
+int sppm_get_stats(pm_sppm *s, pm_sppm_stats *out, int32_t reset, hipStream_t st) {
+    if (!s || !out) return set_error("NULL handle or output"), PM_ERR_ARG;
+    if (out->size < sizeof(pm_sppm_stats)) return set_error("pm_sppm_stats.size too small"), PM_ERR_ARG;
+    unsigned long long c[kStatCount] = {};
+    if (s->stats) {
+        PM_HIP(hipMemcpyAsync(c, s->stats, sizeof(c), hipMemcpyDeviceToHost, st));
+        PM_HIP(hipStreamSynchronize(st));
+    }
+    const uint32_t size = out->size;
+    memset(out, 0, sizeof(pm_sppm_stats));
+    out->size = size;
+    out->counted_iterations = s->prof_counted_iters;
+    out->eye_paths = c[kStatEyePaths];
+    out->eye_rays = c[kStatEyeRays];
+    out->eye_box_tests = c[kStatEyeBoxes];
+    out->eye_tri_tests = c[kStatEyeTris];
+    out->photon_paths = c[kStatPhotonPaths];
+    out->photon_rays = c[kStatPhotonRays];
+    out->photon_box_tests = c[kStatPhotonBoxes];
+    out->photon_tri_tests = c[kStatPhotonTris];
+    out->gather_hit_points = c[kStatGatherHits];
+    out->gather_buckets = c[kStatGatherBuckets];
+    out->gather_examined = c[kStatGatherExamined];
+    out->gather_accepted = c[kStatGatherAccepted];
+    out->photons_stored = c[kStatPhotonStored];
+    out->timed_iterations = s->prof_timed_iters;
+    out->ms_eye = s->prof_ms[0];
+    out->ms_photon = s->prof_ms[1];
+    out->ms_grid = s->prof_ms[2];
+    out->ms_gather = s->prof_ms[3];
+    out->ms_update = s->prof_ms[4];
+    out->ms_iteration = s->prof_ms[5];
+    if (reset) {
+        if (s->stats) {
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kBlock), 0, st, (uint32_t *)s->stats, 2u * kStatCount, 0u);
+            PM_HIP(hipGetLastError());
+        }
+        s->prof_counted_iters = s->prof_timed_iters = 0;
+        for (double &m : s->prof_ms) m = 0.0;
     }
     return PM_OK;
 }
@@ -785,11 +991,12 @@ int sppm_resolve(pm_sppm *s, float *image, hipStream_t st) {
 
 int sppm_status(pm_sppm *s, hipStream_t st) {
     if (!s) return set_error("NULL handle"), PM_ERR_ARG;
-    uint32_t c[4];
+    uint32_t c[8];
     PM_HIP(hipMemcpyAsync(c, s->counters, sizeof(c), hipMemcpyDeviceToHost, st));
     PM_HIP(hipStreamSynchronize(st));
-    if (c[1] & 1u) return set_error("photon store overflow: raise store_factor"), PM_ERR_OVERFLOW;
-    if (c[1] & 2u)
+    const uint32_t flags = c[1] | c[5];  // the sticky flags of both photon stores' counter blocks
+    if (flags & 1u) return set_error("photon store overflow: raise store_factor"), PM_ERR_OVERFLOW;
+    if (flags & 2u)
         return set_error("flux fixed-point overflow (a term or a pixel's sum passed 2^64): lower fixed_shift"),
                PM_ERR_OVERFLOW;
     return PM_OK;
@@ -927,8 +1134,9 @@ int sppm_save(pm_sppm *s, void *buf, uint64_t *size, hipStream_t st) {
         *size = need;
         return set_error("checkpoint buffer too small (the required size is returned in *size)"), PM_ERR_ARG;
     }
-    uint32_t c[4];
+    uint32_t c[8];
     PM_HIP(hipMemcpyAsync(c, s->counters, sizeof(c), hipMemcpyDeviceToHost, st));
+    c[1] |= c[5];
     CheckpointHeader h{};
     memcpy(h.magic, "PMSPPMCK", 8);
     h.version = kCheckpointVersion;
@@ -1002,8 +1210,10 @@ int sppm_views(pm_sppm *s, pm_sppm_views *v) {
     v->D = s->D;
     v->hp_pos = (float *)s->hp_pos;
     v->hp_nrm = (float *)s->hp_nrm;
-    v->photons = (float *)s->store;
-    v->photon_count = s->counters;
+    // the last iteration's photon store and counters (a pipelined handle alternates two)
+    const uint32_t par = (s->store2 && s->K > 0) ? (uint32_t)((s->K - 1) & 1) : 0u;
+    v->photons = (float *)(par ? s->store2 : s->store);
+    v->photon_count = s->counters + 4 * par;
     v->gather_M = s->M;
     v->gather_Phi = (uint64_t *)s->Phi;
     return PM_OK;

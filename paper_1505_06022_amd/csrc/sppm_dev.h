@@ -56,7 +56,35 @@ struct SppmDev {
     unsigned long long *r2max;
     uint32_t *M;
     unsigned long long *Phi;
+    unsigned long long *stats;  // [kStatCount] profiling counts (PM_PROFILE_COUNT), else unused
 };
+
+// Profiling counts (accumulated by the kStats variants of the kernels).
+enum {
+    kStatEyePaths = 0, kStatEyeRays, kStatEyeBoxes, kStatEyeTris,
+    kStatPhotonPaths, kStatPhotonRays, kStatPhotonBoxes, kStatPhotonTris,
+    kStatGatherHits, kStatGatherBuckets, kStatGatherExamined, kStatGatherAccepted,
+    kStatPhotonStored,
+    kStatCount = 16
+};
+
+// Per-lane counts of a traced path (or of all paths a persistent lane traced).
+struct LaneStats {
+    uint64_t paths = 0, rays = 0, boxes = 0, tris = 0, stored = 0;
+};
+
+// Adds v summed over the wavefront to *dst; every lane of the wave must call it.
+__device__ __forceinline__ void wave_stat_add(unsigned long long *dst, uint64_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, (unsigned long long)v);
+}
+
+__device__ __forceinline__ void wave_stats_flush(unsigned long long *dst, const LaneStats &ls) {
+    wave_stat_add(dst + 0, ls.paths);
+    wave_stat_add(dst + 1, ls.rays);
+    wave_stat_add(dst + 2, ls.boxes);
+    wave_stat_add(dst + 3, ls.tris);
+}
 
 // Link set of a ray: by its direction (MTBVH), or one set for every ray.
 __device__ __forceinline__ int ray_set(const SppmDev &d, V3 dir) {
@@ -68,7 +96,9 @@ __device__ __forceinline__ int ray_set(const SppmDev &d, V3 dir) {
 // first diffuse (rho > 0) surface, which becomes the pixel's hit point;
 // directly seen emission is accumulated into D (skipped when replaying).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p, bool accumulate_D) {
+template <bool kStats = false>
+__device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p, bool accumulate_D,
+                                        LaneStats *ls = nullptr) {
     const SceneDev &sc = d.sc;
     int32_t px = (int32_t)(p % sc.W), py = (int32_t)(p / sc.W);
     Rng g = rng_seed(d.seed, kKindEye, k, (uint64_t)p);
@@ -85,12 +115,13 @@ __device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p
     double dadd = 0.0;
     float4 pos = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float4 nrm = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(-1));
-    TraceStats st;
+    TraceStats st{0u, 0u};
     for (int depth = 0; depth < d.max_depth; ++depth) {
         float t;
         uint32_t kp;
-        int32_t h = closest_hit<false>(sc.bvh, ray_set(d, dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st,
-                                       d.paired_walk != 0);
+        int32_t h = closest_hit<kStats>(sc.bvh, ray_set(d, dir), org, dir, tmin, __builtin_inff(), excl, t, kp, st,
+                                        d.paired_walk != 0);
+        if (kStats) ls->rays++;
         if (h < 0) break;
         V3 x = vray(org, t, dir);
         Tri tr = load_tri(sc.bvh.tris, kp);
@@ -120,6 +151,11 @@ __device__ __forceinline__ void eye_elem(const SppmDev &d, uint32_t k, int64_t p
     d.hp_pos[p] = pos;
     d.hp_nrm[p] = nrm;
     if (accumulate_D) d.D[p] += dadd;
+    if (kStats) {
+        ls->paths++;
+        ls->boxes += st.boxes;
+        ls->tris += st.tris;
+    }
 }
 
 // Wave-aggregated append: one atomic per wavefront for all lanes currently
@@ -187,17 +223,39 @@ __device__ __forceinline__ bool photon_emit(const SppmDev &d, uint32_t k, uint32
 // a stored photon (kMatNone: none at that bounce), and the matching entries of
 // adj_tab are cleared for the adjoint gather; photon_finish marks the end
 // (kMatEnd).  Material ids are below kMaxAdjMat, so neither marker is a material.
-template <bool kRecord>
+template <bool kRecord, bool kStats>
+__device__ __forceinline__ bool photon_shade(const SppmDev &d, PhotonPath &P, int32_t h, float t, uint32_t kp,
+                                             uint16_t *__restrict__ mat_tab, long long *__restrict__ adj_tab,
+                                             LaneStats *ls);
+
+template <bool kRecord, bool kStats = false>
 __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, uint16_t *__restrict__ mat_tab,
-                                              long long *__restrict__ adj_tab) {
+                                              long long *__restrict__ adj_tab, LaneStats *ls = nullptr) {
+    const SceneDev &sc = d.sc;
+    float t;
+    uint32_t kp;
+    TraceStats st{0u, 0u};
+    int32_t h = closest_hit<kStats>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp,
+                                    st, d.paired_walk != 0);
+    if (kStats) {
+        ls->rays++;
+        ls->boxes += st.boxes;
+        ls->tris += st.tris;
+    }
+    return photon_shade<kRecord, kStats>(d, P, h, t, kp, mat_tab, adj_tab, ls);
+}
+
+// The rest of a bounce once the closest hit (h, t, kp) of the ray from P.org
+// along P.dir is known: store a photon at a diffuse hit, Russian roulette and
+// a new cosine direction, or a specular direction; returns true while the
+// path continues.
+template <bool kRecord, bool kStats>
+__device__ __forceinline__ bool photon_shade(const SppmDev &d, PhotonPath &P, int32_t h, float t, uint32_t kp,
+                                             uint16_t *__restrict__ mat_tab, long long *__restrict__ adj_tab,
+                                             LaneStats *ls) {
     const SceneDev &sc = d.sc;
     const int32_t mb = d.max_bounces;
     const int b = P.b;
-    float t;
-    uint32_t kp;
-    TraceStats st;
-    int32_t h = closest_hit<false>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp, st,
-                                   d.paired_walk != 0);
     if (h < 0) return false;
     V3 x = vray(P.org, t, P.dir);
     Tri tr = load_tri(sc.bvh.tris, kp);
@@ -216,6 +274,7 @@ __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, u
             row[b] = (uint16_t)m;
             adj_tab[(size_t)P.n * mb + b] = 0;
         }
+        if (kStats) ls->stored++;
         uint32_t slot = wave_append(&d.counters[0]);
         if (slot < d.cap) {
             d.store[2 * (size_t)slot] = make_float4(x.x, x.y, x.z, P.phi);
@@ -264,11 +323,12 @@ __device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32
 // Called by every lane of a wave; the wave's lanes must share one scene.
 // kRecord (adjoint replay): paths also write their rows of mat_tab / adj_tab
 // as in photon_elem.
-template <bool kRecord = false>
+template <bool kRecord = false, bool kStats = false>
 __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, uint32_t refill,
                                                   uint16_t *__restrict__ mat_tab = nullptr,
                                                   long long *__restrict__ adj_tab = nullptr) {
     PhotonPath P;
+    LaneStats ls;
     bool live = false, exhausted = false;
     for (;;) {
         bool idle = !live && !exhausted;
@@ -279,6 +339,7 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
             if (idle) {
                 if (n < d.n_paths) {
                     live = photon_emit(d, k, n, P);
+                    if (kStats) ls.paths++;
                     if (kRecord && !live) photon_finish<true>(d, P, mat_tab);
                 } else {
                     exhausted = true;
@@ -288,9 +349,90 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
         }
         if (live_mask == 0ull && __ballot(!exhausted) == 0ull) break;
         if (live) {
-            live = photon_bounce<kRecord>(d, P, mat_tab, adj_tab);
+            live = photon_bounce<kRecord, kStats>(d, P, mat_tab, adj_tab, &ls);
             if (kRecord && !live) photon_finish<true>(d, P, mat_tab);
         }
+    }
+    if (kStats) {
+        wave_stats_flush(d.stats + kStatPhotonPaths, ls);
+        wave_stat_add(d.stats + kStatPhotonStored, ls.stored);
+    }
+}
+
+// Photon paths with regeneration at ray granularity: each lane walks its own
+// ray; once at least `refill` lanes of the wave wait (their ray has ended, or
+// they have no path and paths remain), those lanes shade their hits and start
+// the next ray of their path, or take a new path from the counter
+// d.counters[2], while the other lanes keep walking.  A wave therefore does
+// not wait for its longest walk at every bounce.  Every path consumes its
+// random stream exactly as in photon_elem, so the photons are the same.
+// Each round of walk steps advances every walking lane and each shading round
+// serves every waiting lane, so every wave exits once the counter passes
+// n_paths.  Called by every lane of a wave.
+constexpr int kStreamVoteSteps = 4;  // walk steps between two votes of the wave
+
+template <bool kStats = false>
+__device__ __forceinline__ void photon_stream_loop(const SppmDev &d, uint32_t k, uint32_t refill) {
+    const SceneDev &sc = d.sc;
+    PhotonPath P;
+    Walker w;
+    TraceStats st{0u, 0u};
+    LaneStats ls;
+    bool live = false, walking = false, exhausted = false;
+    const bool paired = d.paired_walk != 0;
+    for (;;) {
+        if (live && !walking) {  // this lane's ray has ended: the rest of its bounce
+            if (kStats) ls.rays++;
+            // the walker holds the ray (P's copies need not stay live during the walk)
+            P.org = w.o;
+            P.dir = w.d;
+            P.excl = w.exclude;
+            live = photon_shade<false, kStats>(d, P, w.best, w.t_hit(), w.best_k, nullptr, nullptr, &ls);
+            if (live) {
+                w.init(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl);
+                walking = true;
+            }
+        }
+        const bool idle = !live && !exhausted;
+        const uint64_t idle_mask = __ballot(idle);
+        if (idle_mask != 0ull) {
+            const uint32_t n = wave_fetch_add(&d.counters[2], idle_mask, idle);
+            if (idle) {
+                if (n < d.n_paths) {
+                    live = photon_emit(d, k, n, P);
+                    if (kStats) ls.paths++;
+                    if (live) {
+                        w.init(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl);
+                        walking = true;
+                    }
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        if (__ballot(live) == 0ull && __ballot(!exhausted) == 0ull) break;
+        for (;;) {
+            const uint64_t walk_mask = __ballot(walking);
+            if (walk_mask == 0ull) break;
+            // waiting lanes: a finished ray to shade, or no path while paths remain
+            if ((uint32_t)__popcll(__ballot(!walking && (live || !exhausted))) >= refill) break;
+#pragma unroll
+            for (int u = 0; u < kStreamVoteSteps; ++u) {
+                if (walking) {
+                    if (paired)
+                        w.step2<kStats>(sc.bvh.tris, st);
+                    else
+                        w.step<kStats>(sc.bvh.tris, st);
+                    walking = !w.done();
+                }
+            }
+        }
+    }
+    if (kStats) {
+        ls.boxes = st.boxes;
+        ls.tris = st.tris;
+        wave_stats_flush(d.stats + kStatPhotonPaths, ls);
+        wave_stat_add(d.stats + kStatPhotonStored, ls.stored);
     }
 }
 
@@ -678,6 +820,7 @@ __device__ __forceinline__ float readlane_f(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+template <bool kStats = false>
 __device__ __forceinline__ void gather_wave(const SppmDev &d, const Grid &gr, int64_t p,
                                             const uint32_t *__restrict__ start, const float4 *__restrict__ sorted) {
     const bool in = p < d.P;
@@ -760,6 +903,12 @@ __device__ __forceinline__ void gather_wave(const SppmDev &d, const Grid &gr, in
         if (bad) atomicOr(&d.counters[1], 2u);
         d.M[p] = M;
         d.Phi[p] = F;
+    }
+    if (kStats) {  // hit points, distinct buckets visited, photons in them, photons accepted
+        wave_stat_add(d.stats + kStatGatherHits, valid ? 1u : 0u);
+        wave_stat_add(d.stats + kStatGatherBuckets, valid ? (uint64_t)__popc(dc.uniq) : 0u);
+        wave_stat_add(d.stats + kStatGatherExamined, load);
+        wave_stat_add(d.stats + kStatGatherAccepted, M);
     }
 }
 

@@ -19,6 +19,7 @@ struct pm_sppm {
     uint32_t table_bits = 0;
     uint32_t regen_grid = 1;      // workgroups of the regenerating photon kernel
     uint32_t regen_grid_rec = 1;  // and of its recording variant (adjoint replay)
+    uint32_t stream_grid = 1;     // workgroups of the ray-granularity regenerating photon kernel
     float phi0 = 0.0f;
     // device buffers
     int32_t *mat_type = nullptr;
@@ -28,8 +29,13 @@ struct pm_sppm {
     double *N = nullptr, *R2 = nullptr, *tau = nullptr, *D = nullptr;
     float4 *hp_pos = nullptr, *hp_nrm = nullptr;
     float4 *store = nullptr, *sorted = nullptr;
+    // pipelined handles: a second photon store, the stream the photon passes
+    // run on, and events per store (photon pass done, scatter done)
+    float4 *store2 = nullptr;
+    hipStream_t phs = nullptr;
+    hipEvent_t ev_ph[2] = {}, ev_scat[2] = {};
     uint2 *key_rank = nullptr;  // exact gather: [cap] bucket and rank of each stored photon
-    uint32_t *counters = nullptr;  // [0] photons stored, [1] overflow flag
+    uint32_t *counters = nullptr;  // [8]: per photon store [0] photons stored, [1] sticky flags, [2] next path, [3] pass leftovers
     unsigned long long *r2max = nullptr;
     // bucket arrays (absent for a batch member, which uses the batch's)
     uint32_t *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *bsum = nullptr;
@@ -60,7 +66,14 @@ struct pm_sppm {
     void *slot_mem = nullptr;
     pmd::PassSlots slots{};
     int32_t n_pass = 0;
+    // profiling (params.profile): device counts, and stage times of each timed iteration
+    unsigned long long *stats = nullptr;  // [pmd::kStatCount]
+    hipEvent_t prof_ev[9] = {};
+    double prof_ms[6] = {};
+    int64_t prof_counted_iters = 0, prof_timed_iters = 0;
 };
+
+constexpr int kProfTimes = 6;
 
 namespace pm {
 

@@ -68,10 +68,16 @@ def test_host_validation_errors_without_gpu():
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
     assert b"alpha" in L.pm_last_error()
     # the one-bounce-per-pass photon schedule and its two knobs
-    for bad in (dict(photon_kernel=4), dict(photon_kernel=-1)):
+    for bad in (dict(photon_kernel=5), dict(photon_kernel=-1)):
         p = api.sppm_params(1024, **bad)
         assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
         assert b"photon_kernel" in L.pm_last_error()
+    # profiling flags, and counting only where instrumented kernels exist
+    for bad in (dict(profile=4), dict(profile=-1), dict(profile=api.PROFILE_COUNT, gather_mode=1),
+                dict(profile=api.PROFILE_COUNT, photon_kernel=api.PHOTON_PER_PATH)):
+        p = api.sppm_params(1024, **bad)
+        assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
+        assert b"PROFILE" in L.pm_last_error() or b"profile" in L.pm_last_error()
     for bad in (dict(photon_kernel=api.PHOTON_PASSES, pass_threads=-1),
                 dict(photon_kernel=api.PHOTON_PASSES, pass_threads=(1 << 26) + 1),
                 dict(photon_kernel=api.PHOTON_PASSES, passes=1025),

@@ -119,9 +119,10 @@ def test_specular_scene_parity(torch_cuda, oracle_lib):
     _run_parity(torch_cuda, oracle_lib, sc, 1 << 15, 3, 0.05 * diag * 64 / 97, seed=3)
 
 
-@pytest.mark.parametrize("photon_kernel,refill", [(1, 0), (2, 1), (2, 8), (2, 64)])
+@pytest.mark.parametrize("photon_kernel,refill", [(1, 0), (2, 1), (2, 8), (2, 64), (4, 0), (4, 1), (4, 16), (4, 64)])
 def test_photon_kernels_parity(torch_cuda, oracle_lib, photon_kernel, refill):
-    """One path per lane and regenerating lanes give the same photons and images."""
+    """One path per lane, lanes regenerating paths, and lanes regenerating rays
+    give the same photons and images."""
     _log(f"case: photon kernel {photon_kernel} refill {refill}")
     sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
     _run_parity(torch_cuda, oracle_lib, sc, 3 * (1 << 12) + 5, 2, 0.02, seed=8, stage_iters=2,
@@ -230,7 +231,7 @@ def test_determinism_across_schedules(torch_cuda):
     sc = scenes.procedural_scene(width=61, height=37, hf_cells=12, sphere_level=2, glass_level=2, seed=8)
     out = []
     for kw in (dict(), dict(), dict(photon_kernel=1), dict(photon_kernel=2, refill=1), dict(photon_kernel=3),
-               dict(photon_kernel=3, pass_threads=333, passes=2)):
+               dict(photon_kernel=3, pass_threads=333, passes=2), dict(photon_kernel=4), dict(photon_kernel=4, refill=5)):
         s = api.Sppm(sc, api.sppm_params(1 << 13, r0=0.03, seed=21, **kw))
         s.iterate(3)
         img = s.resolve().cpu().numpy()
@@ -446,3 +447,57 @@ def test_stochastic_hashing_is_refused_where_unsupported(torch_cuda):
     with pytest.raises(api.PMError) as e:
         api.Batch([sc, sc], [api.sppm_params(256, r0=0.1), api.sppm_params(256, r0=0.1, photon_kernel=3)])
     assert e.value.code == api.PM_ERR_ARG
+
+
+def test_profile_counts_and_times(torch_cuda, oracle_lib):
+    """PM_PROFILE_COUNT and PM_PROFILE_TIME leave results unchanged; the
+    counts of paths, stored photons, hit points and accepted photons equal
+    the oracle's, and the other counts and the stage times are consistent."""
+    _log("case: profiling counts and stage times")
+    sc = scenes.procedural_scene(width=97, height=61, hf_cells=20, sphere_level=2, glass_level=3, seed=3)
+    Np, K, r0, seed = 1 << 14, 3, 0.02, 5
+    out = {}
+    for prof, pk in ((0, 0), (api.PROFILE_COUNT, 0), (api.PROFILE_TIME, 0), (api.PROFILE_COUNT | api.PROFILE_TIME, 0),
+                     (api.PROFILE_COUNT | 8, 4)):
+        s = api.Sppm(sc, api.sppm_params(Np, r0=r0, seed=seed, profile=prof & 3, photon_kernel=pk))
+        s.iterate(K)
+        img = s.resolve().cpu().numpy()
+        s.status()
+        out[prof] = (img, {k: v.cpu().numpy() for k, v in s.views().items() if k in ("N", "R2", "tau", "D")},
+                     s.stats())
+        s.destroy()
+    for prof in out:
+        assert np.array_equal(out[prof][0], out[0][0])
+        for k in ("N", "R2", "tau", "D"):
+            assert np.array_equal(out[prof][1][k], out[0][1][k])
+    st = out[api.PROFILE_COUNT | api.PROFILE_TIME][2]
+    osc = oracle_lib.OracleScene(sc)
+    P = osc.P
+    R2 = np.full(P, r0 * r0)
+    N, tau = np.zeros(P), np.zeros(P)
+    stored = hits = accepted = 0
+    for k in range(K):
+        hp = oracle_lib.eye_pass(osc, seed, k)
+        ph = oracle_lib.photon_pass(osc, seed, k, Np)
+        M, Phi = oracle_lib.gather(hp, ph, R2)
+        stored += ph.n
+        hits += int((hp.valid > 0).sum())
+        accepted += int(M.astype(np.int64).sum())
+        oracle_lib.update(hp.valid, M, Phi, 0.7, N, R2, tau)
+    assert st["counted_iterations"] == K and st["timed_iterations"] == K
+    assert st["eye_paths"] == K * P and st["photon_paths"] == K * Np
+    assert st["photons_stored"] == stored and st["gather_hit_points"] == hits and st["gather_accepted"] == accepted
+    assert st["eye_rays"] >= st["eye_paths"] and st["photon_rays"] >= stored
+    assert st["eye_box_tests"] >= st["eye_rays"] and st["photon_box_tests"] >= st["photon_rays"]
+    assert st["gather_examined"] >= accepted and st["gather_buckets"] >= hits
+    for k in ("ms_eye", "ms_photon", "ms_grid", "ms_gather", "ms_update"):
+        assert 0 < st[k] < st["ms_iteration"], k
+    assert out[api.PROFILE_TIME][2]["eye_paths"] == 0      # counting was off there
+    # the ray-granularity kernel walks the same rays and stores the same photons
+    st4 = out[api.PROFILE_COUNT | 8][2]
+    for k in ("photon_paths", "photon_rays", "photons_stored", "photon_box_tests", "photon_tri_tests"):
+        assert st4[k] == out[api.PROFILE_COUNT][2][k], k
+    with pytest.raises(api.PMError):
+        api.Sppm(sc, api.sppm_params(Np, r0=r0, gather_mode=1, profile=api.PROFILE_COUNT))
+    with pytest.raises(api.PMError):
+        api.Batch([sc, sc], [api.sppm_params(256, r0=0.1, profile=api.PROFILE_TIME)] * 2)
