@@ -97,6 +97,27 @@ def measured_traffic():
     return 1024.0 * (rec["fetch_factor"] * sum(rec["fetch_kib"]) + rec["write_factor"] * sum(rec["write_kib"]))
 
 
+def measured_sppm_traffic():
+    """L2-to-memory bytes per SPPM stage (read + written, per iteration) from the
+    committed counter record, or None when the SPPM sources changed since the
+    counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "sppm_pmc_procedural250k.md")) as fh:
+            line = next(ln for ln in fh if ln.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if rec["sources_sha256_16"] != h.hexdigest()[:16]:
+        return None
+    return {st: 1024.0 * (rec["fetch_factor"] * rec["fetch_kib"][st] + rec["write_factor"] * rec["write_kib"][st])
+            for st in rec["fetch_kib"]}
+
+
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,11 +387,13 @@ def sppm_roofline(api, sc, p_kw, bvh, iters=4):
                    16.0 * q["gather_examined"] + 16.0 * q["gather_accepted"], t["ms_gather"] / nt),
         "update": (8.0 * P + 56.0 * q["gather_hit_points"], t["ms_update"] / nt),
     }
+    traffic = measured_sppm_traffic()
     out = {}
     for name, (b, ms) in stages.items():
         gbs = b / (ms * 1e-3) / 1e9
         out[name] = {"bytes": round(b), "ms": round(ms, 4), "GBps": round(gbs, 1),
-                     "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": round(traffic[name]) if traffic else None}
     counts = {k: round(v, 1) for k, v in q.items()}
     per_unit = {"eye_rays_per_pixel": round(q["eye_rays"] / P, 3),
                 "boxes_per_photon_ray": round(q["photon_box_tests"] / q["photon_rays"], 2),
