@@ -122,8 +122,9 @@ PM_API int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t
  *          link word: an inner node stores its skip link (preorder index after
  *          its subtree, n_nodes at the end; its hit link is i + 1); a leaf has
  *          bit 31 set and first_tri << 3 | count (both of its links are i + 1)
- *   tris   host, [n_tri][12] 32-bit words in leaf order: v0.xyz, e1.xyz,
- *          e2.xyz (float bits), original index, material, 0. */
+ *   tris   host, [n_tri][12] 32-bit words in leaf order: v0.xyz, v1.xyz,
+ *          v2.xyz (float bits, the vertices as given), original index,
+ *          material, 0. */
 PM_API int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
                       int64_t *n_nodes, uint32_t *nodes, uint32_t *tris, pm_bvh_info *info);
 

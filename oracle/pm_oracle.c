@@ -220,22 +220,58 @@ static inline v3 along(v3 o, float t, v3 d) { return mk(o.x + t * d.x, o.y + t *
 /* ------------------------------------------------------------------------ */
 /* Triangles and the closest-hit definition.                                  */
 /* ------------------------------------------------------------------------ */
-typedef struct { v3 v0, e1, e2; } tri_t;
+typedef struct { v3 v0, v1, v2, e1, e2; } tri_t;   /* e1 = v1 - v0, e2 = v2 - v0 */
 
-/* Moller-Trumbore (two-sided), fixed operation order.  Returns 1 and t on a
- * hit of the supporting triangle. */
-static inline int mt_hit(v3 o, v3 d, const tri_t *tr, float *t_out) {
-    v3 p = cross(d, tr->e2);
-    float det = dot(tr->e1, p);
+/* The ray/triangle test (the paper leaves it open; Sec. 3.1): the watertight
+ * test of Woop, Benthin and Wald (JCGT 2013), two-sided.  Seen along the ray,
+ * after a shear that maps d onto its major axis kz, the ray is the point
+ * (0, 0) of the plane; it hits the triangle when that point lies inside the
+ * sheared triangle, i.e. the three edge functions (doubled signed areas of
+ * the point with each edge) do not differ in sign.  The hit's t is the
+ * depth of the point with those edge functions as barycentric weights.  The
+ * edge functions use Kahan's 2x2 determinant so that their signs are exact
+ * for the rounded, sheared vertices; all steps are float32 in a fixed order. */
+typedef struct { int kx, ky, kz; float sx, sy, sz; } shear_t;
+
+static shear_t ray_shear(v3 d) {
+    float ad[3] = {fabsf(d.x), fabsf(d.y), fabsf(d.z)}, dv[3] = {d.x, d.y, d.z};
+    shear_t h;
+    h.kz = (ad[0] >= ad[1] && ad[0] >= ad[2]) ? 0 : (ad[1] >= ad[2] ? 1 : 2);
+    h.kx = (h.kz + 1) % 3;
+    h.ky = (h.kz + 2) % 3;
+    h.sx = dv[h.kx] / dv[h.kz];
+    h.sy = dv[h.ky] / dv[h.kz];
+    h.sz = 1.0f / dv[h.kz];
+    return h;
+}
+
+/* a b - c d, Kahan: c d rounded, its rounding error recovered exactly by a
+ * fused multiply-add; relative error at most 2^-23. */
+static inline float kahan_det(float a, float b, float c, float d) {
+    float w = c * d;
+    float e = fmaf(-c, d, w);
+    float f = fmaf(a, b, -w);
+    return f + e;
+}
+
+static inline int wt_hit(v3 o, const shear_t *h, const tri_t *tr, float *t_out) {
+    const v3 *vs[3] = {&tr->v0, &tr->v1, &tr->v2};
+    float x[3], y[3], z[3];
+    for (int i = 0; i < 3; ++i) {
+        v3 a = sub(*vs[i], o);
+        float c[3] = {a.x, a.y, a.z};
+        x[i] = fmaf(-h->sx, c[h->kz], c[h->kx]);
+        y[i] = fmaf(-h->sy, c[h->kz], c[h->ky]);
+        z[i] = c[h->kz];
+    }
+    float U = kahan_det(x[2], y[1], y[2], x[1]);   /* edge v1 v2 */
+    float V = kahan_det(x[0], y[2], y[0], x[2]);   /* edge v2 v0 */
+    float W = kahan_det(x[1], y[0], y[1], x[0]);   /* edge v0 v1 */
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return 0;
+    float det = (U + V) + W;
     if (det == 0.0f) return 0;
-    float inv = 1.0f / det;
-    v3 s = sub(o, tr->v0);
-    float u = dot(s, p) * inv;
-    if (u < 0.0f || u > 1.0f) return 0;
-    v3 q = cross(s, tr->e1);
-    float v = dot(d, q) * inv;
-    if (v < 0.0f || u + v > 1.0f) return 0;
-    *t_out = dot(tr->e2, q) * inv;
+    float T = fmaf(W, h->sz * z[2], fmaf(V, h->sz * z[1], U * (h->sz * z[0])));
+    *t_out = T / det;
     return 1;
 }
 
@@ -253,6 +289,8 @@ static tri_t *make_tris(const float *verts, int64_t n) {
         const float *v = verts + 9 * i;
         v3 a = mk(v[0], v[1], v[2]), b = mk(v[3], v[4], v[5]), c = mk(v[6], v[7], v[8]);
         T[i].v0 = a;
+        T[i].v1 = b;
+        T[i].v2 = c;
         T[i].e1 = sub(b, a);
         T[i].e2 = sub(c, a);
     }
@@ -383,7 +421,10 @@ static void obvh_free(obvh *b) {
     free(b);
 }
 
-/* Slab test in double against the padded box, inclusive at both ends. */
+/* Slab test in double against the padded box, inclusive at both ends, with
+ * the far end widened by 2^-16 of itself: an accepted triangle hit's point
+ * o + t d may lie outside the triangle's box by a few 2^-24 of t |d_a| per
+ * axis (its rounding), and the padding covers only absolute amounts. */
 static inline int obox_hit(const obvh_node *nd, const double o[3], const double d[3], double tmin, double tmax) {
     double t0 = tmin, t1 = tmax;
     for (int a = 0; a < 3; ++a) {
@@ -396,19 +437,19 @@ static inline int obox_hit(const obvh_node *nd, const double o[3], const double 
         if (ta > tb) { double t = ta; ta = tb; tb = t; }
         if (ta > t0) t0 = ta;
         if (tb < t1) t1 = tb;
-        if (t0 > t1) return 0;
     }
-    return 1;
+    return t0 <= t1 + fabs(t1) * 0x1p-16;
 }
 
 /* Closest hit in (tmin, tmax), ties to the lower index; excluded index skipped. */
 static int32_t closest_bf(const tri_t *T, int64_t n, v3 o, v3 d, float tmin, float tmax, int32_t exclude, float *t_out) {
     int32_t best = -1;
     float tb = tmax;
+    const shear_t h = ray_shear(d);
     for (int64_t i = 0; i < n; ++i) {
         if ((int32_t)i == exclude) continue;
         float t;
-        if (mt_hit(o, d, &T[i], &t) && better(t, (int32_t)i, tmin, tb, best)) {
+        if (wt_hit(o, &h, &T[i], &t) && better(t, (int32_t)i, tmin, tb, best)) {
             tb = t;
             best = (int32_t)i;
         }
@@ -420,6 +461,7 @@ static int32_t closest_bf(const tri_t *T, int64_t n, v3 o, v3 d, float tmin, flo
 static int32_t closest_bvh(const obvh *b, const tri_t *T, v3 o, v3 d, float tmin, float tmax, int32_t exclude, float *t_out) {
     int32_t best = -1;
     float tb = tmax;
+    const shear_t h = ray_shear(d);
     double od[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
     int32_t stack[256];
     int sp = 0;
@@ -432,7 +474,7 @@ static int32_t closest_bvh(const obvh *b, const tri_t *T, v3 o, v3 d, float tmin
                 int32_t i = b->idx[k];
                 if (i == exclude) continue;
                 float t;
-                if (mt_hit(o, d, &T[i], &t) && better(t, i, tmin, tb, best)) {
+                if (wt_hit(o, &h, &T[i], &t) && better(t, i, tmin, tb, best)) {
                     tb = t;
                     best = i;
                 }

@@ -241,7 +241,10 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     for (int64_t i = nn - 1; i >= 0; --i)
         if (tree[i].left >= 0) size[i] = 1 + size[tree[i].left] + size[tree[i].right];
 
-    // box padding keeps the slab test conservative for accepted triangle hits
+    // box padding: it covers the absolute parts of the error bounds that keep
+    // the slab test conservative (2u ext for the plane distances, 22u L for
+    // the point of an accepted triangle hit, L <= sqrt(3) ext; u = 2^-24)
+    // more than ten times over; the relative parts are the slab test's slack
     float ext = 0.0f;
     for (int a = 0; a < 3; ++a) ext = std::max(ext, scene.hi[a] - scene.lo[a]);
     float mag = 0.0f;
@@ -338,8 +341,8 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
         uint32_t *w = out.tris.data() + (size_t)k * kTriWords;
         for (int a = 0; a < 3; ++a) {
             w[a] = fbits(v[a]);
-            w[3 + a] = fbits(v[3 + a] - v[a]);
-            w[6 + a] = fbits(v[6 + a] - v[a]);
+            w[3 + a] = fbits(v[3 + a]);
+            w[6 + a] = fbits(v[6 + a]);
         }
         w[9] = (uint32_t)t;
         w[10] = mats ? mats[t] : 0u;

@@ -321,18 +321,17 @@ __global__ __launch_bounds__(kLb) void k_lb_thread(int n, int max_leaf, const in
     if (leaf) atomicAdd(&stats->leaves, 1ull);
 }
 
-// Triangle records in leaf (sorted) order: v0, e1 = v1 - v0, e2 = v2 - v0,
-// original index, material.
+// Triangle records in leaf (sorted) order: v0, v1, v2, original index,
+// material.
 __global__ __launch_bounds__(kLb) void k_lb_tris(const float *__restrict__ verts, const uint32_t *__restrict__ mats,
                                                  const uint32_t *__restrict__ order, int n, float4 *__restrict__ tris) {
     const int k = (int)(blockIdx.x * kLb + threadIdx.x);
     if (k >= n) return;
     const uint32_t t = order[k];
     const float *p = verts + 9 * (size_t)t;
-    tris[3 * (size_t)k] = make_float4(p[0], p[1], p[2], p[3] - p[0]);
-    tris[3 * (size_t)k + 1] = make_float4(p[4] - p[1], p[5] - p[2], p[6] - p[0], p[7] - p[1]);
-    tris[3 * (size_t)k + 2] =
-        make_float4(p[8] - p[2], __uint_as_float(t), __uint_as_float(mats ? mats[t] : 0u), 0.0f);
+    tris[3 * (size_t)k] = make_float4(p[0], p[1], p[2], p[3]);
+    tris[3 * (size_t)k + 1] = make_float4(p[4], p[5], p[6], p[7]);
+    tris[3 * (size_t)k + 2] = make_float4(p[8], __uint_as_float(t), __uint_as_float(mats ? mats[t] : 0u), 0.0f);
 }
 
 struct Scratch {

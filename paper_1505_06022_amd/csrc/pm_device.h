@@ -121,40 +121,102 @@ __device__ __forceinline__ V3 vray(V3 o, float t, V3 d) { return v3(o.x + t * d.
 // Scene layout on the device
 // ---------------------------------------------------------------------------
 struct Tri {
-    V3 v0, e1, e2;
+    V3 v0, v1, v2;
     int32_t id;
     uint32_t mat;
 };
 
-// 48-byte triangle record: v0.xyz e1.x | e1.yz e2.xy | e2.z id mat 0
+// 48-byte triangle record: v0.xyz v1.x | v1.yz v2.xy | v2.z id mat 0
 __device__ __forceinline__ Tri load_tri(const float4 *__restrict__ tris, uint32_t k) {
     const float4 *p = tris + 3 * (size_t)k;
     float4 a = p[0], b = p[1], c = p[2];
     Tri t;
     t.v0 = v3(a.x, a.y, a.z);
-    t.e1 = v3(a.w, b.x, b.y);
-    t.e2 = v3(b.z, b.w, c.x);
+    t.v1 = v3(a.w, b.x, b.y);
+    t.v2 = v3(b.z, b.w, c.x);
     t.id = __float_as_int(c.y);
     t.mat = __float_as_uint(c.z);
     return t;
 }
 
-__device__ __forceinline__ V3 tri_normal(const Tri &t) { return vnorm(vcross(t.e1, t.e2)); }
+// Edge vectors v1 - v0 and v2 - v0 (for the normal and for points on the
+// triangle), rounded once per component.
+__device__ __forceinline__ V3 tri_e1(const Tri &t) { return vsub(t.v1, t.v0); }
+__device__ __forceinline__ V3 tri_e2(const Tri &t) { return vsub(t.v2, t.v0); }
+__device__ __forceinline__ V3 tri_normal(const Tri &t) { return vnorm(vcross(tri_e1(t), tri_e2(t))); }
 
-// Moller-Trumbore, two-sided, fixed operation order; returns t or a NaN-free
-// "no hit" flag.
-__device__ __forceinline__ bool mt_hit(V3 o, V3 d, const Tri &tr, float &t_out) {
-    V3 p = vcross(d, tr.e2);
-    float det = vdot(tr.e1, p);
+// Per-ray constants of the watertight triangle test: kz = the major axis of d
+// (ties x, y, z, as for the link set), kx = kz + 1 and ky = kz + 2 (mod 3),
+// and the shear that maps d onto the kz axis: sx = d_kx / d_kz,
+// sy = d_ky / d_kz, sz = 1 / d_kz.
+struct Shear {
+    float sx, sy, sz;
+    uint32_t kz;
+};
+
+__device__ __forceinline__ Shear ray_shear(V3 d) {
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    Shear h;
+    h.kz = (ax >= ay && ax >= az) ? 0u : (ay >= az ? 1u : 2u);
+    const float dz = h.kz == 0u ? d.x : (h.kz == 1u ? d.y : d.z);
+    const float dx = h.kz == 0u ? d.y : (h.kz == 1u ? d.z : d.x);
+    const float dy = h.kz == 0u ? d.z : (h.kz == 1u ? d.x : d.y);
+    h.sx = dx / dz;
+    h.sy = dy / dz;
+    h.sz = 1.0f / dz;
+    return h;
+}
+
+// a b - c d with a relative error of at most 2u (u = 2^-24; Kahan's 2x2
+// determinant with one fused multiply-add for the rounding error of c d), so
+// its sign is the exact value's sign.
+__device__ __forceinline__ float det2(float a, float b, float c, float d) {
+    const float w = c * d;
+    const float e = fmaf(-c, d, w);
+    const float f = fmaf(a, b, -w);
+    return f + e;
+}
+
+// Vertex v seen from the ray: (x, y) its position in the plane sheared along
+// d (the ray passes through (0, 0)) and z its distance along the kz axis.
+__device__ __forceinline__ void shear_vertex(V3 v, V3 o, const Shear &h, float &x, float &y, float &z) {
+    const V3 a = vsub(v, o);
+    const float az = h.kz == 0u ? a.x : (h.kz == 1u ? a.y : a.z);
+    const float ax = h.kz == 0u ? a.y : (h.kz == 1u ? a.z : a.x);
+    const float ay = h.kz == 0u ? a.z : (h.kz == 1u ? a.x : a.y);
+    x = fmaf(-h.sx, az, ax);
+    y = fmaf(-h.sy, az, ay);
+    z = az;
+}
+
+// Watertight ray/triangle test (two-sided; Woop, Benthin and Wald 2013, with
+// the edge functions taken by det2).  The edge functions U, V, W are the
+// doubled signed areas that the ray's point spans with each edge of the
+// sheared triangle; their signs are exact for the sheared vertices, so the
+// ray hits when all three agree, and an edge shared by two triangles has
+// the same vertices and the opposite sign in both (no ray slips between
+// them).  t = (U z0 + V z1 + W z2) / (U + V + W) (z scaled by sz), the
+// depth of the point with those barycentric weights.
+//
+// Error bound (used by the traversal's box test): the point o + t d lies
+// within 22u (t |d_a| + L) of a point of the triangle along every axis a
+// (L its longest edge): the weights are the exact non-negative barycentric
+// coordinates of the ray in the sheared, rounded vertices (relative error of
+// U, V, W at most 2u), each sheared coordinate is within 3u (|t d_a| + L) of
+// the exact one, and t within 16u (|t| + L / |d_kz|).
+__device__ __forceinline__ bool wt_hit(V3 o, const Shear &h, const Tri &tr, float &t_out) {
+    float ax, ay, az, bx, by, bz, cx, cy, cz;
+    shear_vertex(tr.v0, o, h, ax, ay, az);
+    shear_vertex(tr.v1, o, h, bx, by, bz);
+    shear_vertex(tr.v2, o, h, cx, cy, cz);
+    const float U = det2(cx, by, cy, bx);
+    const float V = det2(ax, cy, ay, cx);
+    const float W = det2(bx, ay, by, ax);
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = (U + V) + W;
     if (det == 0.0f) return false;
-    float inv = 1.0f / det;
-    V3 s = vsub(o, tr.v0);
-    float u = vdot(s, p) * inv;
-    if (u < 0.0f || u > 1.0f) return false;
-    V3 q = vcross(s, tr.e1);
-    float v = vdot(d, q) * inv;
-    if (v < 0.0f || u + v > 1.0f) return false;
-    t_out = vdot(tr.e2, q) * inv;
+    const float T = fmaf(W, h.sz * cz, fmaf(V, h.sz * bz, U * (h.sz * az)));
+    t_out = T / det;
     return true;
 }
 
@@ -188,14 +250,15 @@ struct TraceStats {
 // Stackless closest-hit traversal of one link set (Sec. 3.1, Fig. "mtbvh"):
 // follow the hit link (next node) when the ray meets the node's box, else the
 // miss (skip) link; at a leaf test its triangles and continue with the miss
-// link.  The box test is conservative (boxes are padded at build time and the
-// interval is closed at tbest) so the result equals the brute-force closest
-// hit.  Walker holds one lane's traversal state so that a persistent kernel
+// link.  The box test is conservative (padded boxes, a relative slack on the
+// exit distance; the bound is at box_hit) so the result equals the
+// brute-force closest hit.  Walker holds one lane's traversal state so that a persistent kernel
 // can interleave node steps of different rays.
 struct Walker {
     const uint4 *nodes;
     uint32_t n, i;
     V3 o, d;
+    Shear sh;                      // the triangle test's shear
     float sx, sy, sz, bx, by, bz;  // slab planes: t = q * s + b per axis
     uint32_t rx, ry, rz;           // 16 where the axis is walked backwards (near plane = hi), else 0
     float tmin, tbest;
@@ -209,6 +272,7 @@ struct Walker {
         i = 0;
         o = o_;
         d = d_;
+        sh = ray_shear(d_);
         // reciprocal direction; zero components replaced by a tiny signed value
         float dx = fabsf(d.x) > 1e-30f ? d.x : copysignf(1e-30f, d.x);
         float dy = fabsf(d.y) > 1e-30f ? d.y : copysignf(1e-30f, d.y);
@@ -254,6 +318,18 @@ struct Walker {
     // towards -axis puts that axis's entry plane in the low half, so the
     // entry and exit distances need no min/max per axis (the values equal
     // min/max of the two plane distances).
+    //
+    // Conservative: a plane distance fma(q, s, b), with s and b rounded once
+    // each, is within 4u |t| + 2u ext / |d_a| of the exact one (u = 2^-24,
+    // ext the scene extent, for any ray origin).  An accepted triangle hit at
+    // t puts o + t d within 22u (|t d_a| + L) of a point of the triangle along
+    // each axis (see wt_hit), so inside the triangle's box grown by that
+    // much.  The absolute parts (2u ext, 22u L) are covered many times over by
+    // the padding of every box (at least 2^-15 ext), and the relative parts,
+    // at most 52u |t| in all, by the slack kBoxSlack = 256u on the exit
+    // distance: every box that holds a triangle with an accepted hit at a t
+    // in (tmin, tbest] passes, so the walk finds the brute-force closest hit.
+    static constexpr float kBoxSlack = 0x1p-16f;
     __device__ __forceinline__ bool box_hit(const uint4 &q) const {
         const uint32_t ax = __builtin_rotateright32(q.x, rx), ay = __builtin_rotateright32(q.y, ry),
                        az = __builtin_rotateright32(q.z, rz);
@@ -262,7 +338,7 @@ struct Walker {
         const float nz = fmaf((float)(az & 0xffffu), sz, bz), fz = fmaf((float)(az >> 16), sz, bz);
         const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, tmin));
         const float tf = fminf(fminf(fx, fy), fminf(fz, tbest));
-        return tn <= tf;
+        return tn <= fmaf(fabsf(tf), kBoxSlack, tf);
     }
 
     template <bool kStats>
@@ -273,7 +349,7 @@ struct Walker {
             if (kStats) st.tris++;
             if (tr.id == exclude) continue;
             float t;
-            if (mt_hit(o, d, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
+            if (wt_hit(o, sh, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
                 tbest = t;
                 best = tr.id;
                 best_k = first + k;

@@ -210,8 +210,9 @@ __device__ __forceinline__ bool photon_emit(const SppmDev &d, uint32_t k, uint32
         u1 = 1.0f - u1;
         u2 = 1.0f - u2;
     }
-    P.org = v3((et.v0.x + u1 * et.e1.x) + u2 * et.e2.x, (et.v0.y + u1 * et.e1.y) + u2 * et.e2.y,
-               (et.v0.z + u1 * et.e1.z) + u2 * et.e2.z);
+    const V3 e1 = tri_e1(et), e2 = tri_e2(et);
+    P.org = v3((et.v0.x + u1 * e1.x) + u2 * e2.x, (et.v0.y + u1 * e1.y) + u2 * e2.y,
+               (et.v0.z + u1 * e1.z) + u2 * e2.z);
     P.dir = cosine_dir(tri_normal(et), P.g);
     P.phi = d.phi0;
     P.excl = et.id;

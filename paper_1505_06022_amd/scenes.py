@@ -442,6 +442,68 @@ def random_rays(n: int, seed=2, lo=0.0, hi=1.0) -> np.ndarray:
     return out
 
 
+def grazing_rays(verts, n: int, angles, seed=7, dist=(0.05, 1.0), on_edges=False) -> np.ndarray:
+    """Rays aimed at points of random triangles of `verts`, each arriving at
+    one of `angles` (radians) to the triangle's plane from a distance drawn
+    uniformly in dist x the scene's diagonal.  The aim points are uniform over
+    the triangle, or (on_edges) on its edges and vertices, where a hit lies on
+    a face of the leaf's box."""
+    rng = np.random.default_rng(seed)
+    v = np.asarray(verts, np.float64)
+    diag = float(np.linalg.norm(v.reshape(-1, 3).max(0) - v.reshape(-1, 3).min(0)))
+    tri = rng.integers(0, len(v), n)
+    a = rng.random(n)
+    b = rng.random(n)
+    if on_edges:
+        k = rng.integers(0, 3, n)               # edge k, or a vertex when the edge parameter is 0
+        a = np.where(rng.random(n) < 0.3, 0.0, a)
+        bary = np.zeros((n, 3))
+        bary[np.arange(n), k] = 1 - a
+        bary[np.arange(n), (k + 1) % 3] = a
+    else:
+        fold = a + b > 1
+        a, b = np.where(fold, 1 - a, a), np.where(fold, 1 - b, b)
+        bary = np.stack([1 - a - b, a, b], 1)
+    P = np.einsum("nk,nkj->nj", bary, v[tri])
+    nrm = np.cross(v[tri, 1] - v[tri, 0], v[tri, 2] - v[tri, 0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    w = rng.standard_normal((n, 3))
+    w -= (w * nrm).sum(1, keepdims=True) * nrm
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    th = np.asarray(angles, np.float64)[rng.integers(0, len(angles), n)]
+    side = np.where(rng.random(n) < 0.5, -1.0, 1.0)[:, None]
+    d = np.cos(th)[:, None] * w + np.sin(th)[:, None] * side * nrm
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    L = rng.uniform(dist[0], dist[1], n) * diag
+    out = np.zeros((n, 8), np.float32)
+    out[:, 0:3] = P - L[:, None] * d
+    out[:, 4:7] = d
+    out[:, 7] = np.inf
+    return out
+
+
+def far_origin_rays(verts, n: int, scales=(1e2, 1e3, 1e4, 1e5), seed=8) -> np.ndarray:
+    """Rays from far outside the scene (scale x its extent away) aimed at
+    random points of random triangles of `verts`."""
+    rng = np.random.default_rng(seed)
+    v = np.asarray(verts, np.float64)
+    pts = v.reshape(-1, 3)
+    ext = float((pts.max(0) - pts.min(0)).max())
+    tri = rng.integers(0, len(v), n)
+    a, b = rng.random(n), rng.random(n)
+    fold = a + b > 1
+    a, b = np.where(fold, 1 - a, a), np.where(fold, 1 - b, b)
+    P = v[tri, 0] + a[:, None] * (v[tri, 1] - v[tri, 0]) + b[:, None] * (v[tri, 2] - v[tri, 0])
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    L = np.asarray(scales, np.float64)[rng.integers(0, len(scales), n)] * ext
+    out = np.zeros((n, 8), np.float32)
+    out[:, 0:3] = P - L[:, None] * d
+    out[:, 4:7] = d
+    out[:, 7] = np.inf
+    return out
+
+
 def soup_workload(n_tri=1 << 20, width=1920, height=1080, n_incoherent=1 << 21, seed=2):
     """Traversal-only workload: scene + coherent pinhole rays + incoherent rays."""
     s = soup_scene(n_tri, seed)

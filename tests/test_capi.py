@@ -8,7 +8,7 @@ import re
 import numpy as np
 import pytest
 
-from bvh_structure import check_structure, decode, f32
+from bvh_structure import check_structure, decode, f32, wt32
 from paper_1505_06022_amd import api, scenes
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -138,10 +138,10 @@ def _py_traverse(nodes, tris, info, ray, s):
         t1 = (hi[i] - o) * inv
         tn = np.nanmax(np.concatenate([np.minimum(t0, t1), [tmin]]))
         tf_ = np.nanmin(np.concatenate([np.maximum(t0, t1), [tb]]))
-        hit = tn <= tf_ * (1 + 1e-6) + 1e-12
+        hit = tn <= tf_ + abs(tf_) * 2.0 ** -16 + 1e-12
         if hit and leaf[i]:
             for k in range(first[i], first[i] + cnt[i]):
-                t = _mt32(ray, tf[k])
+                t = _wt32(ray, tf[k])
                 idx = int(tris[k, 9])
                 if t is not None and t > tmin and (t < tb or (t == tb and best >= 0 and idx < best)):
                     tb, best = t, idx
@@ -149,31 +149,10 @@ def _py_traverse(nodes, tris, info, ray, s):
     return best, tb
 
 
-def _mt32(ray, tri):
-    f = np.float32
-    o, d = ray[0:3], ray[4:7]
-    v0, e1, e2 = tri[0:3], tri[3:6], tri[6:9]
-
-    def cross(a, b):
-        return np.array([f(a[1] * b[2]) - f(a[2] * b[1]), f(a[2] * b[0]) - f(a[0] * b[2]),
-                         f(a[0] * b[1]) - f(a[1] * b[0])], np.float32)
-
-    def dot(a, b):
-        return f(f(f(a[0] * b[0]) + f(a[1] * b[1])) + f(a[2] * b[2]))
-    p = cross(d, e2)
-    det = dot(e1, p)
-    if det == 0:
-        return None
-    inv = f(f(1) / det)
-    s = (o - v0).astype(np.float32)
-    u = f(dot(s, p) * inv)
-    if u < 0 or u > 1:
-        return None
-    q = cross(s, e1)
-    v = f(dot(d, q) * inv)
-    if v < 0 or f(u + v) > 1:
-        return None
-    return float(f(dot(e2, q) * inv))
+def _wt32(ray, tri):
+    """The device's float32 watertight triangle test for one ray: t or None."""
+    ok, t, _ = wt32(ray[None, 0:3], ray[None, 4:7], tri[None, 0:9])
+    return float(t[0]) if ok[0] else None
 
 
 @pytest.mark.parametrize("seed,n", [(0, 1), (1, 5), (2, 33), (3, 64), (4, 300)])
@@ -216,7 +195,7 @@ def _py_wave_postponed(nodes, tris, info, rays, s, late, steps=1):
         with np.errstate(invalid="ignore"):
             tn = np.nanmax(np.concatenate([np.minimum(t0, t1), [tmin[r]]]))
             tf_ = np.nanmin(np.concatenate([np.maximum(t0, t1), [tb[r]]]))
-        return tn <= tf_ * (1 + 1e-6) + 1e-12
+        return tn <= tf_ + abs(tf_) * 2.0 ** -16 + 1e-12
 
     while True:
         while True:
@@ -245,7 +224,7 @@ def _py_wave_postponed(nodes, tris, info, rays, s, late, steps=1):
         for r in np.nonzero(held >= 0)[0]:
             k = held[r]
             for j in range(first[k], first[k] + cnt[k]):
-                t = _mt32(rays[r], tf[j])
+                t = _wt32(rays[r], tf[j])
                 idx = int(tris[j, 9])
                 if t is not None and t > tmin[r] and (t < tb[r] or (t == tb[r] and best[r] >= 0 and idx < best[r])):
                     tb[r], best[r] = t, idx

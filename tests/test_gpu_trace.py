@@ -1,7 +1,7 @@
 """GPU parity of pm_trace_rays against the oracle's brute-force closest hit.
 
 Hit index must match bit-exactly; t must agree to 1e-5 relative (the same
-float32 Moller-Trumbore arithmetic on both sides makes it exact in practice,
+float32 watertight triangle test on both sides makes it exact in practice,
 which is asserted as well).
 """
 import sys
@@ -103,6 +103,28 @@ def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder
     h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel, refill=refill, counters=cnt, reorder=reorder,
                       block=block)
     _compare(h, t, h_ref, t_ref)
+
+
+@pytest.mark.parametrize("builder", [api.BUILD_HOST_SAH, api.BUILD_GPU_LBVH])
+@pytest.mark.parametrize("kind", ["soup", "box"])
+def test_grazing_and_far_origin_rays(torch_cuda, oracle_lib, builder, kind):
+    """Rays that stress the box test's conservativeness: grazing angles
+    1e-1..1e-6 rad at interior points and at edges/vertices of the triangle
+    they aim at, and origins 10^2..10^5 extents away; every traversal kernel,
+    both builders, against brute force."""
+    _log(f"case: grazing/far-origin rays builder={builder} scene={kind}")
+    verts = (scenes.small_soup(4096, 11, spread=0.03).verts if kind == "soup"
+             else scenes.box_scene(8, 8).verts)
+    angles = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+    rays = np.concatenate([scenes.grazing_rays(verts, 3000, angles, seed=21, on_edges=False),
+                           scenes.grazing_rays(verts, 3000, angles, seed=22, on_edges=True),
+                           scenes.far_origin_rays(verts, 2000, seed=31)])
+    h_ref, t_ref = oracle_lib.trace_brute_force(verts, rays)
+    assert (h_ref >= 0).mean() > 0.5
+    bvh = api.build_bvh(verts, builder=builder)
+    for kernel in (1, 2, 3, 4, 5, 6):
+        h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel)
+        _compare(h, t, h_ref, t_ref)
 
 
 @pytest.mark.parametrize("kernel,block", [(1, 0), (3, 64), (4, 128), (6, 0), (6, 64)])

@@ -1,6 +1,6 @@
 """Pins of the oracle's closest-hit definition and of its independent BVH.
 
-* Moller-Trumbore in float32 against an exact rational solve of
+* The watertight triangle test in float32 against an exact rational solve of
   o + t d = v0 + u e1 + v e2 (Cramer's rule over Fractions) on random
   rays and triangles, wherever the exact answer is not within rounding of a
   boundary.
@@ -38,7 +38,7 @@ def _exact(o, d, tri):
     return t, u, v
 
 
-def test_mt_against_exact_rational_solve(oracle_lib):
+def test_triangle_test_against_exact_rational_solve(oracle_lib):
     rng = np.random.default_rng(1)
     ntri, nray = 24, 150
     verts = rng.uniform(-1, 1, (ntri, 3, 3)).astype(np.float32)

@@ -131,9 +131,15 @@ def test_hit_points_project_back_to_their_pixel(oracle_lib):
     up = np.cross(rgt, f)
     W, H = cam.width, cam.height
     assert hp.valid.all()
+    # the triangle test's hit point o + t d lies within 22u (|t d_y| + L) of the
+    # floor's box (y = 0) along y, L its longest edge, u = 2^-24; forming it in
+    # float adds a rounding of |o_y| + |t d_y| or so
+    u = 2.0 ** -24
+    L = 2 * 40.0 * np.sqrt(2.0)
     for p in range(W * H):
         x = hp.x[p].astype(np.float64)
-        assert abs(x[1]) < 1e-6                       # on the floor
+        dist = np.linalg.norm(x - pos)
+        assert abs(x[1]) <= 22 * u * (dist + L) + 2 * u * (abs(pos[1]) + dist)   # on the floor
         v = x - pos
         sx = np.dot(v, rgt) / np.dot(v, f) / (cam.tan_half_fov * W / H)
         sy = np.dot(v, up) / np.dot(v, f) / cam.tan_half_fov
