@@ -156,7 +156,10 @@ PM_API int pm_trace_rays(const pm_bvh *bvh, const float *rays, int64_t n, int32_
  * in lockstep (two node loads in flight per lane); or a wavefront's rays as
  * one packet (the wavefront follows one node index, taking the hit link when
  * any lane's box test passes; used when all its rays share a link set, else
- * the per-ray walk).  All return the same result. */
+ * the per-ray walk); or the postponed walk over a slice of consecutive rays
+ * per wavefront (the order of reorder, else the input order), a lane taking
+ * the slice's next ray when its own has ended.  All return the same
+ * result. */
 enum {
     PM_TRACE_AUTO = 0,
     PM_TRACE_PER_RAY = 1,
@@ -164,7 +167,8 @@ enum {
     PM_TRACE_PAIRED = 3,
     PM_TRACE_POSTPONED = 4,
     PM_TRACE_TWO_RAYS = 5,
-    PM_TRACE_PACKET = 6
+    PM_TRACE_PACKET = 6,
+    PM_TRACE_SLICES = 7
 };
 
 typedef struct {
@@ -177,7 +181,8 @@ typedef struct {
                            (1..64; 0 = default 16).  Postponed kernel: lanes
                            of a wavefront still searching for a leaf hit at
                            which the held leaves are tested (0..63; 0 = only
-                           once no lane is searching) */
+                           once no lane is searching); the same for the slice
+                           kernel, whose idle lanes also take new rays then */
     int32_t reorder;    /* 1: first bucket the rays by (origin cell of a 16^3
                            grid over the scene in Morton order, then link set)
                            and trace them in that order; 2: the same with a
@@ -194,7 +199,11 @@ typedef struct {
     int32_t tile_width; /* > 0: the rays are the pixels of an image this
                            wide in row-major order (n a multiple of it); each
                            wavefront takes an 8x8 pixel tile.  Not with
-                           reorder, the persistent or the two-ray kernel. */
+                           reorder, the persistent, the two-ray or the slice
+                           kernel. */
+    int32_t slice;      /* slice kernel: rays per wavefront (0 = enough
+                           wavefronts for two per wavefront slot of the
+                           device, at least 64 rays each) */
 } pm_trace_opts;
 
 /* pm_trace_rays with options (ablation of the link-set choice; per-ray

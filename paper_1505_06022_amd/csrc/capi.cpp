@@ -199,11 +199,14 @@ static int parse_trace(const float *rays, int64_t n, int32_t *hit, float *t, con
     if (opts) {
         if (opts->size < sizeof(pm_trace_opts)) return pm::set_error("pm_trace_opts.size too small"), PM_ERR_ARG;
         if (opts->link_set < -1 || opts->link_set > 5) return pm::set_error("link_set must be in [-1,5]"), PM_ERR_ARG;
-        if (opts->kernel < 0 || opts->kernel > PM_TRACE_PACKET)
+        if (opts->kernel < 0 || opts->kernel > PM_TRACE_SLICES)
             return pm::set_error("unknown traversal kernel"), PM_ERR_ARG;
         if (opts->refill < 0 || opts->refill > 64) return pm::set_error("refill must be in [0,64]"), PM_ERR_ARG;
-        if (opts->kernel == PM_TRACE_POSTPONED && opts->refill > 63)
-            return pm::set_error("postponed kernel: refill (lanes still searching) must be in [0,63]"), PM_ERR_ARG;
+        if ((opts->kernel == PM_TRACE_POSTPONED || opts->kernel == PM_TRACE_SLICES) && opts->refill > 63)
+            return pm::set_error("postponed and slice kernels: refill (lanes still searching) must be in [0,63]"),
+                   PM_ERR_ARG;
+        if (opts->slice < 0 || opts->slice > (1 << 24))
+            return pm::set_error("slice must be in [0, 2^24]"), PM_ERR_ARG;
         if (opts->reorder < 0 || opts->reorder > 2) return pm::set_error("reorder must be 0, 1 or 2"), PM_ERR_ARG;
         if (opts->block != 0 && opts->block != 64 && opts->block != 128 && opts->block != 256)
             return pm::set_error("block must be 0, 64, 128 or 256"), PM_ERR_ARG;
@@ -211,9 +214,10 @@ static int parse_trace(const float *rays, int64_t n, int32_t *hit, float *t, con
         if (opts->tile_width > 0) {
             if (n % opts->tile_width != 0)
                 return pm::set_error("tile_width must divide the number of rays"), PM_ERR_ARG;
-            if (opts->reorder != 0 || opts->kernel == PM_TRACE_PERSISTENT || opts->kernel == PM_TRACE_TWO_RAYS)
-                return pm::set_error("tile_width takes the rays in image order: no reorder, persistent or "
-                                     "two-ray kernel"),
+            if (opts->reorder != 0 || opts->kernel == PM_TRACE_PERSISTENT || opts->kernel == PM_TRACE_TWO_RAYS ||
+                opts->kernel == PM_TRACE_SLICES)
+                return pm::set_error("tile_width takes the rays in image order: no reorder, persistent, "
+                                     "two-ray or slice kernel"),
                        PM_ERR_ARG;
         }
         a.link_set = opts->link_set;
@@ -223,6 +227,7 @@ static int parse_trace(const float *rays, int64_t n, int32_t *hit, float *t, con
         a.refill = opts->refill;
         a.reorder = opts->reorder;
         a.block = opts->block;
+        a.slice = opts->slice;
     }
     if (n >= (int64_t(1) << 31)) return pm::set_error("n must be below 2^31"), PM_ERR_ARG;
     return PM_OK;
@@ -236,8 +241,7 @@ int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int32_t *h
         pm::TraceArgs a;
         int rc = parse_trace(rays, n, hit, t, opts, a);
         if (rc) return rc;
-        return pm::launch_trace(bvh, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill, a.reorder,
-                                a.block, a.tile_w, (hipStream_t)stream);
+        return pm::launch_trace(bvh, a, (hipStream_t)stream);
     })
 }
 
@@ -255,8 +259,7 @@ int pm_trace_rays_noalloc(const pm_bvh *bvh, const float *rays, int64_t n, int32
         if (rc) return rc;
         if (a.reorder == 0) a.reorder = 1;
         if (a.tile_w != 0) return pm::set_error("tile_width does not apply to the bucketed trace"), PM_ERR_ARG;
-        return pm::launch_trace_noalloc(bvh, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill,
-                                        a.reorder, a.block, (hipStream_t)stream);
+        return pm::launch_trace_noalloc(bvh, a, (hipStream_t)stream);
     })
 }
 

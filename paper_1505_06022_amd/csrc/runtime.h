@@ -75,27 +75,26 @@ int build_bvh_gpu(const float *verts, const uint32_t *mats, int64_t n_tri, int m
 int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b);
 void free_bvh(pm_bvh *b);
 
-// Launch the closest-hit kernel.  link_set < 0 selects by direction; block:
-// threads per workgroup of the one-ray-per-lane kernels (64, 128 or 256);
-// tile_w > 0: the rays are an image tile_w wide, taken in 8x8 tiles per wave.
-int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, int reorder, int block, int tile_w, hipStream_t s);
-
-// The bucketed trace (reorder 1 or 2) on the library's static per-device
-// scratch: no allocation; n <= PM_NOALLOC_MAX_RAYS; b must be on the current
-// device.
-int launch_trace_noalloc(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                         uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s);
-
-// Validated arguments of one traced batch.
+// Validated arguments of one traced batch.  link_set < 0 selects by
+// direction; block: threads per workgroup of the one-ray-per-lane kernels
+// (64, 128 or 256); tile_w > 0: the rays are an image tile_w wide, taken in
+// 8x8 tiles per wave; slice: rays per wavefront of the slice kernel.
 struct TraceArgs {
     const float *rays = nullptr;
     int64_t n = 0;
     int32_t *hit = nullptr;
     float *t = nullptr;
-    int link_set = -1, kernel = PM_TRACE_AUTO, refill = 0, reorder = 0, block = 0, tile_w = 0;
+    int link_set = -1, kernel = PM_TRACE_AUTO, refill = 0, reorder = 0, block = 0, tile_w = 0, slice = 0;
     uint32_t *counters = nullptr;
 };
+
+// Launch the closest-hit kernel for one batch.
+int launch_trace(const pm_bvh *b, const TraceArgs &a, hipStream_t s);
+
+// The bucketed trace (reorder 1 or 2) on the library's static per-device
+// scratch: no allocation; n <= PM_NOALLOC_MAX_RAYS; b must be on the current
+// device.
+int launch_trace_noalloc(const pm_bvh *b, const TraceArgs &a, hipStream_t s);
 
 // Batches 1.. on the handle's own streams, forked from and joined to s.
 int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, hipStream_t s);

@@ -112,6 +112,80 @@ __device__ __forceinline__ void trace_slot(const pmd::Bvh &bvh, const float4 *__
     }
 }
 
+// Postponed-leaf walk over one wavefront's slice of the ray order: rays
+// begin .. end - 1 of perm (or of the input order without perm).  A lane
+// whose ray has ended takes the next ray of the slice, so lanes do not idle
+// while the wave's longest walk runs: the scheduling idea of the paper's
+// photon path regeneration (Sec. 3.3), applied to rays.  A slice is a
+// contiguous run of the bucketed order, so a wave's rays stay close in
+// space.  The wave visits boxes until at most `late` lanes are still
+// searching for a leaf hit and either some lane holds one or some lane can
+// take a new ray; then the held leaves are tested, ended rays written and
+// idle lanes refilled.  Each round advances a searching lane, tests a held
+// leaf or starts a ray, so the walk ends (late < 64).  The closest hit of a
+// ray does not depend on when it is walked.  Called by all lanes of a wave
+// with wave-uniform begin and end.
+template <bool kStats>
+__device__ __forceinline__ void walk_slice(const pmd::Bvh &bvh, const float4 *__restrict__ rays,
+                                           const uint32_t *__restrict__ perm, uint32_t begin, uint32_t end,
+                                           int32_t *__restrict__ hit, float *__restrict__ tout, int32_t force_set,
+                                           uint32_t *__restrict__ counters, uint32_t late) {
+    pmd::Walker w;
+    w.i = w.n = 0u;  // no ray yet
+    pmd::TraceStats st{0u, 0u};
+    size_t r = 0;
+    bool active = false, halted = false;
+    uint32_t held = 0u;
+    uint32_t cursor = begin;  // next ray of the slice (wave-uniform)
+    for (;;) {
+        const bool idle = !active;
+        const uint64_t idle_mask = __ballot(idle);
+        if (idle_mask != 0ull && cursor < end) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
+            if (idle && rank < end - cursor) {
+                r = perm ? perm[cursor + rank] : (size_t)(cursor + rank);
+                start_walk(w, bvh, rays, r, force_set);
+                st = pmd::TraceStats{0u, 0u};
+                active = true;
+            }
+            const uint32_t taken = (uint32_t)__popcll(idle_mask);
+            cursor = taken < end - cursor ? cursor + taken : end;
+        }
+        if (__ballot(active) == 0ull) break;
+        for (;;) {
+            const uint64_t searching = __ballot(w.i < w.n && held == 0u);
+            if (searching == 0ull) break;
+            if ((uint32_t)__popcll(searching) <= late &&
+                (__ballot(held != 0u) != 0ull || (cursor < end && __ballot(w.i >= w.n && held == 0u) != 0ull)))
+                break;
+            w.postponed_visits<kStats>(held, halted, st);
+        }
+        if (held != 0u) w.leaf_tris<kStats>(bvh.tris, held, st);
+        held = 0u;
+        halted = false;
+        if (active && w.i >= w.n) {
+            finish_walk<kStats>(w, st, r, hit, tout, counters);
+            active = false;
+        }
+    }
+}
+
+// Rays in slices of `slice` consecutive entries of perm (or of the input
+// order), one slice per wavefront.
+template <bool kStats>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_slices(pmd::Bvh bvh, const float4 *__restrict__ rays,
+                                                              const uint32_t *__restrict__ perm, uint32_t n,
+                                                              int32_t *__restrict__ hit, float *__restrict__ tout,
+                                                              int32_t force_set, uint32_t *__restrict__ counters,
+                                                              uint32_t late, uint32_t slice) {
+    const uint32_t wave = (pmd::xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t begin = (uint64_t)wave * slice;
+    if (begin >= n) return;
+    const uint32_t end = (uint32_t)(begin + slice < n ? begin + slice : n);
+    walk_slice<kStats>(bvh, rays, perm, (uint32_t)begin, end, hit, tout, force_set, counters, late);
+}
+
 // Rays in input order.
 template <bool kStats, int kWalk>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(pmd::Bvh bvh, const float4 *__restrict__ rays, int64_t n,
@@ -267,7 +341,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const 
 }
 
 // Two batches in one launch: the first blocksA workgroups walk batch A in
-// the order of perm (postponed leaf tests); the rest take batch B, an image
+// the order of perm (postponed leaf tests, one ray per lane or, with
+// sliceA > 0, one slice of sliceA rays per wavefront); the rest take batch B, an image
 // tile_w wide, one 8x8 pixel tile per wavefront, as packets.  The dispatcher
 // hands out B's workgroups once all of A's are running, so B fills the
 // device as A's last wavefronts drain.
@@ -276,10 +351,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_perm_then_tiles(
     pmd::Bvh bvh, uint32_t blocksA, const float4 *__restrict__ raysA, const uint32_t *__restrict__ perm, uint32_t nA,
     int32_t *__restrict__ hitA, float *__restrict__ tA, int32_t setA, uint32_t *__restrict__ countersA, uint32_t late,
     const float4 *__restrict__ raysB, int64_t nB, int32_t *__restrict__ hitB, float *__restrict__ tB, int32_t setB,
-    uint32_t *__restrict__ countersB, uint32_t tile_w) {
+    uint32_t *__restrict__ countersB, uint32_t tile_w, uint32_t sliceA) {
     if (blockIdx.x < blocksA) {
         const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, blocksA) * blockDim.x + threadIdx.x;
-        trace_slot<kStats, kWalkPostponed, true>(bvh, raysA, perm, lane, nA, hitA, tA, setA, countersA, late, 0u);
+        if (sliceA == 0u) {
+            trace_slot<kStats, kWalkPostponed, true>(bvh, raysA, perm, lane, nA, hitA, tA, setA, countersA, late, 0u);
+        } else {
+            const uint64_t begin = (lane >> 6) * sliceA;
+            if (begin >= nA) return;
+            const uint32_t end = (uint32_t)(begin + sliceA < nA ? begin + sliceA : nA);
+            walk_slice<kStats>(bvh, raysA, perm, (uint32_t)begin, end, hitA, tA, setA, countersA, late);
+        }
     } else {
         const uint64_t lane =
             (uint64_t)pmd::xcd_block(blockIdx.x - blocksA, gridDim.x - blocksA) * blockDim.x + threadIdx.x;
@@ -373,6 +455,38 @@ static int persistent_grid(int device, uint32_t &grid) {
     return PM_OK;
 }
 
+// Rays per wavefront of the slice kernel: the given count, else enough
+// wavefronts for two per wavefront slot of the device (at least 64 rays).
+static int slice_rays(int device, int64_t n, int slice, uint32_t &out) {
+    if (slice > 0) {
+        out = (uint32_t)slice;
+        return PM_OK;
+    }
+    uint32_t grid = 0;
+    int rc = persistent_grid(device, grid);
+    if (rc) return rc;
+    const uint64_t waves = 2ull * grid * (kTraceBlock / 64);
+    uint64_t per = ((uint64_t)n + waves - 1) / waves;
+    per = (per + 63) / 64 * 64;
+    out = (uint32_t)std::max<uint64_t>(64, per);
+    return PM_OK;
+}
+
+static int launch_slices(const pm_bvh *b, const pmd::Bvh &bvh, const float *rays, uint32_t n, int32_t *hit,
+                         float *t, int link_set, uint32_t *counters, uint32_t late, int slice, uint32_t block,
+                         const uint32_t *perm, hipStream_t s) {
+    uint32_t per = 0;
+    int rc = slice_rays(b->device, n, slice, per);
+    if (rc) return rc;
+    const uint64_t waves = ((uint64_t)n + per - 1) / per;
+    const uint64_t blocks = (waves * 64 + block - 1) / block;
+    if (blocks > 0x7fffffffull) return set_error("too many rays for one launch"), PM_ERR_ARG;
+    hipLaunchKernelGGL(counters ? k_trace_slices<true> : k_trace_slices<false>, dim3((uint32_t)blocks), dim3(block),
+                       0, s, bvh, (const float4 *)rays, perm, n, hit, t, link_set, counters, late, per);
+    PM_HIP(hipGetLastError());
+    return PM_OK;
+}
+
 static int walk_of(int kernel) {
     switch (kernel) {
     case PM_TRACE_PAIRED: return kWalkPaired;
@@ -463,12 +577,14 @@ static int bucket_rays(const pm_bvh *b, const BucketScratch &sc, const float *ra
 
 static int launch_trace_reordered(const pm_bvh *b, const BucketScratch &sc, const pmd::Bvh &bvh, const float *rays,
                                   int64_t n, int32_t *hit, float *t, int link_set, uint32_t *counters, int kernel,
-                                  uint32_t late, int reorder, uint32_t block, hipStream_t s) {
+                                  uint32_t late, int reorder, uint32_t block, int slice, hipStream_t s) {
     int rc = bucket_rays(b, sc, rays, n, link_set, reorder, s);
     if (rc) return rc;
     const uint32_t nn = (uint32_t)n;
     if (kernel == PM_TRACE_PERSISTENT)
         return launch_persistent(b, bvh, rays, nn, hit, t, link_set, counters, (int)late, sc.perm, s);
+    if (kernel == PM_TRACE_SLICES)
+        return launch_slices(b, bvh, rays, nn, hit, t, link_set, counters, late, slice, block, sc.perm, s);
     using Kern = void (*)(pmd::Bvh, const float4 *, const uint32_t *, uint32_t, int32_t *, float *, int32_t,
                           uint32_t *, uint32_t);
     const int wk = walk_of(kernel);
@@ -512,33 +628,40 @@ static int noalloc_scratch(int device, BucketScratch &sc) {
     return PM_OK;
 }
 
-int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                 uint32_t *counters, int kernel, int refill, int reorder, int block, int tile_w, hipStream_t s) {
-    if (block == 0) block = kDefaultWalkBlock;
+int launch_trace(const pm_bvh *b, const TraceArgs &a, hipStream_t s) {
+    const int64_t n = a.n;
+    const int block = a.block == 0 ? kDefaultWalkBlock : a.block;
+    int kernel = a.kernel;
     if (n == 0) return PM_OK;
     pmd::Bvh bvh = make_device_bvh(b);
-    // the postponed walk reads its threshold from the refill option (and the
-    // persistent one its refill count)
-    const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT ? (uint32_t)refill : 0u;
-    if (reorder) {
+    // the postponed and slice walks read their threshold from the refill
+    // option (and the persistent one its refill count)
+    const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT || kernel == PM_TRACE_SLICES
+                              ? (uint32_t)a.refill
+                              : 0u;
+    if (a.reorder) {
         BucketScratch sc;
         int rc = bvh_scratch(const_cast<pm_bvh *>(b), n, s, sc);
         if (rc) return rc;
-        return launch_trace_reordered(b, sc, bvh, rays, n, hit, t, link_set, counters, kernel, late, reorder,
-                                      (uint32_t)block, s);
+        return launch_trace_reordered(b, sc, bvh, a.rays, n, a.hit, a.t, a.link_set, a.counters, kernel, late,
+                                      a.reorder, (uint32_t)block, a.slice, s);
     }
     if (kernel == 0) kernel = PM_TRACE_PER_RAY;
-    if (kernel == PM_TRACE_PERSISTENT) {
+    if (kernel == PM_TRACE_PERSISTENT || kernel == PM_TRACE_SLICES) {
         if (n >= (int64_t(1) << 31)) {
             set_error("too many rays for one launch");
             return PM_ERR_ARG;
         }
-        return launch_persistent(b, bvh, rays, (uint32_t)n, hit, t, link_set, counters, refill, nullptr, s);
+        if (kernel == PM_TRACE_SLICES)
+            return launch_slices(b, bvh, a.rays, (uint32_t)n, a.hit, a.t, a.link_set, a.counters, late, a.slice,
+                                 (uint32_t)block, nullptr, s);
+        return launch_persistent(b, bvh, a.rays, (uint32_t)n, a.hit, a.t, a.link_set, a.counters, a.refill, nullptr,
+                                 s);
     }
     const int wk = walk_of(kernel);
     int64_t lanes = wk == kWalkTwo ? (n + 1) / 2 : n;
-    if (tile_w > 0) {  // one wave per 8x8 tile of a tile_w x (n / tile_w) image
-        const int64_t tiles = ((tile_w + 7) / 8) * ((n / tile_w + 7) / 8);
+    if (a.tile_w > 0) {  // one wave per 8x8 tile of a tile_w x (n / tile_w) image
+        const int64_t tiles = ((a.tile_w + 7) / 8) * ((n / a.tile_w + 7) / 8);
         lanes = tiles * 64;
     }
     int64_t nblk = (lanes + block - 1) / block;
@@ -548,14 +671,14 @@ int launch_trace(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, fl
     }
     using Kern = void (*)(pmd::Bvh, const float4 *, int64_t, int32_t *, float *, int32_t, uint32_t *, uint32_t,
                           uint32_t);
-    Kern kern = counters ? pick_walk<Kern>(wk, k_trace<true, kWalkStep>, k_trace<true, kWalkPaired>,
-                                           k_trace<true, kWalkPostponed>, k_trace<true, kWalkTwo>,
-                                           k_trace<true, kWalkPacket>)
-                         : pick_walk<Kern>(wk, k_trace<false, kWalkStep>, k_trace<false, kWalkPaired>,
-                                           k_trace<false, kWalkPostponed>, k_trace<false, kWalkTwo>,
-                                           k_trace<false, kWalkPacket>);
-    hipLaunchKernelGGL(kern, dim3((uint32_t)nblk), dim3(block), 0, s, bvh, (const float4 *)rays, n, hit, t,
-                       link_set, counters, late, (uint32_t)tile_w);
+    Kern kern = a.counters ? pick_walk<Kern>(wk, k_trace<true, kWalkStep>, k_trace<true, kWalkPaired>,
+                                             k_trace<true, kWalkPostponed>, k_trace<true, kWalkTwo>,
+                                             k_trace<true, kWalkPacket>)
+                           : pick_walk<Kern>(wk, k_trace<false, kWalkStep>, k_trace<false, kWalkPaired>,
+                                             k_trace<false, kWalkPostponed>, k_trace<false, kWalkTwo>,
+                                             k_trace<false, kWalkPacket>);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)nblk), dim3(block), 0, s, bvh, (const float4 *)a.rays, n, a.hit, a.t,
+                       a.link_set, a.counters, late, (uint32_t)a.tile_w);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }
@@ -568,7 +691,14 @@ static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs
     if (rc) return rc;
     const pmd::Bvh bvh = make_device_bvh(b);
     const uint32_t nA = (uint32_t)A.n;
-    const uint64_t blocksA = ((uint64_t)nA + block - 1) / block;
+    uint32_t sliceA = 0;  // 0: one ray per lane
+    uint64_t lanesA = nA;
+    if (A.kernel == PM_TRACE_SLICES) {
+        rc = slice_rays(b->device, A.n, A.slice, sliceA);
+        if (rc) return rc;
+        lanesA = ((uint64_t)nA + sliceA - 1) / sliceA * 64;
+    }
+    const uint64_t blocksA = (lanesA + block - 1) / block;
     const int64_t tiles = (((int64_t)B.tile_w + 7) / 8) * ((B.n / B.tile_w + 7) / 8);
     const uint64_t blocksB = ((uint64_t)tiles * 64 + block - 1) / block;
     if (blocksA + blocksB > 0x7fffffffull) return set_error("too many rays for one launch"), PM_ERR_ARG;
@@ -576,22 +706,20 @@ static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs
                        dim3((uint32_t)(blocksA + blocksB)), dim3(block), 0, s, bvh, (uint32_t)blocksA,
                        (const float4 *)A.rays, (const uint32_t *)sc.perm, nA, A.hit, A.t, A.link_set, A.counters,
                        (uint32_t)A.refill, (const float4 *)B.rays, B.n, B.hit, B.t, B.link_set, B.counters,
-                       (uint32_t)B.tile_w);
+                       (uint32_t)B.tile_w, sliceA);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }
 
 int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, hipStream_t s) {
-    auto one = [&](const TraceArgs &a, hipStream_t st) {
-        return launch_trace(b, a.rays, a.n, a.hit, a.t, a.link_set, a.counters, a.kernel, a.refill, a.reorder,
-                            a.block, a.tile_w, st);
-    };
+    auto one = [&](const TraceArgs &a, hipStream_t st) { return launch_trace(b, a, st); };
     if (n_batches == 1) return one(batches[0], s);
     if (n_batches == 2) {  // bucketed postponed walk + packets over image tiles: one launch for both
         for (int k = 0; k < 2; ++k) {
             const TraceArgs &A = batches[k], &B = batches[1 - k];
             const int blk = A.block ? A.block : kDefaultWalkBlock;
-            if (A.reorder != 0 && A.kernel == PM_TRACE_POSTPONED && A.n > 0 && B.kernel == PM_TRACE_PACKET &&
+            if (A.reorder != 0 && (A.kernel == PM_TRACE_POSTPONED || A.kernel == PM_TRACE_SLICES) && A.n > 0 &&
+                B.kernel == PM_TRACE_PACKET &&
                 B.tile_w > 0 && B.reorder == 0 && B.n > 0 && (B.block ? B.block : kDefaultWalkBlock) == blk &&
                 (A.counters == nullptr) == (B.counters == nullptr))
                 return launch_perm_then_tiles(b, A, B, blk, s);
@@ -614,10 +742,11 @@ int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, h
     return rc;
 }
 
-int launch_trace_noalloc(const pm_bvh *b, const float *rays, int64_t n, int32_t *hit, float *t, int link_set,
-                         uint32_t *counters, int kernel, int refill, int reorder, int block, hipStream_t s) {
+int launch_trace_noalloc(const pm_bvh *b, const TraceArgs &a, hipStream_t s) {
+    const int64_t n = a.n;
     if (n > (int64_t)PM_NOALLOC_MAX_RAYS) return set_error("n exceeds PM_NOALLOC_MAX_RAYS"), PM_ERR_ARG;
-    if (reorder != 1 && reorder != 2) return set_error("the allocation-free trace buckets the rays: reorder 1 or 2"), PM_ERR_ARG;
+    if (a.reorder != 1 && a.reorder != 2)
+        return set_error("the allocation-free trace buckets the rays: reorder 1 or 2"), PM_ERR_ARG;
     int dev = -1;
     PM_HIP(hipGetDevice(&dev));
     if (dev != b->device) return set_error("the BVH lives on another device than the current one"), PM_ERR_ARG;
@@ -625,10 +754,13 @@ int launch_trace_noalloc(const pm_bvh *b, const float *rays, int64_t n, int32_t 
     int rc = noalloc_scratch(dev, sc);
     if (rc) return rc;
     if (n == 0) return PM_OK;
-    if (block == 0) block = kDefaultWalkBlock;
-    const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT ? (uint32_t)refill : 0u;
-    return launch_trace_reordered(b, sc, make_device_bvh(b), rays, n, hit, t, link_set, counters, kernel, late, reorder,
-                                  (uint32_t)block, s);
+    const int block = a.block == 0 ? kDefaultWalkBlock : a.block;
+    const int kernel = a.kernel;
+    const uint32_t late = kernel == PM_TRACE_POSTPONED || kernel == PM_TRACE_PERSISTENT || kernel == PM_TRACE_SLICES
+                              ? (uint32_t)a.refill
+                              : 0u;
+    return launch_trace_reordered(b, sc, make_device_bvh(b), a.rays, n, a.hit, a.t, a.link_set, a.counters, kernel,
+                                  late, a.reorder, (uint32_t)block, a.slice, s);
 }
 
 }  // namespace pm

@@ -248,6 +248,104 @@ def test_postponed_leaf_walk_model_matches_brute_force(oracle_lib, late, steps):
         assert np.array_equal(np.float32(t[h >= 0]), t_ref[h >= 0])
 
 
+def _py_wave_slices(nodes, tris, info, rays, s, late, steps, n_rays):
+    """Lockstep model of one wavefront of the slice kernel over rays
+    0 .. n_rays - 1: the postponed walk in which an idle lane takes the
+    slice's next ray (lanes in order) at the top of each round, and the box
+    loop also stops once at most `late` lanes search while a lane could take
+    a new ray.  Returns (best, t) per ray and the number of rounds."""
+    lo, hi, leaf, first, cnt, skip = decode(nodes[s], info)
+    tf = f32(tris)
+    L, n = 64, nodes.shape[1]
+    o_all = rays[:, 0:3].astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv_all = 1.0 / rays[:, 4:7].astype(np.float64)
+    best_out = np.full(n_rays, -2)
+    t_out = np.full(n_rays, np.nan)
+    ray = np.full(L, -1)             # the lane's ray, -1 idle
+    i = np.zeros(L, np.int64)
+    nn = np.zeros(L, np.int64)       # walk length: n while walking, 0 before the first ray
+    tb = np.zeros(L)
+    best = np.full(L, -1)
+    held = np.full(L, -1)
+    halted = np.zeros(L, bool)
+    cursor, rounds = 0, 0
+
+    def box_hit(r, k):
+        rr = ray[r]
+        t0, t1 = (lo[k] - o_all[rr]) * inv_all[rr], (hi[k] - o_all[rr]) * inv_all[rr]
+        with np.errstate(invalid="ignore"):
+            tn = np.nanmax(np.concatenate([np.minimum(t0, t1), [float(rays[rr, 3])]]))
+            tf_ = np.nanmin(np.concatenate([np.maximum(t0, t1), [tb[r]]]))
+        return tn <= tf_ + abs(tf_) * 2.0 ** -16 + 1e-12
+
+    while True:
+        rounds += 1
+        assert rounds < 64 * n * (n_rays + 1), "the slice walk does not end"
+        idle = ray < 0
+        if idle.any() and cursor < n_rays:
+            rank = np.cumsum(idle) - 1
+            for r in np.nonzero(idle & (rank < n_rays - cursor))[0]:
+                ray[r] = cursor + rank[r]
+                i[r], nn[r], tb[r], best[r] = 0, n, float(rays[ray[r], 7]), -1
+            cursor = min(n_rays, cursor + int(idle.sum()))
+        if not (ray >= 0).any():
+            break
+        while True:
+            searching = (i < nn) & (held < 0)
+            if not searching.any():
+                break
+            free = (i >= nn) & (held < 0)
+            if searching.sum() <= late and ((held >= 0).any() or (cursor < n_rays and free.any())):
+                break
+            for _ in range(steps):
+                for r in range(L):
+                    if i[r] >= nn[r] or halted[r]:
+                        continue
+                    k = i[r]
+                    hit = box_hit(r, k)
+                    if hit and leaf[k]:
+                        if held[r] < 0:
+                            held[r], i[r] = k, k + 1
+                        else:
+                            halted[r] = True
+                    else:
+                        i[r] = k + 1 if (hit or leaf[k]) else skip[k]
+        for r in np.nonzero(held >= 0)[0]:
+            k = held[r]
+            for j in range(first[k], first[k] + cnt[k]):
+                t = _wt32(rays[ray[r]], tf[j])
+                idx = int(tris[j, 9])
+                if t is not None and t > rays[ray[r], 3] and (t < tb[r] or (t == tb[r] and best[r] >= 0 and idx < best[r])):
+                    tb[r], best[r] = t, idx
+        held[:] = -1
+        halted[:] = False
+        for r in np.nonzero((ray >= 0) & (i >= nn))[0]:
+            best_out[ray[r]] = best[r]
+            t_out[ray[r]] = tb[r] if best[r] >= 0 else np.inf
+            ray[r] = -1
+    return best_out, t_out, rounds
+
+
+@pytest.mark.parametrize("late,steps,n_rays", [(0, 1, 300), (5, 8, 300), (32, 8, 300), (63, 1, 300), (16, 3, 17),
+                                               (32, 8, 64), (0, 8, 129)])
+def test_slice_walk_model_matches_brute_force(oracle_lib, late, steps, n_rays):
+    """The wave schedule of the slice traversal kernel, modelled on the CPU:
+    it ends, every ray of the slice (also fewer rays than lanes, and a
+    ragged last refill) is written once, and each equals brute force."""
+    sc = scenes.small_soup(300, 4, spread=0.4 / np.cbrt(300))
+    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
+    rays = scenes.random_rays(n_rays, 5)
+    rays[::4, 4:7] = np.abs(rays[::4, 4:7]) * [1, 0.1, 0.1]   # a share of the rays in one link set
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+    for s in (0, 3):
+        h, t, rounds = _py_wave_slices(nodes, tris, info, rays, s, late, steps, n_rays)
+        assert np.all(h >= -1), "a ray of the slice was not written"
+        assert np.array_equal(h, h_ref)
+        assert np.array_equal(np.float32(t[h >= 0]), t_ref[h >= 0])
+        assert np.all(np.isinf(t[h < 0]))
+
+
 def test_host_bvh_box_scene_and_soup_statistics():
     sc = scenes.box_scene()
     nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)

@@ -105,6 +105,52 @@ def test_traversal_kernels_agree(torch_cuda, oracle_lib, kernel, refill, reorder
     _compare(h, t, h_ref, t_ref)
 
 
+@pytest.mark.parametrize("late,reorder,block,slice_", [(32, 1, 64, 0), (32, 0, 256, 0), (0, 2, 128, 100),
+                                                        (63, 1, 64, 1000), (5, 1, 64, 7), (16, 0, 64, 64),
+                                                        (32, 1, 256, 100000)])
+def test_slice_kernel_agrees(torch_cuda, oracle_lib, late, reorder, block, slice_):
+    """The postponed walk over per-wavefront slices with lane refill: every
+    slice size (automatic, ragged, shorter than a wavefront, longer than the
+    batch), threshold and bucketing gives the brute-force closest hits, also
+    in statistics mode."""
+    _log(f"case: slice kernel late={late} reorder={reorder} block={block} slice={slice_}")
+    sc = scenes.small_soup(5000, 11, spread=0.02)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    rays = np.concatenate([scenes.random_rays(7001, 11), scenes.pinhole_rays(sc.camera)])
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+    kw = dict(kernel=api.TRACE_SLICES, refill=late, reorder=reorder, block=block, slice=slice_)
+    h, t = _gpu_trace(torch_cuda, bvh, rays, **kw)
+    _compare(h, t, h_ref, t_ref)
+    cnt = torch_cuda.zeros((len(rays), 2), dtype=torch_cuda.int32, device="cuda")
+    h, t = _gpu_trace(torch_cuda, bvh, rays, counters=cnt, **kw)
+    _compare(h, t, h_ref, t_ref)
+    c = cnt.cpu().numpy()
+    assert np.all(c[:, 0] >= 1) and np.all(c[:, 1] >= (h >= 0))
+
+
+def test_fused_slices_and_packets_equal_single_calls(torch_cuda, oracle_lib):
+    """Two batches, the bucketed slice walk and packets over image tiles, in
+    one fused launch: the same results as two single calls and as brute
+    force (automatic and explicit slice sizes)."""
+    _log("case: fused slices + packets, soup 2^14")
+    sc = scenes.soup_scene(1 << 14, 4)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    cam = scenes.pinhole_rays(scenes.Camera(pos=(0.5, 0.5, -1.5), look=(0.5, 0.5, 0.5), up=(0, 1, 0),
+                                            tan_half_fov=0.4, width=96, height=40))
+    inc = scenes.random_rays(5000, 9)
+    rc, ri = (torch_cuda.from_numpy(np.ascontiguousarray(x)).cuda() for x in (cam, inc))
+    kc = dict(kernel=api.TRACE_PACKET, block=64, tile_width=96)
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, inc)
+    for slice_ in (0, 130):
+        ki = dict(kernel=api.TRACE_SLICES, refill=32, reorder=1, block=64, slice=slice_)
+        single = [api.trace_rays(bvh, rc, **kc), api.trace_rays(bvh, ri, **ki)]
+        two = api.trace_rays_multi(bvh, [dict(rays=rc, **kc), dict(rays=ri, **ki)])
+        for (h, t), (hr, tr) in zip(two, single):
+            assert np.array_equal(h.cpu().numpy(), hr.cpu().numpy()), slice_
+            assert np.array_equal(t.cpu().numpy(), tr.cpu().numpy()), slice_
+        _compare(two[1][0].cpu().numpy(), two[1][1].cpu().numpy(), h_ref, t_ref)
+
+
 @pytest.mark.parametrize("builder", [api.BUILD_HOST_SAH, api.BUILD_GPU_LBVH])
 @pytest.mark.parametrize("kind", ["soup", "box"])
 def test_grazing_and_far_origin_rays(torch_cuda, oracle_lib, builder, kind):
@@ -211,9 +257,10 @@ def test_trace_option_errors(torch_cuda):
     sc = scenes.small_soup(64, 1)
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     r = torch_cuda.from_numpy(scenes.random_rays(100, 1)).cuda()
-    for kw in (dict(block=100), dict(block=512), dict(kernel=7), dict(kernel=4, refill=64), dict(reorder=3),
-               dict(tile_width=7), dict(tile_width=-1), dict(tile_width=10, reorder=1), dict(tile_width=10, kernel=2),
-               dict(link_set=6)):
+    for kw in (dict(block=100), dict(block=512), dict(kernel=8), dict(kernel=-1), dict(kernel=4, refill=64),
+               dict(kernel=7, refill=64), dict(kernel=7, slice=-1), dict(kernel=7, slice=(1 << 24) + 1),
+               dict(tile_width=10, kernel=7), dict(reorder=3), dict(tile_width=7), dict(tile_width=-1),
+               dict(tile_width=10, reorder=1), dict(tile_width=10, kernel=2), dict(link_set=6)):
         with pytest.raises(api.PMError) as e:
             api.trace_rays(bvh, r, **kw)
         assert e.value.code == api.PM_ERR_ARG, kw

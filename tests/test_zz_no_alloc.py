@@ -46,7 +46,7 @@ def _both(torch, bvh, rays, **kw):
 
 
 @pytest.mark.parametrize("reorder,kernel,refill", [(1, 0, 0), (2, api.TRACE_POSTPONED, 32),
-                                                   (1, api.TRACE_PAIRED, 0)])
+                                                   (1, api.TRACE_PAIRED, 0), (1, api.TRACE_SLICES, 32)])
 def test_noalloc_equals_bucketed_trace_two_calls(torch_cuda, reorder, kernel, refill):
     torch = torch_cuda
     _log(f"case: noalloc trace, soup 2^16, reorder {reorder} kernel {kernel}")
