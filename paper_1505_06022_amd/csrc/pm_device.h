@@ -396,25 +396,6 @@ struct Walker {
 #endif
     static constexpr int kPostponedSteps = PM_POSTPONED_STEPS;
 
-    // kPostponedSteps box visits of a lane that has not halted: the first
-    // leaf hit is held (its link word; the walk moves past it), the next one
-    // halts the lane in front of it until the held leaf has been tested.
-    template <bool kStats>
-    __device__ __forceinline__ void postponed_visits(uint32_t &held, bool &halted, TraceStats &st) {
-#pragma unroll
-        for (int u = 0; u < kPostponedSteps; ++u) {
-            if (i < n && !halted) {
-                const uint4 q = nodes[i];
-                if (kStats) st.boxes++;
-                const bool leaf = (q.w >> 31) != 0u, hit = box_hit(q);
-                const bool leaf_hit = hit && leaf;
-                halted = leaf_hit && held != 0u;
-                held = (leaf_hit && held == 0u) ? q.w : held;
-                i = halted ? i : ((hit || leaf) ? i + 1 : q.w);
-            }
-        }
-    }
-
     template <bool kStats>
     __device__ __forceinline__ void walk_postponed(const float4 *__restrict__ tris, uint32_t late, TraceStats &st) {
         uint32_t held = 0u;  // link word of a leaf hit not yet tested, or 0
@@ -424,7 +405,18 @@ struct Walker {
                 const uint64_t searching = __ballot(i < n && held == 0u);
                 if (searching == 0ull) break;
                 if ((uint32_t)__popcll(searching) <= late && __ballot(held != 0u) != 0ull) break;
-                postponed_visits<kStats>(held, halted, st);
+#pragma unroll
+                for (int u = 0; u < kPostponedSteps; ++u) {
+                    if (i < n && !halted) {
+                        const uint4 q = nodes[i];
+                        if (kStats) st.boxes++;
+                        const bool leaf = (q.w >> 31) != 0u, hit = box_hit(q);
+                        const bool leaf_hit = hit && leaf;
+                        halted = leaf_hit && held != 0u;
+                        held = (leaf_hit && held == 0u) ? q.w : held;
+                        i = halted ? i : ((hit || leaf) ? i + 1 : q.w);
+                    }
+                }
             }
             if (__ballot(held != 0u) == 0ull) break;  // no lane searching and none holding: all done
             if (held != 0u) leaf_tris<kStats>(tris, held, st);

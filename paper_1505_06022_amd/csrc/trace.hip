@@ -159,7 +159,18 @@ __device__ __forceinline__ void walk_slice(const pmd::Bvh &bvh, const float4 *__
             if ((uint32_t)__popcll(searching) <= late &&
                 (__ballot(held != 0u) != 0ull || (cursor < end && __ballot(w.i >= w.n && held == 0u) != 0ull)))
                 break;
-            w.postponed_visits<kStats>(held, halted, st);
+#pragma unroll
+            for (int u = 0; u < pmd::Walker::kPostponedSteps; ++u) {
+                if (w.i < w.n && !halted) {  // the box visits of Walker::walk_postponed
+                    const uint4 q = w.nodes[w.i];
+                    if (kStats) st.boxes++;
+                    const bool leaf = (q.w >> 31) != 0u, hit = w.box_hit(q);
+                    const bool leaf_hit = hit && leaf;
+                    halted = leaf_hit && held != 0u;
+                    held = (leaf_hit && held == 0u) ? q.w : held;
+                    w.i = halted ? w.i : ((hit || leaf) ? w.i + 1 : q.w);
+                }
+            }
         }
         if (held != 0u) w.leaf_tris<kStats>(bvh.tris, held, st);
         held = 0u;
@@ -341,8 +352,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const 
 }
 
 // Two batches in one launch: the first blocksA workgroups walk batch A in
-// the order of perm (postponed leaf tests, one ray per lane or, with
-// sliceA > 0, one slice of sliceA rays per wavefront); the rest take batch B, an image
+// the order of perm (postponed leaf tests); the rest take batch B, an image
 // tile_w wide, one 8x8 pixel tile per wavefront, as packets.  The dispatcher
 // hands out B's workgroups once all of A's are running, so B fills the
 // device as A's last wavefronts drain.
@@ -351,17 +361,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_perm_then_tiles(
     pmd::Bvh bvh, uint32_t blocksA, const float4 *__restrict__ raysA, const uint32_t *__restrict__ perm, uint32_t nA,
     int32_t *__restrict__ hitA, float *__restrict__ tA, int32_t setA, uint32_t *__restrict__ countersA, uint32_t late,
     const float4 *__restrict__ raysB, int64_t nB, int32_t *__restrict__ hitB, float *__restrict__ tB, int32_t setB,
-    uint32_t *__restrict__ countersB, uint32_t tile_w, uint32_t sliceA) {
+    uint32_t *__restrict__ countersB, uint32_t tile_w) {
     if (blockIdx.x < blocksA) {
         const uint64_t lane = (uint64_t)pmd::xcd_block(blockIdx.x, blocksA) * blockDim.x + threadIdx.x;
-        if (sliceA == 0u) {
-            trace_slot<kStats, kWalkPostponed, true>(bvh, raysA, perm, lane, nA, hitA, tA, setA, countersA, late, 0u);
-        } else {
-            const uint64_t begin = (lane >> 6) * sliceA;
-            if (begin >= nA) return;
-            const uint32_t end = (uint32_t)(begin + sliceA < nA ? begin + sliceA : nA);
-            walk_slice<kStats>(bvh, raysA, perm, (uint32_t)begin, end, hitA, tA, setA, countersA, late);
-        }
+        trace_slot<kStats, kWalkPostponed, true>(bvh, raysA, perm, lane, nA, hitA, tA, setA, countersA, late, 0u);
     } else {
         const uint64_t lane =
             (uint64_t)pmd::xcd_block(blockIdx.x - blocksA, gridDim.x - blocksA) * blockDim.x + threadIdx.x;
@@ -691,14 +694,7 @@ static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs
     if (rc) return rc;
     const pmd::Bvh bvh = make_device_bvh(b);
     const uint32_t nA = (uint32_t)A.n;
-    uint32_t sliceA = 0;  // 0: one ray per lane
-    uint64_t lanesA = nA;
-    if (A.kernel == PM_TRACE_SLICES) {
-        rc = slice_rays(b->device, A.n, A.slice, sliceA);
-        if (rc) return rc;
-        lanesA = ((uint64_t)nA + sliceA - 1) / sliceA * 64;
-    }
-    const uint64_t blocksA = (lanesA + block - 1) / block;
+    const uint64_t blocksA = ((uint64_t)nA + block - 1) / block;
     const int64_t tiles = (((int64_t)B.tile_w + 7) / 8) * ((B.n / B.tile_w + 7) / 8);
     const uint64_t blocksB = ((uint64_t)tiles * 64 + block - 1) / block;
     if (blocksA + blocksB > 0x7fffffffull) return set_error("too many rays for one launch"), PM_ERR_ARG;
@@ -706,7 +702,7 @@ static int launch_perm_then_tiles(pm_bvh *b, const TraceArgs &A, const TraceArgs
                        dim3((uint32_t)(blocksA + blocksB)), dim3(block), 0, s, bvh, (uint32_t)blocksA,
                        (const float4 *)A.rays, (const uint32_t *)sc.perm, nA, A.hit, A.t, A.link_set, A.counters,
                        (uint32_t)A.refill, (const float4 *)B.rays, B.n, B.hit, B.t, B.link_set, B.counters,
-                       (uint32_t)B.tile_w, sliceA);
+                       (uint32_t)B.tile_w);
     PM_HIP(hipGetLastError());
     return PM_OK;
 }
@@ -718,8 +714,7 @@ int launch_trace_multi(pm_bvh *b, const TraceArgs *batches, int32_t n_batches, h
         for (int k = 0; k < 2; ++k) {
             const TraceArgs &A = batches[k], &B = batches[1 - k];
             const int blk = A.block ? A.block : kDefaultWalkBlock;
-            if (A.reorder != 0 && (A.kernel == PM_TRACE_POSTPONED || A.kernel == PM_TRACE_SLICES) && A.n > 0 &&
-                B.kernel == PM_TRACE_PACKET &&
+            if (A.reorder != 0 && A.kernel == PM_TRACE_POSTPONED && A.n > 0 && B.kernel == PM_TRACE_PACKET &&
                 B.tile_w > 0 && B.reorder == 0 && B.n > 0 && (B.block ? B.block : kDefaultWalkBlock) == blk &&
                 (A.counters == nullptr) == (B.counters == nullptr))
                 return launch_perm_then_tiles(b, A, B, blk, s);

@@ -128,11 +128,11 @@ def test_slice_kernel_agrees(torch_cuda, oracle_lib, late, reorder, block, slice
     assert np.all(c[:, 0] >= 1) and np.all(c[:, 1] >= (h >= 0))
 
 
-def test_fused_slices_and_packets_equal_single_calls(torch_cuda, oracle_lib):
+def test_slices_and_packets_in_one_multi_call_equal_single_calls(torch_cuda, oracle_lib):
     """Two batches, the bucketed slice walk and packets over image tiles, in
-    one fused launch: the same results as two single calls and as brute
-    force (automatic and explicit slice sizes)."""
-    _log("case: fused slices + packets, soup 2^14")
+    one pm_trace_rays_multi call: the same results as two single calls and
+    as brute force (automatic and explicit slice sizes)."""
+    _log("case: multi call slices + packets, soup 2^14")
     sc = scenes.soup_scene(1 << 14, 4)
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     cam = scenes.pinhole_rays(scenes.Camera(pos=(0.5, 0.5, -1.5), look=(0.5, 0.5, 0.5), up=(0, 1, 0),
