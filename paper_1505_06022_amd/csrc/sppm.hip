@@ -260,25 +260,41 @@ __global__ void k_adj_begin(unsigned long long *__restrict__ adj_max, unsigned l
     if (threadIdx.x < 2) adj_max[threadIdx.x] = 0ull;
 }
 
+// Maximum of v over the workgroup (non-negative doubles compare as their bit
+// patterns): one atomic per workgroup.
+__device__ __forceinline__ void block_max_atomic(unsigned long long v, unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long wave_max[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) v = wave_max[w] > v ? wave_max[w] : v;
+        if (v) atomicMax(out, v);
+    }
+}
+
+// Workgroups of the two maxima below: a grid-stride loop each, so that at
+// most this many same-address atomics are issued.
+constexpr uint32_t kAdjMaxBlocks = 256;
+
 // max over valid hit points of |G_h| wk_h (non-negative doubles order like
 // their bit patterns, so the maximum is an integer maximum)
 __global__ __launch_bounds__(kBlock) void k_adj_gmax(SppmDev d, const double *__restrict__ R2k,
                                                      const float *__restrict__ g, double K,
                                                      unsigned long long *__restrict__ adj_max) {
-    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     unsigned long long v = 0ull;
-    if (p < d.P) {
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < d.P; p += (int64_t)gridDim.x * kBlock) {
         float4 hn = d.hp_nrm[p];
         if (__float_as_int(hn.w) >= 0) {
             double a = fabs(adj_G(g, p, R2k[p], K)) * (double)d.hp_pos[p].w;
-            v = (unsigned long long)__double_as_longlong(a);
+            unsigned long long b = (unsigned long long)__double_as_longlong(a);
+            v = b > v ? b : v;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long o = __shfl_xor(v, off);
-        v = o > v ? o : v;
-    }
-    if ((threadIdx.x & 63) == 0 && v) atomicMax(&adj_max[0], v);
+    block_max_atomic(v, &adj_max[0]);
 }
 
 // max flux over the stored photons
@@ -289,11 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_phimax(SppmDev d, unsigned long 
         unsigned long long b = (unsigned long long)__double_as_longlong((double)d.store[2 * (size_t)i].w);
         v = b > v ? b : v;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long o = __shfl_xor(v, off);
-        v = o > v ? o : v;
-    }
-    if ((threadIdx.x & 63) == 0 && v) atomicMax(&adj_max[1], v);
+    block_max_atomic(v, &adj_max[1]);
 }
 
 // Scale 2^(39 - e) with 2^e above the product of the two maxima, so
@@ -451,7 +463,8 @@ void sppm_free(pm_sppm *s) {
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->mat_type, s->mat_f, s->emit_pos, s->emit_cdf, s->N, s->R2, s->tau, s->D, s->hp_pos,
                     s->hp_nrm, s->store, s->store2, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
-                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->grad_mat,
+                    s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->adj_tab2,
+                    s->mat_tab2, s->grad_mat,
                     s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->stats, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -655,7 +668,11 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         PM_HIPF(hipMalloc(&s->mat_tab, sizeof(uint16_t) * (size_t)p->n_photons * p->max_photon_bounces));
         PM_HIPF(hipMalloc(&s->grad_mat, sizeof(double) * (nm + 1)));
         PM_HIPF(hipMalloc(&s->adj_wide, sizeof(unsigned long long) * 2 * nm));
-        PM_HIPF(hipMalloc(&s->adj_max, sizeof(unsigned long long) * 2));
+        PM_HIPF(hipMalloc(&s->adj_max, sizeof(unsigned long long) * 4));
+        if (s->store2) {  // the adjoint overlaps consecutive iterations like the forward
+            PM_HIPF(hipMalloc(&s->adj_tab2, sizeof(long long) * (size_t)p->n_photons * p->max_photon_bounces));
+            PM_HIPF(hipMalloc(&s->mat_tab2, sizeof(uint16_t) * (size_t)p->n_photons * p->max_photon_bounces));
+        }
         PM_HIPF(hipMalloc(&s->adj_scale, sizeof(double)));
         PM_HIPF(hipMalloc(&s->le_part, sizeof(double) * blocks_for(s->P)));
     }
@@ -1002,6 +1019,79 @@ int sppm_status(pm_sppm *s, hipStream_t st) {
     return PM_OK;
 }
 
+// The adjoint's replay with consecutive iterations overlapped, as in the
+// forward iteration: the replayed photon pass of k + 1 (with its flux
+// maximum) runs on the photon stream beside the grid, gather and path sums of
+// k, into the other photon store, (path, bounce) tables and maxima; the
+// replayed eye pass of k, R_max and the |G| wk maximum run on the side stream
+// once iteration k - 1 is done with the hit points.  Every sum is an integer
+// sum, so the gradient equals the serial schedule's bit for bit.
+static int adjoint_overlapped(pm_sppm *s, const float *g, hipStream_t st) {
+    const uint32_t T = 1u << s->table_bits;
+    const uint32_t np = (uint32_t)s->prm.n_photons;
+    const int32_t mb = s->prm.max_photon_bounces;
+    const uint32_t ph_blocks = std::min<uint32_t>(blocks_for(s->cap), 256u * 64u);
+    const uint32_t K = (uint32_t)s->K;
+    const double Kd = (double)s->K;
+    auto mat_of = [&](uint32_t k) { return (k & 1u) ? s->mat_tab2 : s->mat_tab; };
+    auto tab_of = [&](uint32_t k) { return (k & 1u) ? s->adj_tab2 : s->adj_tab; };
+    auto max_of = [&](uint32_t k) { return s->adj_max + 2 * (k & 1u); };
+    auto replay = [&](uint32_t k) -> int {  // on the photon stream
+        const SppmDev dk = iteration_view(s, k);
+        hipLaunchKernelGGL(k_photon_begin, dim3(1), dim3(64), 0, s->phs, dk);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s->phs, (uint32_t *)(max_of(k) + 1), 2u, 0u);
+        hipLaunchKernelGGL(k_photon_regen_rec, dim3(s->regen_grid_rec), dim3(kBlock), 0, s->phs, dk, k, mat_of(k),
+                           tab_of(k));
+        hipLaunchKernelGGL(k_adj_phimax, dim3(std::min<uint32_t>(ph_blocks, kAdjMaxBlocks)), dim3(kBlock), 0, s->phs,
+                           dk, max_of(k));
+        PM_HIP(hipGetLastError());
+        PM_HIP(hipEventRecord(s->ev_ph[k & 1u], s->phs));
+        return PM_OK;
+    };
+    PM_HIP(hipEventRecord(s->ev_fork, st));
+    PM_HIP(hipStreamWaitEvent(s->phs, s->ev_fork, 0));
+    int rc = replay(0);
+    if (rc) return rc;
+    for (uint32_t k = 0; k < K; ++k) {
+        const SppmDev dk = iteration_view(s, k);
+        const double *R2k = s->R2_hist + (size_t)k * s->P;
+        if (k + 1 < K) {
+            // the replay of k + 1 reuses the store and tables that iteration k - 1 read
+            if (k >= 1) PM_HIP(hipStreamWaitEvent(s->phs, s->ev_scat[(k + 1u) & 1u], 0));
+            if ((rc = replay(k + 1))) return rc;
+        }
+        PM_HIP(hipEventRecord(s->ev_fork, st));
+        PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+        hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, s->side, dk);
+        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 0);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, dk, R2k);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s->side, (uint32_t *)max_of(k), 2u, 0u);
+        hipLaunchKernelGGL(k_adj_gmax, dim3(std::min<uint32_t>(blocks_for(s->P), kAdjMaxBlocks)), dim3(kBlock), 0,
+                           s->side, dk, R2k, g, Kd, max_of(k));
+        PM_HIP(hipEventRecord(s->ev_join, s->side));
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(4 * s->n_mat)), dim3(kBlock), 0, st, (uint32_t *)s->adj_wide,
+                           (uint32_t)(4 * s->n_mat), 0u);
+        PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+        PM_HIP(hipStreamWaitEvent(st, s->ev_ph[k & 1u], 0));
+        hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(64), 0, st, (const unsigned long long *)max_of(k), s->adj_scale);
+        hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, dk, s->cell_count);
+        launch_bucket_scan(s->cell_count, s->cell_start, s->cell_fill, s->bsum, T, st);
+        hipLaunchKernelGGL(k_scatter, dim3(ph_blocks), dim3(kBlock), 0, st, dk, (const uint32_t *)s->cell_start,
+                           s->sorted);
+        hipLaunchKernelGGL(k_gather_adj, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk, R2k,
+                           (const uint32_t *)s->cell_start, (const float4 *)s->sorted, g, Kd,
+                           (const double *)s->adj_scale, tab_of(k), s->n_mat, s->adj_wide);
+        hipLaunchKernelGGL(k_path_adj, dim3(blocks_for(np)), dim3(kBlock), 0, st, (const uint16_t *)mat_of(k),
+                           (const long long *)tab_of(k), np, mb, s->n_mat, s->adj_wide);
+        PM_HIP(hipEventRecord(s->ev_scat[k & 1u], st));
+        hipLaunchKernelGGL(k_adj_fold, dim3(1), dim3(kMaxAdjMat), 0, st, (const unsigned long long *)s->adj_wide,
+                           s->n_mat, (const double *)s->adj_scale, dk.sc.mat_rho, s->grad_mat);
+        PM_HIP(hipGetLastError());
+    }
+    return PM_OK;
+}
+
 int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par, double *grad, hipStream_t st) {
     if (!s || !g || !grad || n_par < 0 || (n_par > 0 && !pmat))
         return set_error("invalid handle, gradient or parameter pointers"), PM_ERR_ARG;
@@ -1024,7 +1114,11 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
     for (int32_t i = 0; i < n_par; ++i) pms.m[i] = (uint8_t)pmat[i];
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(s->n_mat + 1)), dim3(kBlock), 0, st, s->grad_mat,
                        (int64_t)s->n_mat + 1);
-    for (int32_t k = 0; k < s->K; ++k) {
+    if (s->adj_tab2) {
+        int rc = adjoint_overlapped(s, g, st);
+        if (rc) return rc;
+    }
+    for (int32_t k = 0; k < (s->adj_tab2 ? 0 : s->K); ++k) {
         const double *R2k = s->R2_hist + (size_t)k * s->P;
         hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_adj_begin, dim3(1), dim3(kBlock), 0, st, s->adj_max, s->adj_wide, s->n_mat);
@@ -1034,11 +1128,12 @@ int sppm_adjoint(pm_sppm *s, const float *g, const int32_t *pmat, int32_t n_par,
         PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
         hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, (uint32_t)k, 0);
         hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, d, R2k);
-        hipLaunchKernelGGL(k_adj_gmax, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, d, R2k, g, K, s->adj_max);
+        hipLaunchKernelGGL(k_adj_gmax, dim3(std::min<uint32_t>(blocks_for(s->P), kAdjMaxBlocks)), dim3(kBlock), 0,
+                           s->side, d, R2k, g, K, s->adj_max);
         PM_HIP(hipEventRecord(s->ev_join, s->side));
         hipLaunchKernelGGL(k_photon_regen_rec, dim3(s->regen_grid_rec), dim3(kBlock), 0, st, d, (uint32_t)k,
                            s->mat_tab, s->adj_tab);
-        hipLaunchKernelGGL(k_adj_phimax, dim3(std::min<uint32_t>(ph_blocks, 1024u)), dim3(kBlock), 0, st, d,
+        hipLaunchKernelGGL(k_adj_phimax, dim3(std::min<uint32_t>(ph_blocks, kAdjMaxBlocks)), dim3(kBlock), 0, st, d,
                            s->adj_max);
         PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(64), 0, st, (const unsigned long long *)s->adj_max,

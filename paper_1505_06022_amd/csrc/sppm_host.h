@@ -49,9 +49,13 @@ struct pm_sppm {
     double *R2_hist = nullptr;    // [rec_iters][P] radius used in each iteration
     long long *adj_tab = nullptr;  // [n_photons][max_bounces] photon sensitivities (fixed point, see adj_*)
     uint16_t *mat_tab = nullptr;   // [n_photons][max_bounces] stored-photon materials
+    // second copies for odd iterations when the adjoint overlaps iterations (with store2)
+    long long *adj_tab2 = nullptr;
+    uint16_t *mat_tab2 = nullptr;
     double *grad_mat = nullptr;    // [n_mat + 1]; last entry: sum g L
     unsigned long long *adj_wide = nullptr;  // [2][n_mat] per-material integer sums of one iteration (lo | hi)
-    unsigned long long *adj_max = nullptr;   // [2] max |G| wk over hit points, max flux over photons (double bits)
+    unsigned long long *adj_max = nullptr;   // [2][2] per iteration parity: max |G| wk over hit points, max
+                                             // flux over photons (double bits)
     double *adj_scale = nullptr;             // [1] fixed-point scale of the current iteration
     double *le_part = nullptr;               // [blocks over pixels] partial sums of g L
     uint64_t scene_hash = 0;      // fingerprint of the scene description (checkpoint matching)

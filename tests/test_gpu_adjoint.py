@@ -176,6 +176,32 @@ def test_adjoint_is_bit_reproducible(torch_cuda):
     assert np.count_nonzero(out[0]) >= len(out[0]) - 2
 
 
+@pytest.mark.parametrize("K", [1, 2, 5])
+def test_overlapped_adjoint_equals_serial(torch_cuda, K):
+    """The adjoint overlaps the replayed photon pass of iteration k + 1 with
+    the grid, gather and path sums of k (two stores, tables and maxima by
+    iteration parity).  A handle that times its stages (PM_PROFILE_TIME) has
+    one store and runs the adjoint serially: the gradients are the same bits,
+    for one, two (each parity once) and an odd number of iterations, also
+    on a second call of the overlapped schedule."""
+    _log(f"case: overlapped vs serial adjoint, K={K}")
+    torch = torch_cuda
+    sc = scenes.procedural_scene(width=97, height=61, hf_cells=20, sphere_level=2, glass_level=3, seed=3)
+    P = sc.camera.width * sc.camera.height
+    g = torch.from_numpy(np.random.default_rng(10).standard_normal(P).astype(np.float32)).cuda()
+    grads = []
+    for profile in (0, api.PROFILE_TIME):
+        s = api.Sppm(sc, api.sppm_params(1 << 14, r0=0.02, seed=5, record_iterations=K, profile=profile))
+        s.iterate(K)
+        grads.append(s.adjoint(g, sc.albedo_params).cpu().numpy())
+        if profile == 0:
+            grads.append(s.adjoint(g, sc.albedo_params).cpu().numpy())
+        s.destroy()
+    assert np.count_nonzero(grads[0]) > 3
+    for o in grads[1:]:
+        assert np.array_equal(o, grads[0])
+
+
 def _many_materials(sc, n_mat=256):
     """The box scene with its materials moved to the top of a 256-entry table:
     the light to 0, the seven diffuse materials to 249..255 (so materials 254
