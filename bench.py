@@ -64,7 +64,7 @@ KERNEL_VARIANTS = (
     ("postponed_late16_reorder2_block64", dict(kernel=4, refill=16, reorder=2, block=64)),
     ("postponed_late16_reorder1_block128", dict(kernel=4, refill=16, reorder=1, block=128)),
     ("slices_late32_reorder1_block64", dict(kernel=7, refill=32, reorder=1, block=64)),
-    ("slices256_late32_reorder1_block64", dict(kernel=7, refill=32, reorder=1, block=64, slice=256)))
+    ("slices256_late32_reorder1_block64", dict(kernel=7, refill=32, reorder=1, block=64, slice_rays=256)))
 
 IMAGE_WIDTH = 1920   # of the camera batch
 

@@ -271,8 +271,9 @@ def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32
 
 
 def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=None, kernel: int = 0, refill: int = 0,
-               reorder: int = 0, block: int = 0, tile_width: int = 0, slice: int = 0, stream=None):
-    """Closest hit of each ray.  rays: float32 cuda tensor [n, 8]; returns (hit int32 [n], t float32 [n])."""
+               reorder: int = 0, block: int = 0, tile_width: int = 0, slice_rays: int = 0, stream=None):
+    """Closest hit of each ray.  rays: float32 cuda tensor [n, 8]; returns (hit int32 [n], t float32 [n]).
+    The options are pm_trace_opts' fields (slice_rays is its field slice)."""
     import torch
     assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
     n = rays.shape[0]
@@ -281,10 +282,10 @@ def trace_rays(bvh: Bvh, rays, hit=None, t=None, link_set: int = -1, counters=No
     if t is None:
         t = torch.empty(n, dtype=torch.float32, device=rays.device)
     if link_set == -1 and counters is None and kernel == 0 and refill == 0 and not reorder and not block \
-            and not tile_width and not slice:
+            and not tile_width and not slice_rays:
         _check(lib().pm_trace_rays(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), _stream(stream)))
     else:
-        o = _trace_opts(link_set, counters, kernel, refill, reorder, block, tile_width, slice)
+        o = _trace_opts(link_set, counters, kernel, refill, reorder, block, tile_width, slice_rays)
         _check(lib().pm_trace_rays_ex(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t
 
@@ -293,23 +294,23 @@ NOALLOC_MAX_RAYS = 1 << 22
 
 
 def trace_rays_noalloc(bvh: Bvh, rays, hit, t, link_set: int = -1, counters=None, kernel: int = 0, refill: int = 0,
-                       reorder: int = 1, block: int = 0, slice: int = 0, stream=None):
+                       reorder: int = 1, block: int = 0, slice_rays: int = 0, stream=None):
     """The bucketed trace on the library's static scratch (pm_trace_rays_noalloc):
     the caller passes the outputs hit (int32 cuda [n]) and t (float32 cuda [n])."""
     import torch
     assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 8
     n = rays.shape[0]
     assert hit.dtype == torch.int32 and t.dtype == torch.float32 and hit.numel() >= n and t.numel() >= n
-    o = _trace_opts(link_set, counters, kernel, refill, reorder, block, 0, slice)
+    o = _trace_opts(link_set, counters, kernel, refill, reorder, block, 0, slice_rays)
     _check(lib().pm_trace_rays_noalloc(bvh.h, _ptr(rays), n, _ptr(hit), _ptr(t), C.byref(o), _stream(stream)))
     return hit, t
 
 
 def _trace_opts(link_set=-1, counters=None, kernel=0, refill=0, reorder=0, block=0, tile_width=0,
-                slice=0) -> TraceOpts:
+                slice_rays=0) -> TraceOpts:
     o = TraceOpts()
     o.size, o.link_set, o.kernel, o.refill = C.sizeof(TraceOpts), link_set, kernel, refill
-    o.reorder, o.block, o.tile_width, o.slice = int(reorder), int(block), int(tile_width), int(slice)
+    o.reorder, o.block, o.tile_width, o.slice = int(reorder), int(block), int(tile_width), int(slice_rays)
     o.counters = None if counters is None else counters.data_ptr()
     return o
 

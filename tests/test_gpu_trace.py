@@ -118,7 +118,7 @@ def test_slice_kernel_agrees(torch_cuda, oracle_lib, late, reorder, block, slice
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     rays = np.concatenate([scenes.random_rays(7001, 11), scenes.pinhole_rays(sc.camera)])
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
-    kw = dict(kernel=api.TRACE_SLICES, refill=late, reorder=reorder, block=block, slice=slice_)
+    kw = dict(kernel=api.TRACE_SLICES, refill=late, reorder=reorder, block=block, slice_rays=slice_)
     h, t = _gpu_trace(torch_cuda, bvh, rays, **kw)
     _compare(h, t, h_ref, t_ref)
     cnt = torch_cuda.zeros((len(rays), 2), dtype=torch_cuda.int32, device="cuda")
@@ -142,7 +142,7 @@ def test_slices_and_packets_in_one_multi_call_equal_single_calls(torch_cuda, ora
     kc = dict(kernel=api.TRACE_PACKET, block=64, tile_width=96)
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, inc)
     for slice_ in (0, 130):
-        ki = dict(kernel=api.TRACE_SLICES, refill=32, reorder=1, block=64, slice=slice_)
+        ki = dict(kernel=api.TRACE_SLICES, refill=32, reorder=1, block=64, slice_rays=slice_)
         single = [api.trace_rays(bvh, rc, **kc), api.trace_rays(bvh, ri, **ki)]
         two = api.trace_rays_multi(bvh, [dict(rays=rc, **kc), dict(rays=ri, **ki)])
         for (h, t), (hr, tr) in zip(two, single):
@@ -171,6 +171,30 @@ def test_grazing_and_far_origin_rays(torch_cuda, oracle_lib, builder, kind):
     for kernel in (1, 2, 3, 4, 5, 6):
         h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel)
         _compare(h, t, h_ref, t_ref)
+
+
+@pytest.mark.parametrize("builder", [api.BUILD_HOST_SAH, api.BUILD_GPU_LBVH])
+def test_closed_mesh_watertight_on_device(torch_cuda, oracle_lib, builder):
+    """Rays from inside a closed icosphere (level 3, 1,280 triangles) aimed
+    exactly at its shared vertices and at points of its shared edges: every
+    ray hits, with every traversal kernel, and equals brute force."""
+    _log(f"case: watertight icosphere, builder={builder}")
+    rng = np.random.default_rng(12)
+    verts = (scenes._icosphere(3) * 2.5 + np.array([0.3, -1.2, 0.8])).astype(np.float32)
+    pts = np.unique(verts.reshape(-1, 3), axis=0)
+    edges = [f[i].astype(np.float64) + lam * (f[(i + 1) % 3].astype(np.float64) - f[i].astype(np.float64))
+             for f in verts for i in range(3) for lam in (0.5, rng.random())]
+    targets = np.concatenate([pts, np.asarray(edges)]).astype(np.float32)
+    o = (np.array([0.3, -1.2, 0.8]) + 1.2 * rng.uniform(-1, 1, (len(targets), 3)) / np.sqrt(3)).astype(np.float32)
+    rays = np.zeros((len(targets), 8), np.float32)
+    rays[:, 0:3], rays[:, 4:7], rays[:, 7] = o, targets - o, np.inf
+    h_ref, t_ref = oracle_lib.trace_brute_force(verts, rays)
+    assert (h_ref >= 0).all()
+    bvh = api.build_bvh(verts, builder=builder)
+    for kernel in (1, 2, 3, 4, 5, 6, 7):
+        h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel)
+        _compare(h, t, h_ref, t_ref)
+        assert (h >= 0).all(), kernel
 
 
 @pytest.mark.parametrize("kernel,block", [(1, 0), (3, 64), (4, 128), (6, 0), (6, 64)])
@@ -258,7 +282,7 @@ def test_trace_option_errors(torch_cuda):
     bvh = api.build_bvh(sc.verts, sc.tri_mat)
     r = torch_cuda.from_numpy(scenes.random_rays(100, 1)).cuda()
     for kw in (dict(block=100), dict(block=512), dict(kernel=8), dict(kernel=-1), dict(kernel=4, refill=64),
-               dict(kernel=7, refill=64), dict(kernel=7, slice=-1), dict(kernel=7, slice=(1 << 24) + 1),
+               dict(kernel=7, refill=64), dict(kernel=7, slice_rays=-1), dict(kernel=7, slice_rays=(1 << 24) + 1),
                dict(tile_width=10, kernel=7), dict(reorder=3), dict(tile_width=7), dict(tile_width=-1),
                dict(tile_width=10, reorder=1), dict(tile_width=10, kernel=2), dict(link_set=6)):
         with pytest.raises(api.PMError) as e:
