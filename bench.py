@@ -143,6 +143,10 @@ def _parse():
                     help="traversal options of the incoherent batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run the library's 1 GiB stream copy (calibrates HBM byte counters)")
+    ap.add_argument("--split-alpha", type=float, default=None,
+                    help="spatial-split threshold of the traversal BVH (default: the soup's, 1e-4; 0 = none)")
+    ap.add_argument("--trav-cost", type=float, default=None,
+                    help="SAH node-visit cost of the traversal BVH (default: the soup's, 2)")
     return ap.parse_args()
 
 
@@ -182,9 +186,25 @@ def _host_info() -> dict:
             "cpu_model": model}
 
 
+def _time_multi(torch, api, bvh, multi, reps=20):
+    """Mean ms of one pm_trace_rays_multi call over `reps` calls after a short warm-up."""
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        api.trace_rays_multi(bvh, multi)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record(stream)
+    for _ in range(reps):
+        api.trace_rays_multi(bvh, multi)
+    e[1].record(stream)
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]) / reps
+
+
 def traversal_bench(args, torch, api, scenes):
     sc, coh, inc = scenes.soup_workload()
-    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    split_alpha = scenes.SOUP_SPLIT_ALPHA if args.split_alpha is None else args.split_alpha
+    trav_cost = scenes.SOUP_TRAV_COST if args.trav_cost is None else args.trav_cost
+    bvh = api.build_bvh(sc.verts, sc.tri_mat, split_alpha=split_alpha, trav_cost=trav_cost)
     info = bvh.info()
     dev = "cuda"
     rc = torch.from_numpy(coh).to(dev)
@@ -302,30 +322,23 @@ def traversal_bench(args, torch, api, scenes):
                 "incoherent_mrays_s": round(len(ri) / ms[1] / 1e3, 1),
                 "mrays_s": round((len(rc) + len(ri)) / ms.sum() / 1e3, 1)}
         lb.destroy()
-    # SAH node-visit cost (relative to a triangle test): tree size vs traversal rate
-    sah = {}
     if not args.no_variants:
-        for tc in (2.0, 4.0):
-            bv = api.build_bvh(sc.verts, sc.tri_mat, trav_cost=tc)
+        # spatial splits and node-visit cost: BVH size, build time and the timed call's rate
+        spl = {}
+        for a, tc in ((0.0, 1.0), (0.0, 2.0), (1e-3, 1.0), (1e-4, 1.0), (1e-3, 1.5)):
+            if (a, tc) == (split_alpha, trav_cost):
+                continue
+            t_b = time.perf_counter()
+            bv = api.build_bvh(sc.verts, sc.tri_mat, split_alpha=a, trav_cost=tc)
+            wall_ms = (time.perf_counter() - t_b) * 1e3
             inf = bv.info()
-            res = {"n_nodes": inf["n_nodes"], "device_mb": round(inf["device_bytes"] / 1e6, 1)}
-            for name, kw in (("per_ray", dict(kernel=1)), ("paired", dict(kernel=3)),
-                             ("paired_reorder1", dict(kernel=3, reorder=1))):
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(batches))]
-                ms = np.zeros(len(batches))
-                for rep in range(4):
-                    for b, (r, (h, t)) in enumerate(zip(batches, outs)):
-                        e[2 * b].record(stream)
-                        api.trace_rays(bv, r, h, t, **kw)
-                        e[2 * b + 1].record(stream)
-                    torch.cuda.synchronize()
-                    if rep:
-                        ms += [e[2 * b].elapsed_time(e[2 * b + 1]) for b in range(len(batches))]
-                ms /= 3
-                res[name] = [round(len(rc) / ms[0] / 1e3, 1), round(len(ri) / ms[1] / 1e3, 1)]
-            sah[f"trav_cost_{tc:g}"] = res
+            ms = _time_multi(torch, api, bv, multi)
+            spl[f"split_alpha_{a:g}_trav_cost_{tc:g}"] = {"n_refs": inf["n_refs"], "n_nodes": inf["n_nodes"],
+                                         "device_mb": round(inf["device_bytes"] / 1e6, 1),
+                                         "sah_cost": round(inf["sah_cost"], 1), "build_ms_wall": round(wall_ms, 1),
+                                         "step_ms": round(ms, 4), "mrays_s": round(n_rays / ms / 1e3, 1)}
             bv.destroy()
-        variants["sah_trav_cost"] = sah
+        variants["spatial_splits"] = spl
     avg_launch_ms = kern_ms.mean()
     per_launch_bytes = alg_bytes   # one call traces both batches
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
@@ -333,7 +346,7 @@ def traversal_bench(args, torch, api, scenes):
     return dict(
         n_rays=n_rays, step_ms=step_ms, kern_ms=kern_ms, batch_ms=batch_ms, info=info, per_batch=per_batch,
         achieved=achieved, per_launch_bytes=per_launch_bytes, hit_frac=hit_frac, variants=variants, tbvh=tbvh,
-        lbvh=lbvh, prewarm_steps=prewarm_steps,
+        lbvh=lbvh, prewarm_steps=prewarm_steps, split_alpha=split_alpha, trav_cost=trav_cost,
         coherent_mrays=len(rc) / (batch_ms[0] * 1e-3) / 1e6,
         incoherent_mrays=len(ri) / (batch_ms[1] * 1e-3) / 1e6,
         scene=sc, rays=(coh, inc),
@@ -780,7 +793,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "traversal: 2^20 random triangles (lognormal(-5,0.5) edges), SAH 32 bins leaf<=4, "
+        "config": {"workload": "traversal: 2^20 random triangles (lognormal(-5,0.5) edges), SAH 32 bins leaf<=4 "
+                               f"node cost {tb['trav_cost']:g}, spatial splits alpha={tb['split_alpha']:g}, "
                                "1920x1080 coherent + 2^21 incoherent rays",
                    "n_rays": tb["n_rays"], "n_tri": 1 << 20, "parallelism": "none",
                    "trace_options": {"coherent": [args.coherent, dict(KERNEL_VARIANTS)[args.coherent]],
@@ -789,7 +803,9 @@ def main():
         "incoherent_mrays_s": round(tb["incoherent_mrays"], 2),
         "kernel_mrays_s": round(tb["n_rays"] / (tb["kern_ms"].mean() * 1e-3) / 1e6, 2),
         "one_after_another_mrays_s": round(tb["n_rays"] / (tb["batch_ms"].sum() * 1e-3) / 1e6, 2),
-        "bvh": {k: tb["info"][k] for k in ("n_nodes", "n_leaves", "depth", "sah_cost", "device_bytes", "build_ms")},
+        "bvh": dict({k: tb["info"][k] for k in ("n_tri", "n_refs", "n_nodes", "n_leaves", "depth", "sah_cost",
+                                                 "device_bytes", "build_ms")}, split_alpha=tb["split_alpha"],
+                    trav_cost=tb["trav_cost"]),
         "kernel_variants": tb["variants"],
         "gpu_lbvh": tb["lbvh"],
         "tbvh_ablation": ({"single_link_set": tb["tbvh"],

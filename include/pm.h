@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PM_ABI_VERSION 1
+#define PM_ABI_VERSION 2
 
 #if defined(__GNUC__)
 #define PM_API __attribute__((visibility("default")))
@@ -75,6 +75,13 @@ typedef struct {
     float trav_cost;   /* SAH cost of a node visit relative to a triangle
                           test (0 = default 1; range (0, 64]) */
     int32_t builder;   /* PM_BUILD_*: pm_build_bvh only */
+    float split_alpha; /* host SAH build only: spatial splits (Stich et al.
+                          2009) are tried at a node when its best object
+                          split leaves children whose boxes overlap by more
+                          than split_alpha x the scene box's surface area;
+                          a triangle may then be referenced by several
+                          leaves (n_refs > n_tri).  0 = none (default);
+                          range [0, 1] */
 } pm_bvh_opts;
 
 /* BVH builders.  HOST_SAH: binned SAH on the host threads, then threading and
@@ -88,12 +95,14 @@ enum { PM_BUILD_HOST_SAH = 0, PM_BUILD_GPU_LBVH = 1 };
 typedef struct {
     uint32_t size;        /* sizeof(pm_bvh_info) */
     int64_t n_tri;
+    int64_t n_refs;       /* triangle records in leaf order (n_tri without
+                             spatial splits; each triangle at least once) */
     int64_t n_nodes;      /* nodes of the binary tree (each stored once per link set) */
     int64_t n_leaves;
     int32_t depth;
     int32_t max_leaf;
     double sah_cost;      /* C_trav = C_isect = 1, normalised by the root area */
-    int64_t device_bytes; /* nodes (6 link sets x 16 B) + triangles (48 B) */
+    int64_t device_bytes; /* nodes (6 link sets x 16 B) + triangle records (48 B) */
     double build_ms;      /* host build + threading time */
     float grid_lo[3];     /* node boxes: coordinate = grid_lo + q * grid_step */
     float grid_step[3];
@@ -107,13 +116,15 @@ typedef struct {
  *   tri_mat    host, uint32 [n_tri] material ids (may be NULL: all 0)
  *   opts       may be NULL (defaults above)
  *   out        receives a library-owned handle; free with pm_bvh_destroy.
- * Errors: PM_ERR_ARG for n_tri < 1, n_tri >= 2^28, non-finite vertices or bad
- * options; PM_ERR_HIP / PM_ERR_NOMEM for device failures. */
+ * Errors: PM_ERR_ARG for n_tri < 1, n_tri >= 2^28, non-finite vertices, bad
+ * options, or spatial splits that make 2^28 or more triangle records;
+ * PM_ERR_HIP / PM_ERR_NOMEM for device failures. */
 PM_API int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
                  void *stream, pm_bvh **out);
 
 /* Host-only build (no device needed), for inspection and tests.  Two-phase:
- * call with nodes == tris == NULL to learn *n_nodes; then call again with
+ * call with nodes == tris == NULL to learn *n_nodes (and, with info,
+ * info->n_refs); then call again with
  *   nodes  host, [6][n_nodes][4] 32-bit words per link set s (0:+x 1:-x 2:+y
  *          3:-y 4:+z 5:-z), node i in that set's preorder: its padded box
  *          rounded outward to 16-bit grid coordinates, one word per axis
@@ -122,9 +133,10 @@ PM_API int pm_build_bvh(const float *tri_verts, const uint32_t *tri_mat, int64_t
  *          link word: an inner node stores its skip link (preorder index after
  *          its subtree, n_nodes at the end; its hit link is i + 1); a leaf has
  *          bit 31 set and first_tri << 3 | count (both of its links are i + 1)
- *   tris   host, [n_tri][12] 32-bit words in leaf order: v0.xyz, v1.xyz,
+ *   tris   host, [n_refs][12] 32-bit words in leaf order: v0.xyz, v1.xyz,
  *          v2.xyz (float bits, the vertices as given), original index,
- *          material, 0. */
+ *          material, 0.  n_refs = n_tri unless opts->split_alpha > 0.
+ * The build is deterministic: both calls give the same BVH. */
 PM_API int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n_tri, const pm_bvh_opts *opts,
                       int64_t *n_nodes, uint32_t *nodes, uint32_t *tris, pm_bvh_info *info);
 
@@ -132,7 +144,7 @@ PM_API int pm_bvh_destroy(pm_bvh *bvh);
 PM_API int pm_bvh_get_info(const pm_bvh *bvh, pm_bvh_info *info);
 
 /* Copy a device BVH to host memory, in the layout of pm_build_bvh_host
- * (nodes [6][n_nodes][4] words, tris [n_tri][12] words; either may be NULL).
+ * (nodes [6][n_nodes][4] words, tris [n_refs][12] words; either may be NULL).
  * Synchronises `stream`.  Errors: PM_ERR_ARG for a NULL bvh. */
 PM_API int pm_bvh_download(const pm_bvh *bvh, uint32_t *nodes, uint32_t *tris, void *stream);
 

@@ -34,14 +34,15 @@ class PMError(RuntimeError):
 
 class BvhOpts(C.Structure):
     _fields_ = [("size", C.c_uint32), ("bins", C.c_int32), ("max_leaf", C.c_int32), ("n_threads", C.c_int32),
-                ("trav_cost", C.c_float), ("builder", C.c_int32)]
+                ("trav_cost", C.c_float), ("builder", C.c_int32), ("split_alpha", C.c_float)]
 
 
 BUILD_HOST_SAH, BUILD_GPU_LBVH = 0, 1
 
 
 class BvhInfo(C.Structure):
-    _fields_ = [("size", C.c_uint32), ("n_tri", C.c_int64), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64),
+    _fields_ = [("size", C.c_uint32), ("n_tri", C.c_int64), ("n_refs", C.c_int64), ("n_nodes", C.c_int64),
+                ("n_leaves", C.c_int64),
                 ("depth", C.c_int32), ("max_leaf", C.c_int32), ("sah_cost", C.c_double),
                 ("device_bytes", C.c_int64), ("build_ms", C.c_double),
                 ("grid_lo", C.c_float * 3), ("grid_step", C.c_float * 3)]
@@ -182,10 +183,10 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _opts(bins, max_leaf, n_threads, trav_cost=0.0, builder=0):
+def _opts(bins, max_leaf, n_threads, trav_cost=0.0, builder=0, split_alpha=0.0):
     o = BvhOpts()
     o.size, o.bins, o.max_leaf, o.n_threads = C.sizeof(BvhOpts), bins, max_leaf, n_threads
-    o.trav_cost, o.builder = trav_cost, builder
+    o.trav_cost, o.builder, o.split_alpha = trav_cost, builder, split_alpha
     return o
 
 
@@ -220,10 +221,10 @@ class Bvh:
         return _info_dict(inf)
 
     def download(self, stream=None):
-        """(nodes uint32 [6, n_nodes, 4], tris uint32 [n_tri, 12]) copied from the device."""
-        n_nodes = self.info()["n_nodes"]
-        nodes = np.zeros((6, n_nodes, 4), np.uint32)
-        tris = np.zeros((self.n_tri, 12), np.uint32)
+        """(nodes uint32 [6, n_nodes, 4], tris uint32 [n_refs, 12]) copied from the device."""
+        inf = self.info()
+        nodes = np.zeros((6, inf["n_nodes"], 4), np.uint32)
+        tris = np.zeros((inf["n_refs"], 12), np.uint32)
         _check(lib().pm_bvh_download(self.h, _ptr(nodes), _ptr(tris), _stream(stream)))
         return nodes, tris
 
@@ -240,31 +241,32 @@ class Bvh:
 
 
 def build_bvh(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0,
-              trav_cost=0.0, builder=0, stream=None) -> Bvh:
-    """Build a device BVH: builder 0 = SAH on the host, 1 = linear BVH on the GPU."""
+              trav_cost=0.0, builder=0, split_alpha=0.0, stream=None) -> Bvh:
+    """Build a device BVH: builder 0 = SAH on the host (spatial splits with split_alpha > 0),
+    1 = linear BVH on the GPU."""
     v = np.ascontiguousarray(verts, np.float32)
     m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
     out = C.c_void_p()
-    o = _opts(bins, max_leaf, n_threads, trav_cost, builder)
+    o = _opts(bins, max_leaf, n_threads, trav_cost, builder, split_alpha)
     _check(lib().pm_build_bvh(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), _stream(stream),
                               C.byref(out)))
     return Bvh(out.value, v.shape[0])
 
 
 def build_bvh_host(verts: np.ndarray, tri_mat: np.ndarray | None = None, bins=32, max_leaf=4, n_threads=0,
-                   trav_cost=0.0):
-    """Host-only build: returns (nodes uint32 [6, n_nodes, 4], tris uint32 [T, 12], info dict)."""
+                   trav_cost=0.0, split_alpha=0.0):
+    """Host-only build: returns (nodes uint32 [6, n_nodes, 4], tris uint32 [n_refs, 12], info dict)."""
     v = np.ascontiguousarray(verts, np.float32)
     m = None if tri_mat is None else np.ascontiguousarray(tri_mat, np.uint32)
-    o = _opts(bins, max_leaf, n_threads, trav_cost)
+    o = _opts(bins, max_leaf, n_threads, trav_cost, 0, split_alpha)
     nn = C.c_int64()
     L = lib()
-    _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
-                               None, None, None))
-    nodes = np.zeros((6, nn.value, 4), np.uint32)
-    tris = np.zeros((v.shape[0], 12), np.uint32)
     inf = BvhInfo()
     inf.size = C.sizeof(BvhInfo)
+    _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
+                               None, None, C.byref(inf)))
+    nodes = np.zeros((6, nn.value, 4), np.uint32)
+    tris = np.zeros((inf.n_refs, 12), np.uint32)
     _check(L.pm_build_bvh_host(_ptr(v), None if m is None else _ptr(m), v.shape[0], C.byref(o), C.byref(nn),
                                _ptr(nodes), _ptr(tris), C.byref(inf)))
     return nodes, tris, _info_dict(inf)

@@ -2,6 +2,12 @@
 //
 // 1. Top-down SAH build with binned centroids (bins per axis, leaves of at
 //    most max_leaf triangles; a node larger than max_leaf is always split).
+//    Optionally with spatial splits as well (Stich, Friedrich and Dietrich,
+//    "Spatial splits in bounding volume hierarchies", HPG 2009): where the
+//    best object split leaves children whose boxes overlap by more than
+//    split_alpha of the scene box's area, planes through the node's box are
+//    also tried, each straddling triangle clipped to both sides; a triangle
+//    may then sit in several leaves, each time with the box of its part.
 // 2. Threading: for each of the six principal directions the tree is walked
 //    in preorder with, at every inner node, the child whose box centre comes
 //    first along that direction visited first.  Each node stores its skip
@@ -167,6 +173,253 @@ struct Builder {
     }
 };
 
+// Spatial-split build.  A reference is a triangle with the box of its part
+// inside the region it was clipped to.  Boxes are float, rounded outward from
+// the double clipping, so each contains the exact part: the union of a
+// triangle's leaf boxes covers it.
+struct Ref {
+    int32_t tri;
+    Box box;
+};
+
+// Box of the part of triangle t inside region r (its polygon clipped by the
+// six planes of r, in double), rounded outward to float; empty if none.
+Box clip_tri(const float *V, int32_t t, const double rlo[3], const double rhi[3]) {
+    double poly[9][3], tmp[9][3];
+    int n = 3;
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) poly[k][a] = V[9 * (size_t)t + 3 * k + a];
+    for (int a = 0; a < 3 && n; ++a)
+        for (int side = 0; side < 2 && n; ++side) {
+            const double pl = side ? rhi[a] : rlo[a];
+            int m = 0;
+            for (int i = 0; i < n; ++i) {
+                const double *p = poly[i], *q = poly[(i + 1) % n];
+                const bool pin = side ? p[a] <= pl : p[a] >= pl, qin = side ? q[a] <= pl : q[a] >= pl;
+                if (pin) std::memcpy(tmp[m++], p, sizeof(double) * 3);
+                if (pin != qin) {
+                    const double f = (pl - p[a]) / (q[a] - p[a]);
+                    for (int c = 0; c < 3; ++c) tmp[m][c] = p[c] + f * (q[c] - p[c]);
+                    tmp[m][a] = pl;
+                    ++m;
+                }
+            }
+            std::memcpy(poly, tmp, sizeof(double) * 3 * (size_t)m);
+            n = m;
+        }
+    Box b;
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            // clamp to the region, then round outward to float
+            const double x = std::min(std::max(poly[i][a], rlo[a]), rhi[a]);
+            float lo = (float)x, hi = lo;
+            if ((double)lo > x) lo = std::nextafter(lo, -INFINITY);
+            if ((double)hi < x) hi = std::nextafter(hi, INFINITY);
+            b.lo[a] = std::min(b.lo[a], lo);
+            b.hi[a] = std::max(b.hi[a], hi);
+        }
+    return b;
+}
+
+double overlap_area(const Box &a, const Box &b) {
+    Box r;
+    for (int k = 0; k < 3; ++k) {
+        r.lo[k] = std::max(a.lo[k], b.lo[k]);
+        r.hi[k] = std::min(a.hi[k], b.hi[k]);
+        if (!(r.lo[k] <= r.hi[k])) return 0.0;
+    }
+    return r.area();
+}
+
+struct SplitBuilder {
+    const float *V;
+    int bins, max_leaf;
+    double trav_cost, min_overlap;  // split_alpha x the scene box's area
+    int par_depth;
+
+    // Builds the subtree of refs into out (node indices local to out) with its
+    // leaves' triangle indices appended to leaf (leaf starts local to leaf).
+    int32_t build(std::vector<Ref> &refs, int depth, std::vector<TNode> &out, std::vector<int32_t> &leaf) {
+        int32_t ni = (int32_t)out.size();
+        out.emplace_back();
+        const int32_t count = (int32_t)refs.size();
+        Box nb, cb;
+        for (const Ref &r : refs) {
+            nb.grow(r.box);
+            float c[3];
+            for (int a = 0; a < 3; ++a) c[a] = 0.5f * (r.box.lo[a] + r.box.hi[a]);
+            cb.grow(c);
+        }
+        out[ni].box = nb;
+        auto make_leaf = [&]() {
+            out[ni].left = out[ni].right = -1;
+            out[ni].start = (int32_t)leaf.size();
+            out[ni].count = count;
+            for (const Ref &r : refs) leaf.push_back(r.tri);
+            std::vector<Ref>().swap(refs);
+            return ni;
+        };
+        if (count == 1) return make_leaf();
+
+        const int B = bins;
+        std::vector<Box> bb(B), rb(B);
+        std::vector<int32_t> bc(B), ec(B), rc(B);
+        // object split: binned centroids, as in Builder
+        double best_cost = INFINITY;
+        int best_axis = -1, best_split = -1;
+        Box best_l, best_r;
+        for (int a = 0; a < 3; ++a) {
+            const float ext = cb.hi[a] - cb.lo[a];
+            if (!(ext > 0.0f)) continue;
+            const double scale = (double)B / (double)ext;
+            for (int b = 0; b < B; ++b) bb[b] = Box(), bc[b] = 0;
+            for (const Ref &r : refs) {
+                int b = (int)(((double)(0.5f * (r.box.lo[a] + r.box.hi[a])) - cb.lo[a]) * scale);
+                b = std::min(std::max(b, 0), B - 1);
+                bb[b].grow(r.box);
+                bc[b]++;
+            }
+            Box acc;
+            int32_t c = 0;
+            for (int b = B - 1; b > 0; --b) acc.grow(bb[b]), c += bc[b], rb[b] = acc, rc[b] = c;
+            acc = Box();
+            c = 0;
+            for (int b = 0; b < B - 1; ++b) {
+                acc.grow(bb[b]);
+                c += bc[b];
+                if (c == 0 || rc[b + 1] == 0) continue;
+                const double cost = acc.area() * c + rb[b + 1].area() * rc[b + 1];
+                if (cost < best_cost) best_cost = cost, best_axis = a, best_split = b, best_l = acc, best_r = rb[b + 1];
+            }
+        }
+        // spatial split: planes at B - 1 bin boundaries of the node's box per
+        // axis; a reference enters the bins its box spans, with the box of its
+        // part in each (clipped), and is counted entering its first bin and
+        // leaving its last
+        double sbest = INFINITY;
+        int saxis = -1;
+        double splane = 0.0;
+        if (best_axis >= 0 && overlap_area(best_l, best_r) > min_overlap) {
+            for (int a = 0; a < 3; ++a) {
+                const double lo = nb.lo[a], ext = (double)nb.hi[a] - lo;
+                if (!(ext > 0.0)) continue;
+                auto plane = [&](int k) { return k == B ? (double)nb.hi[a] : lo + ext * k / B; };
+                for (int b = 0; b < B; ++b) bb[b] = Box(), bc[b] = 0, ec[b] = 0;
+                for (const Ref &r : refs) {
+                    int b0 = (int)(((double)r.box.lo[a] - lo) * B / ext), b1 = (int)(((double)r.box.hi[a] - lo) * B / ext);
+                    b0 = std::min(std::max(b0, 0), B - 1);
+                    b1 = std::min(std::max(b1, b0), B - 1);
+                    bc[b0]++;
+                    ec[b1]++;
+                    if (b0 == b1) {
+                        bb[b0].grow(r.box);
+                        continue;
+                    }
+                    double rlo[3], rhi[3];
+                    for (int k = 0; k < 3; ++k) rlo[k] = r.box.lo[k], rhi[k] = r.box.hi[k];
+                    for (int b = b0; b <= b1; ++b) {
+                        rlo[a] = std::max((double)r.box.lo[a], plane(b));
+                        rhi[a] = std::min((double)r.box.hi[a], plane(b + 1));
+                        bb[b].grow(clip_tri(V, r.tri, rlo, rhi));
+                    }
+                }
+                Box acc;
+                int32_t c = 0;
+                for (int b = B - 1; b > 0; --b) acc.grow(bb[b]), c += ec[b], rb[b] = acc, rc[b] = c;
+                acc = Box();
+                c = 0;
+                for (int b = 0; b < B - 1; ++b) {
+                    acc.grow(bb[b]);
+                    c += bc[b];
+                    if (c == 0 || rc[b + 1] == 0) continue;
+                    const double cost = acc.area() * c + rb[b + 1].area() * rc[b + 1];
+                    if (cost < sbest) sbest = cost, saxis = a, splane = plane(b + 1);
+                }
+            }
+        }
+        const double parea = nb.area();
+        const double bc_min = std::min(best_cost, sbest);
+        const double split_cost = bc_min < INFINITY ? trav_cost + (parea > 0 ? bc_min / parea : 0.0) : INFINITY;
+        if (count <= max_leaf && (double)count <= split_cost) return make_leaf();
+
+        std::vector<Ref> L, R;
+        if (!(sbest < best_cost)) saxis = -1;
+        if (saxis >= 0) {
+            const int a = saxis;
+            for (const Ref &r : refs) {
+                if ((double)r.box.hi[a] <= splane) {
+                    L.push_back(r);
+                } else if ((double)r.box.lo[a] >= splane) {
+                    R.push_back(r);
+                } else {
+                    double rlo[3], rhi[3];
+                    for (int k = 0; k < 3; ++k) rlo[k] = r.box.lo[k], rhi[k] = r.box.hi[k];
+                    rhi[a] = splane;
+                    const Box bl = clip_tri(V, r.tri, rlo, rhi);
+                    rhi[a] = r.box.hi[a];
+                    rlo[a] = splane;
+                    const Box br = clip_tri(V, r.tri, rlo, rhi);
+                    if (bl.lo[0] <= bl.hi[0]) L.push_back({r.tri, bl});
+                    if (br.lo[0] <= br.hi[0]) R.push_back({r.tri, br});
+                }
+            }
+            // a spatial split must shrink both sides, or the object split is taken
+            if (L.empty() || R.empty() || (int32_t)L.size() == count || (int32_t)R.size() == count) {
+                L.clear();
+                R.clear();
+                saxis = -1;
+            }
+        }
+        if (saxis < 0) {
+            if (best_axis < 0) {
+                if (count <= max_leaf) return make_leaf();
+                L.assign(refs.begin(), refs.begin() + count / 2);  // coincident centroids
+                R.assign(refs.begin() + count / 2, refs.end());
+            } else {
+                const int a = best_axis;
+                const double scale = (double)B / (double)(cb.hi[a] - cb.lo[a]);
+                for (const Ref &r : refs) {
+                    int b = (int)(((double)(0.5f * (r.box.lo[a] + r.box.hi[a])) - cb.lo[a]) * scale);
+                    b = std::min(std::max(b, 0), B - 1);
+                    (b <= best_split ? L : R).push_back(r);
+                }
+                if (L.empty() || R.empty()) {
+                    L.assign(refs.begin(), refs.begin() + count / 2);
+                    R.assign(refs.begin() + count / 2, refs.end());
+                }
+            }
+        }
+        std::vector<Ref>().swap(refs);
+        int32_t l, r;
+        if (depth < par_depth && count > 50000) {
+            std::vector<TNode> right_nodes;
+            std::vector<int32_t> right_leaf;
+            auto fut = std::async(std::launch::async, [&]() { return build(R, depth + 1, right_nodes, right_leaf); });
+            l = build(L, depth + 1, out, leaf);
+            fut.get();
+            const int32_t off = (int32_t)out.size(), loff = (int32_t)leaf.size();
+            for (auto &nd : right_nodes) {
+                if (nd.left >= 0) {
+                    nd.left += off;
+                    nd.right += off;
+                } else {
+                    nd.start += loff;
+                }
+                out.push_back(nd);
+            }
+            leaf.insert(leaf.end(), right_leaf.begin(), right_leaf.end());
+            r = off;
+        } else {
+            l = build(L, depth + 1, out, leaf);
+            r = build(R, depth + 1, out, leaf);
+        }
+        out[ni].left = l;
+        out[ni].right = r;
+        out[ni].start = out[ni].count = 0;
+        return ni;
+    }
+};
+
 inline uint32_t fbits(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);
@@ -187,21 +440,26 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
         err = "bins must be in [2,256], max_leaf in [1,7] and trav_cost in (0,64]";
         return false;
     }
+    if (!(opt.split_alpha >= 0.0 && opt.split_alpha <= 1.0)) {
+        err = "split_alpha must be in [0, 1]";
+        return false;
+    }
     for (int64_t i = 0; i < 9 * n_tri; ++i)
         if (!std::isfinite(verts[i])) {
             err = "non-finite vertex coordinate at triangle " + std::to_string(i / 9);
             return false;
         }
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int nth = opt.n_threads > 0 ? opt.n_threads : (int)std::min(hw, 16u);
+    int par_depth = 0;
+    while ((1 << par_depth) < nth) par_depth++;
     Builder b;
     b.V = verts;
     b.n = n_tri;
     b.bins = opt.bins;
     b.max_leaf = opt.max_leaf;
     b.trav_cost = opt.trav_cost;
-    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    int nth = opt.n_threads > 0 ? opt.n_threads : (int)std::min(hw, 16u);
-    b.par_depth = 0;
-    while ((1 << b.par_depth) < nth) b.par_depth++;
+    b.par_depth = par_depth;
     b.tb.resize((size_t)n_tri);
     b.cen.resize(3 * (size_t)n_tri);
     b.idx.resize((size_t)n_tri);
@@ -216,8 +474,31 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     }
     std::vector<TNode> tree;
     tree.reserve((size_t)(2 * n_tri));
-    b.build(0, (int32_t)n_tri, 0, tree);
+    // leaf order: the triangle of each record (with spatial splits a triangle
+    // can appear more than once)
+    std::vector<int32_t> &order = b.idx;
+    if (opt.split_alpha > 0.0) {
+        SplitBuilder sb;
+        sb.V = verts;
+        sb.bins = opt.bins;
+        sb.max_leaf = opt.max_leaf;
+        sb.trav_cost = opt.trav_cost;
+        sb.min_overlap = opt.split_alpha * scene.area();
+        sb.par_depth = par_depth;
+        std::vector<Ref> refs((size_t)n_tri);
+        for (int64_t i = 0; i < n_tri; ++i) refs[i] = Ref{(int32_t)i, b.tb[i]};
+        order.clear();
+        order.reserve((size_t)(n_tri + n_tri / 2));
+        sb.build(refs, 0, tree, order);
+        if ((int64_t)order.size() >= (int64_t(1) << 28)) {
+            err = "spatial splits made 2^28 or more triangle records: raise split_alpha";
+            return false;
+        }
+    } else {
+        b.build(0, (int32_t)n_tri, 0, tree);
+    }
     const int64_t nn = (int64_t)tree.size();
+    const int64_t n_rec = (int64_t)order.size();
 
     // statistics: depth, leaves, SAH cost
     std::vector<int32_t> dep((size_t)nn, 0), size((size_t)nn, 1);
@@ -278,6 +559,7 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     };
 
     out.n_tri = n_tri;
+    out.n_refs = n_rec;
     out.n_nodes = nn;
     out.n_leaves = leaves;
     out.depth = maxdep;
@@ -334,9 +616,9 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
     for (int s = 0; s < kLinkSets; ++s) th.emplace_back(thread_set, s);
     for (auto &x : th) x.join();
 
-    out.tris.assign((size_t)n_tri * kTriWords, 0u);
-    for (int64_t k = 0; k < n_tri; ++k) {
-        int32_t t = b.idx[k];
+    out.tris.assign((size_t)n_rec * kTriWords, 0u);
+    for (int64_t k = 0; k < n_rec; ++k) {
+        int32_t t = order[k];
         const float *v = verts + 9 * (size_t)t;
         uint32_t *w = out.tris.data() + (size_t)k * kTriWords;
         for (int a = 0; a < 3; ++a) {

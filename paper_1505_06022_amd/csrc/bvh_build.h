@@ -12,6 +12,7 @@ struct BuildOptions {
     int n_threads = 0;
     double trav_cost = 1.0;  // SAH: node visit cost relative to a triangle test
     int builder = 0;         // PM_BUILD_HOST_SAH or PM_BUILD_GPU_LBVH
+    double split_alpha = 0;  // spatial splits where children overlap by more than this x scene area; 0 = none
 };
 
 // Device layout (words are 32-bit):
@@ -25,10 +26,11 @@ struct BuildOptions {
 //          first_tri << 3 | count.  The "hit" link of an inner node is the
 //          next node (i + 1); a leaf occupies one slot, so both of its links
 //          are i + 1.
-//   tris:  n_tri x 12 words in leaf order: v0.xyz, e1 = v1-v0, e2 = v2-v0,
-//          original triangle index, material id, 0.
+//   tris:  n_refs x 12 words in leaf order: v0.xyz, v1.xyz, v2.xyz (float32,
+//          as given), original triangle index, material id, 0.  n_refs =
+//          n_tri unless spatial splits put a triangle in several leaves.
 struct HostBvh {
-    int64_t n_tri = 0, n_nodes = 0, n_leaves = 0;
+    int64_t n_tri = 0, n_refs = 0, n_nodes = 0, n_leaves = 0;
     int32_t depth = 0, max_leaf = 0;
     double sah_cost = 0.0, build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // scene bounds (unpadded)

@@ -45,8 +45,13 @@ static bool read_opts(const pm_bvh_opts *o, BuildOptions &bo) {
     bo.n_threads = o->n_threads;
     bo.trav_cost = o->trav_cost == 0.0f ? 1.0 : (double)o->trav_cost;
     bo.builder = o->builder;
+    bo.split_alpha = (double)o->split_alpha;
     if (bo.builder != PM_BUILD_HOST_SAH && bo.builder != PM_BUILD_GPU_LBVH) {
         set_error("builder must be PM_BUILD_HOST_SAH or PM_BUILD_GPU_LBVH");
+        return false;
+    }
+    if (bo.builder == PM_BUILD_GPU_LBVH && bo.split_alpha != 0.0) {
+        set_error("spatial splits (split_alpha) are an option of the host SAH build");
         return false;
     }
     return true;
@@ -91,6 +96,7 @@ int pm_build_bvh_host(const float *tri_verts, const uint32_t *tri_mat, int64_t n
         if (tris) std::memcpy(tris, hb.tris.data(), hb.tris.size() * sizeof(uint32_t));
         if (info) {
             info->n_tri = hb.n_tri;
+            info->n_refs = hb.n_refs;
             info->n_nodes = hb.n_nodes;
             info->n_leaves = hb.n_leaves;
             info->depth = hb.depth;
@@ -161,7 +167,7 @@ int pm_bvh_download(const pm_bvh *b, uint32_t *nodes, uint32_t *tris, void *stre
             PM_HIP(hipMemcpyAsync(nodes, b->d_nodes, sizeof(uint32_t) * 4 * 6 * (size_t)b->n_nodes,
                                   hipMemcpyDeviceToHost, s));
         if (tris)
-            PM_HIP(hipMemcpyAsync(tris, b->d_tris, sizeof(uint32_t) * 12 * (size_t)b->n_tri, hipMemcpyDeviceToHost, s));
+            PM_HIP(hipMemcpyAsync(tris, b->d_tris, sizeof(uint32_t) * 12 * (size_t)b->n_refs, hipMemcpyDeviceToHost, s));
         PM_HIP(hipStreamSynchronize(s));
         return PM_OK;
     })
@@ -171,12 +177,13 @@ int pm_bvh_get_info(const pm_bvh *b, pm_bvh_info *info) {
     PM_GUARD({
         if (!b || !info || info->size < sizeof(pm_bvh_info)) return pm::set_error("invalid bvh or info"), PM_ERR_ARG;
         info->n_tri = b->n_tri;
+        info->n_refs = b->n_refs;
         info->n_nodes = b->n_nodes;
         info->n_leaves = b->n_leaves;
         info->depth = b->depth;
         info->max_leaf = b->max_leaf;
         info->sah_cost = b->sah_cost;
-        info->device_bytes = b->n_nodes * 6 * 16 + b->n_tri * 48;
+        info->device_bytes = b->n_nodes * 6 * 16 + b->n_refs * 48;
         info->build_ms = b->build_ms;
         for (int a = 0; a < 3; ++a) {
             info->grid_lo[a] = b->qlo[a];

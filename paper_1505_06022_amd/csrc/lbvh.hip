@@ -485,6 +485,7 @@ int build_bvh_gpu(const float *verts_h, const uint32_t *mats_h, int64_t n_tri, i
     PM_HIP(hipStreamSynchronize(s));
     if (st.bad) return set_error("GPU BVH build: inconsistent tree"), PM_ERR_STATE;
     b->n_tri = n_tri;
+    b->n_refs = n_tri;
     b->n_nodes = n_nodes;
     b->n_leaves = (int64_t)st.leaves;
     b->depth = (int32_t)st.depth;

@@ -31,13 +31,13 @@ constexpr size_t kPadNodes = 1;
 }  // namespace pm
 
 struct pm_bvh {
-    int64_t n_tri = 0, n_nodes = 0, n_leaves = 0;
+    int64_t n_tri = 0, n_refs = 0, n_nodes = 0, n_leaves = 0;  // n_refs: triangle records
     int32_t depth = 0, max_leaf = 0;
     double sah_cost = 0.0, build_ms = 0.0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float qlo[3] = {0, 0, 0}, qstep[3] = {1, 1, 1};
     uint4 *d_nodes = nullptr;   // [6][n_nodes] 16-byte nodes, then kPadNodes zeroed nodes
-    float4 *d_tris = nullptr;   // [n_tri][3]
+    float4 *d_tris = nullptr;   // [n_refs][3]
     uint32_t *d_next = nullptr; // work counter of the persistent traversal kernel
     uint32_t *d_perm = nullptr; // ray order of the reordering traversal (perm_cap entries)
     uint64_t perm_cap = 0;
@@ -48,7 +48,7 @@ struct pm_bvh {
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[PM_MAX_TRACE_BATCHES] = {};
     int device = 0;
-    std::vector<int32_t> pos_of;  // original triangle index -> position in d_tris
+    std::vector<int32_t> pos_of;  // original triangle index -> its first record in d_tris
 };
 
 namespace pmd {

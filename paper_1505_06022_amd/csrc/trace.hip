@@ -403,6 +403,7 @@ pmd::Bvh make_device_bvh(const pm_bvh *b) {
 
 int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b) {
     b->n_tri = h.n_tri;
+    b->n_refs = h.n_refs;
     b->n_nodes = h.n_nodes;
     b->n_leaves = h.n_leaves;
     b->depth = h.depth;
@@ -415,8 +416,11 @@ int upload_bvh(const HostBvh &h, hipStream_t s, pm_bvh *b) {
         b->qlo[a] = h.qlo[a];
         b->qstep[a] = h.qstep[a];
     }
-    b->pos_of.assign((size_t)h.n_tri, 0);
-    for (int64_t k = 0; k < h.n_tri; ++k) b->pos_of[h.tris[(size_t)k * kTriWords + 9]] = (int32_t)k;
+    b->pos_of.assign((size_t)h.n_tri, -1);
+    for (int64_t k = 0; k < h.n_refs; ++k) {
+        int32_t &p = b->pos_of[h.tris[(size_t)k * kTriWords + 9]];
+        if (p < 0) p = (int32_t)k;
+    }
     PM_HIP(hipGetDevice(&b->device));
     size_t nb = h.nodes.size() * sizeof(uint32_t), tb = h.tris.size() * sizeof(uint32_t);
     // zeroed pad nodes after the six arrays (a packet walk reads the node after the one it visits)

@@ -25,29 +25,68 @@ def decode(nodes_s, info):
     return lo, hi, leaf, first, cnt, skip
 
 
+def _sample_points(verts, k=12, seed=0):
+    """Points on each triangle, float64 [T, 3 + 3 + k, 3]: the vertices, the
+    edge midpoints and k random barycentric points."""
+    v = np.asarray(verts, np.float64)
+    rng = np.random.default_rng(seed)
+    a = rng.random((len(v), k, 1))
+    b = rng.random((len(v), k, 1))
+    flip = (a + b) > 1
+    a, b = np.where(flip, 1 - a, a), np.where(flip, 1 - b, b)
+    rnd = v[:, None, 0] + a * (v[:, None, 1] - v[:, None, 0]) + b * (v[:, None, 2] - v[:, None, 0])
+    mid = 0.5 * (v[:, [0, 1, 2]] + v[:, [1, 2, 0]])
+    return np.concatenate([v, mid, rnd], 1)
+
+
 def check_structure(verts, nodes, tris, max_leaf, info):
+    """Without spatial splits (n_refs == n_tri) every triangle is in exactly
+    one leaf and inside its box.  With them a triangle may be in several
+    leaves, and sample points of it (vertices, edge midpoints, random
+    interior points) must each lie in the box of one of its leaves."""
     T = len(verts)
     S, n, _ = nodes.shape
     assert S == 6
-    # triangles: every original index exactly once, its three vertices as given
+    R = info.get("n_refs", T)
+    assert len(tris) == R and R >= T
+    # records: every original index at least once (exactly once without
+    # spatial splits), each with its three vertices as given
     ids = tris[:, 9].astype(np.int64)
-    assert np.array_equal(np.sort(ids), np.arange(T))
+    if R == T:
+        assert np.array_equal(np.sort(ids), np.arange(T))
+    else:
+        assert np.array_equal(np.unique(ids), np.arange(T))
     tf = f32(tris)
     v = verts[ids]
     assert np.array_equal(tf[:, 0:9], v.reshape(-1, 9))
     assert np.all(tris[:, 11] == 0)
+    pts = None if R == T else _sample_points(verts)
     for s in range(6):
         lo, hi, is_leaf, first, cnt, skip = decode(nodes[s], info)
         assert skip[0] == n                              # root's miss link ends the walk
         assert np.all(skip > np.arange(n)) and np.all(skip <= n)
         assert np.all(cnt[is_leaf] >= 1) and np.all(cnt[is_leaf] <= max_leaf)
-        # every triangle in exactly one leaf, inside its (padded, quantised) box
-        cover = np.zeros(T, np.int64)
-        for i in np.nonzero(is_leaf)[0]:
+        # every record in exactly one leaf
+        cover = np.zeros(R, np.int64)
+        leaves = np.nonzero(is_leaf)[0]
+        for i in leaves:
             cover[first[i]:first[i] + cnt[i]] += 1
-            tv = verts[ids[first[i]:first[i] + cnt[i]]].reshape(-1, 3).astype(np.float64)
-            assert np.all(tv > lo[i]) and np.all(tv < hi[i])
         assert np.all(cover == 1)
+        rec_leaf = np.zeros(R, np.int64)
+        for i in leaves:
+            rec_leaf[first[i]:first[i] + cnt[i]] = i
+        if R == T:
+            # each triangle inside its leaf's (padded, quantised) box
+            tv = verts[ids].astype(np.float64)
+            assert np.all(tv > lo[rec_leaf][:, None]) and np.all(tv < hi[rec_leaf][:, None])
+        else:
+            # each sample point inside the box of at least one of its triangle's leaves
+            inside = np.zeros(pts.shape[:2], bool)
+            for r in range(R):
+                p = pts[ids[r]]
+                i = rec_leaf[r]
+                inside[ids[r]] |= np.all((p > lo[i]) & (p < hi[i]), axis=1)
+            assert inside.all()
         # inner nodes: children are i+1 and skip[i+1]; their boxes nest
         for i in np.nonzero(~is_leaf)[0]:
             a = i + 1

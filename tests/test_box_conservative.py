@@ -36,8 +36,11 @@ def _scene(kind):
     return scenes.box_scene(8, 8).verts
 
 
-def _check(oracle_lib, verts, rays):
-    nodes, tris, info = api.build_bvh_host(verts)
+def _check(oracle_lib, verts, rays, alpha=0.0):
+    """alpha > 0: a BVH with spatial splits, whose leaves hold the boxes of
+    clipped parts of triangles (rounded outward, then padded like any box)."""
+    nodes, tris, info = api.build_bvh_host(verts, split_alpha=alpha)
+    assert (info["n_refs"] > info["n_tri"]) == (alpha > 0)
     h_ref, t_ref = oracle_lib.trace_brute_force(verts, rays)
     h, t, _ = walk32(nodes, tris, info, rays)
     bad = np.nonzero(h != h_ref)[0]
@@ -47,21 +50,21 @@ def _check(oracle_lib, verts, rays):
     return h_ref
 
 
-@pytest.mark.parametrize("kind", ["soup", "box"])
+@pytest.mark.parametrize("kind,alpha", [("soup", 0.0), ("box", 0.0), ("soup", 1e-5)])
 @pytest.mark.parametrize("on_edges", [False, True])
-def test_grazing_rays_walk_equals_brute_force(oracle_lib, kind, on_edges):
+def test_grazing_rays_walk_equals_brute_force(oracle_lib, kind, alpha, on_edges):
     verts = _scene(kind)
     angles = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
     rays = scenes.grazing_rays(verts, 3000, angles, seed=21 + on_edges, on_edges=on_edges)
-    h = _check(oracle_lib, verts, rays)
+    h = _check(oracle_lib, verts, rays, alpha)
     assert (h >= 0).mean() > 0.5
 
 
-@pytest.mark.parametrize("kind", ["soup", "box"])
-def test_far_origin_rays_walk_equals_brute_force(oracle_lib, kind):
+@pytest.mark.parametrize("kind,alpha", [("soup", 0.0), ("box", 0.0), ("soup", 1e-5)])
+def test_far_origin_rays_walk_equals_brute_force(oracle_lib, kind, alpha):
     verts = _scene(kind)
     rays = scenes.far_origin_rays(verts, 2000, seed=31)
-    h = _check(oracle_lib, verts, rays)
+    h = _check(oracle_lib, verts, rays, alpha)
     assert (h >= 0).mean() > 0.5
 
 

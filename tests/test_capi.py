@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(L, name), name
     assert sorted(api.EXPORTS) == decl
-    assert api.abi_version() == 1
+    assert api.abi_version() == 2
 
 
 def test_host_validation_errors_without_gpu():
@@ -49,6 +49,14 @@ def test_host_validation_errors_without_gpu():
     assert b"builder" in L.pm_last_error()
     o = api._opts(32, 4, 0, 0.0, builder=api.BUILD_GPU_LBVH)
     assert L.pm_build_bvh_host(v.ctypes.data, None, 1, C.byref(o), C.byref(nn), None, None, None) == api.PM_ERR_ARG
+    for a in (-1e-3, 1.5, float("nan")):
+        o = api._opts(32, 4, 0, 0.0, split_alpha=a)
+        assert L.pm_build_bvh_host(v.ctypes.data, None, 1, C.byref(o), C.byref(nn), None, None, None) == api.PM_ERR_ARG
+        assert b"split_alpha" in L.pm_last_error()
+    # spatial splits are a host-build option
+    o = api._opts(32, 4, 0, 0.0, builder=api.BUILD_GPU_LBVH, split_alpha=1e-3)
+    assert L.pm_build_bvh(v.ctypes.data, None, 1, C.byref(o), None, C.byref(out_bvh)) == api.PM_ERR_ARG
+    assert b"split_alpha" in L.pm_last_error()
     assert L.pm_bvh_download(None, None, None, None) == api.PM_ERR_ARG
     # scene/param validation happens before any device work
     sc = scenes.box_scene(8, 8)
@@ -155,12 +163,18 @@ def _wt32(ray, tri):
     return float(t[0]) if ok[0] else None
 
 
-@pytest.mark.parametrize("seed,n", [(0, 1), (1, 5), (2, 33), (3, 64), (4, 300)])
-def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, seed, n):
-    sc = scenes.small_soup(n, seed, spread=0.4 / max(1.0, np.cbrt(n)))
-    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat)
+@pytest.mark.parametrize("seed,n,spread,alpha", [(0, 1, None, 0.0), (1, 5, None, 0.0), (2, 33, None, 0.0),
+                                                 (3, 64, None, 0.0), (4, 300, None, 0.0), (3, 64, None, 1e-4),
+                                                 (4, 300, None, 1e-4), (5, 200, 0.3, 1e-5)])
+def test_host_bvh_structure_and_every_link_set_matches_brute_force(oracle_lib, seed, n, spread, alpha):
+    """alpha > 0: spatial splits put triangles in several leaves, each with the
+    box of its clipped part; the walk must still find the brute-force hit."""
+    sc = scenes.small_soup(n, seed, spread=0.4 / max(1.0, np.cbrt(n)) if spread is None else spread)
+    nodes, tris, info = api.build_bvh_host(sc.verts, sc.tri_mat, split_alpha=alpha)
     assert check_structure(sc.verts, nodes, tris, 4, info)
     assert info["n_nodes"] == nodes.shape[1] and info["n_tri"] == n
+    assert (info["n_refs"] > n) if alpha > 0 else (info["n_refs"] == n)
+    assert info["device_bytes"] == 6 * 16 * info["n_nodes"] + 48 * info["n_refs"]
     rays = scenes.random_rays(60, seed)
     h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
     for s in range(6):
@@ -362,6 +376,12 @@ def test_host_bvh_box_scene_and_soup_statistics():
     assert info2["n_nodes"] < info["n_nodes"]
     # storage: 6 link sets x 16 B per node + 48 B per triangle
     assert info["device_bytes"] == 6 * 16 * info["n_nodes"] + 48 * info["n_tri"]
+    # spatial splits: more records, a lower SAH cost, and the same BVH from two builds
+    n3, t3, info3 = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8, split_alpha=1e-5)
+    check_structure(sc.verts, n3, t3, 2, info3)
+    assert info3["n_refs"] > info3["n_tri"] and info3["sah_cost"] < info["sah_cost"]
+    n4, t4, info4 = api.build_bvh_host(sc.verts, sc.tri_mat, max_leaf=2, bins=8, split_alpha=1e-5, n_threads=3)
+    assert np.array_equal(n3, n4) and np.array_equal(t3, t4)
 
 
 def test_binding_classes_expose_the_abi():

@@ -151,14 +151,60 @@ def test_slices_and_packets_in_one_multi_call_equal_single_calls(torch_cuda, ora
         _compare(two[1][0].cpu().numpy(), two[1][1].cpu().numpy(), h_ref, t_ref)
 
 
-@pytest.mark.parametrize("builder", [api.BUILD_HOST_SAH, api.BUILD_GPU_LBVH])
+# (builder, split_alpha): the host SAH build, the GPU linear BVH, and the host
+# SAH build with spatial splits (triangles in several leaves, clipped boxes)
+BUILDS = [(api.BUILD_HOST_SAH, 0.0), (api.BUILD_GPU_LBVH, 0.0), (api.BUILD_HOST_SAH, 1e-5)]
+
+
+@pytest.mark.parametrize("alpha", [1e-3, 1e-5])
+def test_spatial_split_bvh_every_kernel(torch_cuda, oracle_lib, alpha):
+    """A BVH with spatial splits (triangles referenced by several leaves, each
+    with the box of its clipped part): every traversal kernel, with
+    bucketing, packets over image tiles, slices, forced link sets, statistics
+    and the two-batch call, equals brute force; hits are original indices."""
+    _log(f"case: spatial-split BVH alpha={alpha}")
+    sc = scenes.small_soup(5000, 13, spread=0.04)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat, split_alpha=alpha)
+    inf = bvh.info()
+    assert inf["n_refs"] > inf["n_tri"] == 5000
+    nodes, tris = bvh.download()
+    assert tris.shape == (inf["n_refs"], 12) and np.array_equal(np.unique(tris[:, 9]), np.arange(5000))
+    hn, ht, hinf = api.build_bvh_host(sc.verts, sc.tri_mat, split_alpha=alpha)   # the same BVH
+    assert np.array_equal(nodes, hn) and np.array_equal(tris, ht) and hinf["n_refs"] == inf["n_refs"]
+    inc = scenes.random_rays(7001, 13)
+    cam = scenes.pinhole_rays(sc.camera)
+    rays = np.concatenate([inc, cam])
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays)
+    for kw in (dict(kernel=1), dict(kernel=2, refill=16), dict(kernel=3, reorder=1), dict(kernel=4, refill=32,
+               reorder=1, block=64), dict(kernel=5, reorder=2), dict(kernel=6),
+               dict(kernel=api.TRACE_SLICES, refill=32, reorder=1, block=64, slice_rays=100)):
+        h, t = _gpu_trace(torch_cuda, bvh, rays, **kw)
+        _compare(h, t, h_ref, t_ref)
+    for s_ in range(6):
+        h, t = _gpu_trace(torch_cuda, bvh, rays, link_set=s_, kernel=4, refill=32)
+        _compare(h, t, h_ref, t_ref)
+    cnt = torch_cuda.zeros((len(rays), 2), dtype=torch_cuda.int32, device="cuda")
+    h, t = _gpu_trace(torch_cuda, bvh, rays, counters=cnt, kernel=4, refill=32, reorder=1)
+    _compare(h, t, h_ref, t_ref)
+    W, H = sc.camera.width, sc.camera.height
+    h, t = _gpu_trace(torch_cuda, bvh, cam, kernel=6, block=64, tile_width=W)
+    _compare(h, t, h_ref[len(inc):], t_ref[len(inc):])
+    ri, rc = (torch_cuda.from_numpy(np.ascontiguousarray(x)).cuda() for x in (inc, cam))
+    (hi_, ti_), (hc_, tc_) = api.trace_rays_multi(bvh, [dict(rays=ri, kernel=4, refill=32, reorder=1, block=64),
+                                                        dict(rays=rc, kernel=6, block=64, tile_width=W)])
+    _compare(hi_.cpu().numpy(), ti_.cpu().numpy(), h_ref[:len(inc)], t_ref[:len(inc)])
+    _compare(hc_.cpu().numpy(), tc_.cpu().numpy(), h_ref[len(inc):], t_ref[len(inc):])
+    bvh.destroy()
+
+
+@pytest.mark.parametrize("builder,alpha", BUILDS)
 @pytest.mark.parametrize("kind", ["soup", "box"])
-def test_grazing_and_far_origin_rays(torch_cuda, oracle_lib, builder, kind):
+def test_grazing_and_far_origin_rays(torch_cuda, oracle_lib, builder, alpha, kind):
     """Rays that stress the box test's conservativeness: grazing angles
     1e-1..1e-6 rad at interior points and at edges/vertices of the triangle
     they aim at, and origins 10^2..10^5 extents away; every traversal kernel,
-    both builders, against brute force."""
-    _log(f"case: grazing/far-origin rays builder={builder} scene={kind}")
+    every build, against brute force."""
+    _log(f"case: grazing/far-origin rays builder={builder} alpha={alpha} scene={kind}")
     verts = (scenes.small_soup(4096, 11, spread=0.03).verts if kind == "soup"
              else scenes.box_scene(8, 8).verts)
     angles = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
@@ -167,30 +213,53 @@ def test_grazing_and_far_origin_rays(torch_cuda, oracle_lib, builder, kind):
                            scenes.far_origin_rays(verts, 2000, seed=31)])
     h_ref, t_ref = oracle_lib.trace_brute_force(verts, rays)
     assert (h_ref >= 0).mean() > 0.5
-    bvh = api.build_bvh(verts, builder=builder)
+    bvh = api.build_bvh(verts, builder=builder, split_alpha=alpha)
     for kernel in (1, 2, 3, 4, 5, 6):
         h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel)
         _compare(h, t, h_ref, t_ref)
 
 
-@pytest.mark.parametrize("builder", [api.BUILD_HOST_SAH, api.BUILD_GPU_LBVH])
-def test_closed_mesh_watertight_on_device(torch_cuda, oracle_lib, builder):
-    """Rays from inside a closed icosphere (level 3, 1,280 triangles) aimed
-    exactly at its shared vertices and at points of its shared edges: every
+def _closed_box(lo, hi):
+    """The 12 triangles of the closed box [lo, hi]^3 (two per face)."""
+    c = np.array([[x, y, z] for x in (lo, hi) for y in (lo, hi) for z in (lo, hi)], np.float64)
+    quads = [(0, 1, 3, 2), (4, 6, 7, 5), (0, 4, 5, 1), (2, 3, 7, 6), (0, 2, 6, 4), (1, 5, 7, 3)]
+    return np.asarray([[c[a], c[b], c[d]] for a, b, cc, d in quads for b, d in ((b, cc), (cc, d))])
+
+
+@pytest.mark.parametrize("builder,alpha", BUILDS)
+@pytest.mark.parametrize("mesh", ["sphere", "sphere_in_box"])
+def test_closed_mesh_watertight_on_device(torch_cuda, oracle_lib, builder, alpha, mesh):
+    """Rays aimed exactly at the shared vertices and at points of the shared
+    edges of closed meshes: an icosphere (level 3, 1,280 triangles) from inside
+    it, and that sphere (radius 0.5) inside a closed box of 12 triangles, from
+    points between the two, aimed at both meshes' edges and vertices (with
+    spatial splits the box's triangles are clipped into several leaves).  Every
     ray hits, with every traversal kernel, and equals brute force."""
-    _log(f"case: watertight icosphere, builder={builder}")
+    _log(f"case: watertight {mesh}, builder={builder} alpha={alpha}")
     rng = np.random.default_rng(12)
-    verts = (scenes._icosphere(3) * 2.5 + np.array([0.3, -1.2, 0.8])).astype(np.float32)
+    c0 = np.array([0.3, -1.2, 0.8])
+    if mesh == "sphere":
+        verts = (scenes._icosphere(3) * 2.5 + c0).astype(np.float32)
+    else:
+        verts = np.concatenate([scenes._icosphere(3) * 0.5, _closed_box(-3.0, 3.0)]) + c0
+        verts = verts.astype(np.float32)
     pts = np.unique(verts.reshape(-1, 3), axis=0)
     edges = [f[i].astype(np.float64) + lam * (f[(i + 1) % 3].astype(np.float64) - f[i].astype(np.float64))
              for f in verts for i in range(3) for lam in (0.5, rng.random())]
     targets = np.concatenate([pts, np.asarray(edges)]).astype(np.float32)
-    o = (np.array([0.3, -1.2, 0.8]) + 1.2 * rng.uniform(-1, 1, (len(targets), 3)) / np.sqrt(3)).astype(np.float32)
+    if mesh == "sphere":
+        o = c0 + 1.2 * rng.uniform(-1, 1, (len(targets), 3)) / np.sqrt(3)
+    else:   # between the sphere and the box
+        o = rng.uniform(-2.5, 2.5, (len(targets), 3))
+        o = c0 + o * np.maximum(1.0, 0.8 / np.linalg.norm(o, axis=1))[:, None]
+    o = o.astype(np.float32)
     rays = np.zeros((len(targets), 8), np.float32)
     rays[:, 0:3], rays[:, 4:7], rays[:, 7] = o, targets - o, np.inf
     h_ref, t_ref = oracle_lib.trace_brute_force(verts, rays)
     assert (h_ref >= 0).all()
-    bvh = api.build_bvh(verts, builder=builder)
+    bvh = api.build_bvh(verts, builder=builder, split_alpha=alpha)
+    if alpha > 0 and mesh == "sphere_in_box":
+        assert bvh.info()["n_refs"] > len(verts)
     for kernel in (1, 2, 3, 4, 5, 6, 7):
         h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=kernel)
         _compare(h, t, h_ref, t_ref)
@@ -255,7 +324,17 @@ def test_soup_full_size_sampled_rays(torch_cuda, oracle_lib):
                                                         dict(rays=rc, kernel=6, block=64, tile_width=1920)])
     assert np.array_equal(h[nc:], hi_.cpu().numpy()) and np.array_equal(t[nc:], ti_.cpu().numpy())
     assert np.array_equal(h[:nc], hc_.cpu().numpy()) and np.array_equal(t[:nc], tc_.cpu().numpy())
-    del ri, rc
+    # the bench's BVH: spatial splits; its timed call gives the same hits
+    bs = api.build_bvh(sc.verts, sc.tri_mat, split_alpha=scenes.SOUP_SPLIT_ALPHA, trav_cost=scenes.SOUP_TRAV_COST)
+    assert bs.info()["n_refs"] > bs.info()["n_tri"]
+    (hi_, ti_), (hc_, tc_) = api.trace_rays_multi(bs, [dict(rays=ri, kernel=4, refill=32, reorder=1, block=64),
+                                                       dict(rays=rc, kernel=6, block=64, tile_width=1920)])
+    assert np.array_equal(h[nc:], hi_.cpu().numpy()) and np.array_equal(t[nc:], ti_.cpu().numpy())
+    assert np.array_equal(h[:nc], hc_.cpu().numpy()) and np.array_equal(t[:nc], tc_.cpu().numpy())
+    hs, ts = _gpu_trace(torch_cuda, bs, rays, kernel=1)
+    assert np.array_equal(h, hs) and np.array_equal(t, ts)
+    bs.destroy()
+    del ri, rc, hi_, ti_, hc_, tc_
     h5, t5 = _gpu_trace(torch_cuda, bvh, rays[:-1], kernel=5, reorder=1, block=64)   # odd count
     assert np.array_equal(h[:-1], h5) and np.array_equal(t[:-1], t5)
     for level in (1, 2):                                      # reordered: identical
