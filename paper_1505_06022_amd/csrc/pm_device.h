@@ -253,8 +253,11 @@ struct TraceStats {
 // link.  The box test is conservative (padded boxes, a relative slack on the
 // exit distance; the bound is at box_hit) so the result equals the
 // brute-force closest hit.  Walker holds one lane's traversal state so that a persistent kernel
-// can interleave node steps of different rays.
-struct Walker {
+// can interleave node steps of different rays.  kPairTris: a leaf's triangle
+// records are requested two at a time (more registers; it pays where leaves
+// are full and the kernel's occupancy is already register-bound).
+template <bool kPairTris>
+struct WalkerT {
     const uint4 *nodes;
     uint32_t n, i;
     V3 o, d;
@@ -344,16 +347,35 @@ struct Walker {
     template <bool kStats>
     __device__ __forceinline__ void leaf_tris(const float4 *__restrict__ tris, uint32_t w, TraceStats &st) {
         uint32_t first = (w >> 3) & 0x0fffffffu, cnt = w & 7u;
-        for (uint32_t k = 0; k < cnt; ++k) {
-            Tri tr = load_tri(tris, first + k);
-            if (kStats) st.tris++;
-            if (tr.id == exclude) continue;
-            float t;
-            if (wt_hit(o, sh, tr, t) && accept_hit(t, tr.id, tmin, tbest, best)) {
-                tbest = t;
-                best = tr.id;
-                best_k = first + k;
+        // the excluded triangle is checked after the test, so that a record's
+        // words arrive in one round trip (a branch on the index first would
+        // wait for it before loading the vertices)
+        if constexpr (kPairTris) {
+            for (uint32_t k = 0; k < cnt; k += 2) {
+                const bool two = k + 1 < cnt;
+                const Tri ta = load_tri(tris, first + k);
+                const Tri tb = load_tri(tris, first + k + (two ? 1u : 0u));
+                if (kStats) st.tris += two ? 2u : 1u;
+                tri_test(ta, first + k);
+                if (two) tri_test(tb, first + k + 1);
             }
+        } else {
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const Tri tr = load_tri(tris, first + k);
+                if (kStats) st.tris++;
+                tri_test(tr, first + k);
+            }
+        }
+    }
+
+    // Triangle record rec against the ray: the closest hit so far, ties in t
+    // to the lower original index, the excluded triangle skipped.
+    __device__ __forceinline__ void tri_test(const Tri &tr, uint32_t rec) {
+        float t;
+        if (wt_hit(o, sh, tr, t) && tr.id != exclude && accept_hit(t, tr.id, tmin, tbest, best)) {
+            tbest = t;
+            best = tr.id;
+            best_k = rec;
         }
     }
 
@@ -427,6 +449,7 @@ struct Walker {
 
     __device__ __forceinline__ float t_hit() const { return best >= 0 ? tbest : __builtin_inff(); }
 };
+using Walker = WalkerT<false>;
 
 // Packet walk, for a wave whose lanes all walk one link set (nodes = that
 // set's node array, the same on every lane): the wave follows one node index,
@@ -492,17 +515,18 @@ __device__ __forceinline__ void walk_two(Walker &a, Walker &b, const float4 *__r
 
 // Returns the original index of the closest triangle (-1: none); t_out gets
 // its distance (+inf on a miss) and k_out its position in the triangle array.
-// paired: the walk requests nodes i and i + 1 together (step2).
-template <bool kStats>
+// paired: the walk requests nodes i and i + 1 together (step2); kPairTris:
+// a leaf's triangle records two at a time.
+template <bool kStats, bool kPairTris = false>
 __device__ __forceinline__ int32_t closest_hit(const Bvh &bvh, int set, V3 o, V3 d, float tmin, float tmax,
                                                int32_t exclude, float &t_out, uint32_t &k_out, TraceStats &st,
                                                bool paired = false) {
-    Walker w;
+    WalkerT<kPairTris> w;
     w.init(bvh, set, o, d, tmin, tmax, exclude);
     if (paired) {
-        while (!w.done()) w.step2<kStats>(bvh.tris, st);
+        while (!w.done()) w.template step2<kStats>(bvh.tris, st);
     } else {
-        while (!w.done()) w.step<kStats>(bvh.tris, st);
+        while (!w.done()) w.template step<kStats>(bvh.tris, st);
     }
     t_out = w.t_hit();
     k_out = w.best_k;

@@ -236,8 +236,8 @@ __device__ __forceinline__ bool photon_bounce(const SppmDev &d, PhotonPath &P, u
     float t;
     uint32_t kp;
     TraceStats st{0u, 0u};
-    int32_t h = closest_hit<kStats>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl, t, kp,
-                                    st, d.paired_walk != 0);
+    int32_t h = closest_hit<kStats, true>(sc.bvh, ray_set(d, P.dir), P.org, P.dir, sc.eps, __builtin_inff(), P.excl,
+                                          t, kp, st, d.paired_walk != 0);
     if (kStats) {
         ls->rays++;
         ls->boxes += st.boxes;
