@@ -491,6 +491,7 @@ def sppm_bench(args, torch, api, scenes):
     runs = [("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
             ("regen_refill16", dict(photon_kernel=2, refill=16)), ("regen_refill32", dict(photon_kernel=2, refill=32))]
     runs += [(f"ray_regen_refill{r}", dict(photon_kernel=4, refill=r)) for r in (4, 8, 16, 24, 32, 48)]
+    runs += [("lds_queue", dict(photon_kernel=5))]
     # the paper's own schedule: one bounce per thread per launch (threads = pixels, then fixed pools)
     P = sc.camera.width * sc.camera.height
     runs += [("passes_threads_per_pixel", dict(photon_kernel=3)),

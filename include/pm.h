@@ -377,8 +377,20 @@ enum { PM_GATHER_EXACT = 0, PM_GATHER_STOCHASTIC = 1 };
  * at ray granularity: persistent lanes each walk their own ray, and once
  * `refill` lanes of a wavefront wait, those lanes shade their hits and start
  * the next ray of their path (or a new path) while the others keep walking,
- * so a wavefront does not wait for its longest walk at every bounce. */
-enum { PM_PHOTON_AUTO = 0, PM_PHOTON_PER_PATH = 1, PM_PHOTON_REGEN = 2, PM_PHOTON_PASSES = 3, PM_PHOTON_RAY_REGEN = 4 };
+ * so a wavefront does not wait for its longest walk at every bounce.
+ * POOL: regeneration from a queue in LDS: each wavefront keeps up to 128
+ * started paths in its own slice of LDS; when lanes are idle and the queue
+ * is short, the whole wavefront starts 64 new paths at once and appends
+ * them, compacted by ballot rank, and every idle lane then takes a queued
+ * path, so the lanes of a bounce step stay full. */
+enum {
+    PM_PHOTON_AUTO = 0,
+    PM_PHOTON_PER_PATH = 1,
+    PM_PHOTON_REGEN = 2,
+    PM_PHOTON_PASSES = 3,
+    PM_PHOTON_RAY_REGEN = 4,
+    PM_PHOTON_POOL = 5
+};
 
 /* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)
  * and allocates the per-pixel state (N = 0, R^2 = r0^2, tau = 0, D = 0).

@@ -45,6 +45,14 @@ __global__ __launch_bounds__(kBlock) void k_photon_regen_stats(SppmDev d, uint32
     photon_regen_loop<false, true>(d, k, d.refill);
 }
 
+// Regeneration from a queue of started paths in LDS (PM_PHOTON_POOL): each
+// wavefront owns kPoolWords x kPoolSlots words of the workgroup's LDS.
+template <bool kStats>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_photon_pool(SppmDev d, uint32_t k) {
+    __shared__ uint32_t pool[kBlock / 64][kPoolWords * kPoolSlots];
+    photon_pool_loop<kStats>(d, k, pool[threadIdx.x >> 6]);
+}
+
 // Regeneration at ray granularity (PM_PHOTON_RAY_REGEN).
 __global__ __launch_bounds__(kBlock) void k_photon_stream(SppmDev d, uint32_t k) {
     photon_stream_loop(d, k, d.refill);
@@ -514,8 +522,8 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->store_factor < 1 || p->n_photons * p->store_factor > (int64_t(1) << 30))
         return set_error("store_factor must be >= 1 and the store below 2^30 photons"), PM_ERR_ARG;
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
-    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_RAY_REGEN || p->refill < 0 || p->refill > 64)
-        return set_error("photon_kernel must be 0..4 and refill 0..64"), PM_ERR_ARG;
+    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_POOL || p->refill < 0 || p->refill > 64)
+        return set_error("photon_kernel must be 0..5 and refill 0..64"), PM_ERR_ARG;
     if (p->pass_threads < 0 || p->pass_threads > (1 << 26) || p->passes < 0 || p->passes > 1024)
         return set_error("pass_threads must be in [0, 2^26] and passes in [0, 1024]"), PM_ERR_ARG;
     if (p->photon_kernel != PM_PHOTON_PASSES && (p->pass_threads != 0 || p->passes != 0))
@@ -767,6 +775,8 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         s->regen_grid_rec = (uint32_t)std::max(1, cus * std::max(1, per_cu));
         PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_stream, kBlock, 0));
         s->stream_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_pool<false>, kBlock, 0));
+        s->pool_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
     }
     dv.hp_pos = s->hp_pos;
     dv.hp_nrm = s->hp_nrm;
@@ -826,6 +836,11 @@ static int enqueue_photon(pm_sppm *s, const SppmDev &dk, uint32_t k, bool count,
             hipLaunchKernelGGL(k_photon_stream_stats, dim3(s->stream_grid), dim3(kBlock), 0, q, dk, k);
         else
             hipLaunchKernelGGL(k_photon_stream, dim3(s->stream_grid), dim3(kBlock), 0, q, dk, k);
+    } else if (dk.photon_kernel == PM_PHOTON_POOL) {
+        if (count)
+            hipLaunchKernelGGL(k_photon_pool<true>, dim3(s->pool_grid), dim3(kBlock), 0, q, dk, k);
+        else
+            hipLaunchKernelGGL(k_photon_pool<false>, dim3(s->pool_grid), dim3(kBlock), 0, q, dk, k);
     } else if (dk.photon_kernel == PM_PHOTON_REGEN) {
         if (count)
             hipLaunchKernelGGL(k_photon_regen_stats, dim3(s->regen_grid), dim3(kBlock), 0, q, dk, k);

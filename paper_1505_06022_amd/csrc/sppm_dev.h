@@ -360,6 +360,100 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
     }
 }
 
+// Photon paths from a wavefront's queue in LDS (PM_PHOTON_POOL).  Each
+// wavefront keeps up to kPoolSlots started paths in its own slice of LDS.
+// Once some lanes are idle and the queue holds fewer paths than that, the
+// whole wavefront starts 64 new paths at once (every lane emits one, so the
+// emission runs at full width) and appends them to the queue, compacted by
+// ballot rank.  Then every idle lane takes a queued path, so the lanes of a
+// bounce step are full until the path counter runs out.  Each path consumes
+// its random stream as in photon_elem, so the photons are the same.  Every
+// step advances each live path by one bounce, and a wavefront starts new
+// paths only while the counter is below n_paths, so every wavefront exits.
+// Called by every lane of a wavefront; pool is the wavefront's slice
+// (kPoolWords x kPoolSlots words), used by that wavefront only.
+constexpr int kPoolSlots = 128;  // >= 63 queued + 64 new
+constexpr int kPoolWords = 14;   // Rng (4), org (3), dir (3), phi, excl, n, b
+
+__device__ __forceinline__ void pool_put(uint32_t *pool, uint32_t slot, const PhotonPath &P) {
+    const uint32_t w[kPoolWords] = {(uint32_t)P.g.s0, (uint32_t)P.g.s1, (uint32_t)P.g.s2, (uint32_t)P.g.s3,
+                                    __float_as_uint(P.org.x), __float_as_uint(P.org.y), __float_as_uint(P.org.z),
+                                    __float_as_uint(P.dir.x), __float_as_uint(P.dir.y), __float_as_uint(P.dir.z),
+                                    __float_as_uint(P.phi), (uint32_t)P.excl, P.n, (uint32_t)P.b};
+#pragma unroll
+    for (int i = 0; i < kPoolWords; ++i) pool[i * kPoolSlots + slot] = w[i];
+}
+
+__device__ __forceinline__ void pool_get(const uint32_t *pool, uint32_t slot, PhotonPath &P) {
+    uint32_t w[kPoolWords];
+#pragma unroll
+    for (int i = 0; i < kPoolWords; ++i) w[i] = pool[i * kPoolSlots + slot];
+    P.g.s0 = (int32_t)w[0];
+    P.g.s1 = (int32_t)w[1];
+    P.g.s2 = (int32_t)w[2];
+    P.g.s3 = (int32_t)w[3];
+    P.org = v3(__uint_as_float(w[4]), __uint_as_float(w[5]), __uint_as_float(w[6]));
+    P.dir = v3(__uint_as_float(w[7]), __uint_as_float(w[8]), __uint_as_float(w[9]));
+    P.phi = __uint_as_float(w[10]);
+    P.excl = (int32_t)w[11];
+    P.n = w[12];
+    P.b = (int32_t)w[13];
+    P.last = -1;
+}
+
+template <bool kStats = false>
+__device__ __forceinline__ void photon_pool_loop(const SppmDev &d, uint32_t k, uint32_t *__restrict__ pool) {
+    PhotonPath P;
+    LaneStats ls;
+    bool live = false, exhausted = false;
+    uint32_t queued = 0;  // paths in the queue (wave-uniform)
+    for (;;) {
+        const uint64_t idle_mask = __ballot(!live);
+        const uint32_t n_idle = (uint32_t)__popcll(idle_mask);
+        if (n_idle != 0u && queued < n_idle && !exhausted) {
+            // every lane starts a path; the started ones join the queue
+            const uint32_t n = wave_fetch_add(&d.counters[2], __ballot(1), true);
+            PhotonPath Q;
+            bool ok = false;
+            if (n < d.n_paths) {
+                ok = photon_emit(d, k, n, Q);
+                if (kStats) ls.paths++;
+            }
+            exhausted = __ballot(n >= d.n_paths) != 0ull;
+            const uint64_t ok_mask = __ballot(ok);
+            if (ok) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(ok_mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)ok_mask, 0u));
+                pool_put(pool, queued + rank, Q);
+            }
+            queued += (uint32_t)__popcll(ok_mask);
+            // the queue is shared by the wavefront's lanes: order the writes before the reads below
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // idle lanes take queued paths, the last ones first
+        const uint32_t take = n_idle < queued ? n_idle : queued;
+        if (!live) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
+            if (rank < take) {
+                pool_get(pool, queued - 1u - rank, P);
+                live = true;
+            }
+        }
+        queued -= take;
+        // the slots just read may be written by the next refill
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (__ballot(live) == 0ull && exhausted && queued == 0u) break;
+        if (live) live = photon_bounce<false, kStats>(d, P, nullptr, nullptr, &ls);
+    }
+    if (kStats) {
+        wave_stats_flush(d.stats + kStatPhotonPaths, ls);
+        wave_stat_add(d.stats + kStatPhotonStored, ls.stored);
+    }
+}
+
 // Photon paths with regeneration at ray granularity: each lane walks its own
 // ray; once at least `refill` lanes of the wave wait (their ray has ended, or
 // they have no path and paths remain), those lanes shade their hits and start

@@ -20,6 +20,7 @@ struct pm_sppm {
     uint32_t regen_grid = 1;      // workgroups of the regenerating photon kernel
     uint32_t regen_grid_rec = 1;  // and of its recording variant (adjoint replay)
     uint32_t stream_grid = 1;     // workgroups of the ray-granularity regenerating photon kernel
+    uint32_t pool_grid = 1;       // workgroups of the LDS-queue photon kernel
     float phi0 = 0.0f;
     // device buffers
     int32_t *mat_type = nullptr;
