@@ -301,11 +301,8 @@ struct OrderBox {
     int32_t fine;
 };
 
-__device__ __forceinline__ uint32_t ray_bucket(const float4 *__restrict__ rays, uint32_t i, const OrderBox &ob,
-                                               int32_t force_set) {
-    const NtFloat4 a0 = __builtin_nontemporal_load((const NtFloat4 *)(rays + 2 * (size_t)i));
-    const NtFloat4 a1 = __builtin_nontemporal_load((const NtFloat4 *)(rays + 2 * (size_t)i + 1));
-    const float4 r0 = make_float4(a0.x, a0.y, a0.z, a0.w), r1 = make_float4(a1.x, a1.y, a1.z, a1.w);
+__device__ __forceinline__ uint32_t bucket_of(const float4 &r0, const float4 &r1, const OrderBox &ob,
+                                              int32_t force_set) {
     int set = force_set >= 0 ? force_set : pmd::link_set(pmd::v3(r1.x, r1.y, r1.z));
     uint32_t c[3];
     float o[3] = {r0.x, r0.y, r0.z};
@@ -323,6 +320,14 @@ __device__ __forceinline__ uint32_t ray_bucket(const float4 *__restrict__ rays, 
     return morton * 24u + (uint32_t)set * 4u + sg;
 }
 
+// Ray i's two float4 words, read once (non-temporal).
+__device__ __forceinline__ void load_ray_nt(const float4 *__restrict__ rays, uint32_t i, float4 &r0, float4 &r1) {
+    const NtFloat4 a0 = __builtin_nontemporal_load((const NtFloat4 *)(rays + 2 * (size_t)i));
+    const NtFloat4 a1 = __builtin_nontemporal_load((const NtFloat4 *)(rays + 2 * (size_t)i + 1));
+    r0 = make_float4(a0.x, a0.y, a0.z, a0.w);
+    r1 = make_float4(a1.x, a1.y, a1.z, a1.w);
+}
+
 // Wave-aggregated increment when every active lane has the same key.
 __device__ __forceinline__ uint32_t bucket_add(uint32_t *counters, uint32_t key) {
     uint32_t k0 = __shfl(key, __ffsll((unsigned long long)__ballot(1)) - 1);
@@ -330,14 +335,50 @@ __device__ __forceinline__ uint32_t bucket_add(uint32_t *counters, uint32_t key)
     return atomicAdd(&counters[key], 1u);
 }
 
+// Each thread of the bucketing kernels takes kBucketRays rays (block-strided,
+// so each step's loads stay coalesced) and issues their atomics back to back,
+// so that their round trips overlap.
+constexpr uint32_t kBucketRays = 4;
+
 __global__ __launch_bounds__(kTraceBlock) void k_ray_count(const float4 *__restrict__ rays, uint32_t n, OrderBox ob,
                                                            int32_t force_set, uint32_t *__restrict__ counts,
                                                            uint2 *__restrict__ key_rank) {
-    uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
-    if (i < n) {
-        const uint32_t key = ray_bucket(rays, i, ob, force_set);
-        const NtUint2 kr = {key, bucket_add(counts, key)};
-        __builtin_nontemporal_store(kr, (NtUint2 *)(key_rank + i));
+    const uint32_t i0 = blockIdx.x * (kTraceBlock * kBucketRays) + threadIdx.x;
+    uint32_t key[kBucketRays], rank[kBucketRays];
+    if (i0 + (kBucketRays - 1) * kTraceBlock < n) {  // every ray of the thread exists (all but the last block)
+        float4 r0[kBucketRays], r1[kBucketRays];
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) load_ray_nt(rays, i0 + j * kTraceBlock, r0[j], r1[j]);
+        bool uniform = false;  // some step's keys are equal across the wave
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) {
+            key[j] = bucket_of(r0[j], r1[j], ob, force_set);
+            uniform |= __ballot(key[j] != __shfl(key[j], __ffsll((unsigned long long)__ballot(1)) - 1)) == 0ull;
+        }
+        if (uniform) {  // wave-uniform branch
+#pragma unroll
+            for (uint32_t j = 0; j < kBucketRays; ++j) rank[j] = bucket_add(counts, key[j]);
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < kBucketRays; ++j) rank[j] = atomicAdd(&counts[key[j]], 1u);
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) {
+            const NtUint2 kr = {key[j], rank[j]};
+            __builtin_nontemporal_store(kr, (NtUint2 *)(key_rank + i0 + j * kTraceBlock));
+        }
+    } else {
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) {
+            const uint32_t i = i0 + j * kTraceBlock;
+            if (i < n) {
+                float4 r0, r1;
+                load_ray_nt(rays, i, r0, r1);
+                const uint32_t k = bucket_of(r0, r1, ob, force_set);
+                const NtUint2 kr = {k, bucket_add(counts, k)};
+                __builtin_nontemporal_store(kr, (NtUint2 *)(key_rank + i));
+            }
+        }
     }
 }
 
@@ -345,10 +386,26 @@ __global__ __launch_bounds__(kTraceBlock) void k_ray_count(const float4 *__restr
 __global__ __launch_bounds__(kTraceBlock) void k_ray_scatter(const uint2 *__restrict__ key_rank, uint32_t n,
                                                              const uint32_t *__restrict__ start,
                                                              uint32_t *__restrict__ perm) {
-    uint32_t i = blockIdx.x * kTraceBlock + threadIdx.x;
-    if (i < n) {
-        const NtUint2 kr = __builtin_nontemporal_load((const NtUint2 *)(key_rank + i));
-        perm[start[kr.x] + kr.y] = i;
+    const uint32_t i0 = blockIdx.x * (kTraceBlock * kBucketRays) + threadIdx.x;
+    if (i0 + (kBucketRays - 1) * kTraceBlock < n) {  // every ray of the thread exists (all but the last block)
+        NtUint2 kr[kBucketRays];
+        uint32_t at[kBucketRays];
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j)
+            kr[j] = __builtin_nontemporal_load((const NtUint2 *)(key_rank + i0 + j * kTraceBlock));
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) at[j] = start[kr[j].x] + kr[j].y;
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) perm[at[j]] = i0 + j * kTraceBlock;
+    } else {
+#pragma unroll
+        for (uint32_t j = 0; j < kBucketRays; ++j) {
+            const uint32_t i = i0 + j * kTraceBlock;
+            if (i < n) {
+                const NtUint2 kr = __builtin_nontemporal_load((const NtUint2 *)(key_rank + i));
+                perm[start[kr.x] + kr.y] = i;
+            }
+        }
     }
 }
 
@@ -582,7 +639,8 @@ static int bucket_rays(const pm_bvh *b, const BucketScratch &sc, const float *ra
         ob.lo[a] = b->lo[a];
         ob.scale[a] = ext > 0.0f ? (float)ob.cells / ext : 0.0f;
     }
-    const uint32_t nn = (uint32_t)n, blocks = (uint32_t)((n + kTraceBlock - 1) / kTraceBlock);
+    const uint32_t nn = (uint32_t)n;
+    const uint32_t blocks = (uint32_t)((n + kTraceBlock * kBucketRays - 1) / (kTraceBlock * kBucketRays));
     hipLaunchKernelGGL(k_fill_u32, dim3((nbk + 255) / 256), dim3(256), 0, s, counts, nbk, 0u);
     uint2 *key_rank = (uint2 *)(sc.perm + ((sc.perm_cap + 1) & ~uint64_t(1)));
     hipLaunchKernelGGL(k_ray_count, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
