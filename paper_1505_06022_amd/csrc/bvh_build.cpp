@@ -182,43 +182,76 @@ struct Ref {
     Box box;
 };
 
-// Box of the part of triangle t inside region r (its polygon clipped by the
-// six planes of r, in double), rounded outward to float; empty if none.
-Box clip_tri(const float *V, int32_t t, const double rlo[3], const double rhi[3]) {
-    double poly[9][3], tmp[9][3];
-    int n = 3;
+// A convex polygon in double: a triangle clipped by the six planes of a box
+// has at most 9 vertices, and each cut by one more plane adds at most one.
+struct Poly {
+    double v[12][3];
+    int n = 0;
+};
+
+// The part of p on one side of the plane x_a = pl (below: x_a <= pl).
+void clip_plane(const Poly &p, int a, double pl, bool below, Poly &out) {
+    out.n = 0;
+    for (int i = 0; i < p.n; ++i) {
+        const double *u = p.v[i], *w = p.v[(i + 1) % p.n];
+        const bool uin = below ? u[a] <= pl : u[a] >= pl, win = below ? w[a] <= pl : w[a] >= pl;
+        if (uin) std::memcpy(out.v[out.n++], u, sizeof(double) * 3);
+        if (uin != win) {
+            const double f = (pl - u[a]) / (w[a] - u[a]);
+            for (int c = 0; c < 3; ++c) out.v[out.n][c] = u[c] + f * (w[c] - u[c]);
+            out.v[out.n][a] = pl;
+            ++out.n;
+        }
+    }
+}
+
+// The polygon of triangle t inside the region [rlo, rhi].
+Poly tri_in_box(const float *V, int32_t t, const double rlo[3], const double rhi[3]) {
+    Poly p, q;
+    p.n = 3;
     for (int k = 0; k < 3; ++k)
-        for (int a = 0; a < 3; ++a) poly[k][a] = V[9 * (size_t)t + 3 * k + a];
-    for (int a = 0; a < 3 && n; ++a)
-        for (int side = 0; side < 2 && n; ++side) {
-            const double pl = side ? rhi[a] : rlo[a];
-            int m = 0;
-            for (int i = 0; i < n; ++i) {
-                const double *p = poly[i], *q = poly[(i + 1) % n];
-                const bool pin = side ? p[a] <= pl : p[a] >= pl, qin = side ? q[a] <= pl : q[a] >= pl;
-                if (pin) std::memcpy(tmp[m++], p, sizeof(double) * 3);
-                if (pin != qin) {
-                    const double f = (pl - p[a]) / (q[a] - p[a]);
-                    for (int c = 0; c < 3; ++c) tmp[m][c] = p[c] + f * (q[c] - p[c]);
-                    tmp[m][a] = pl;
-                    ++m;
-                }
-            }
-            std::memcpy(poly, tmp, sizeof(double) * 3 * (size_t)m);
-            n = m;
+        for (int a = 0; a < 3; ++a) p.v[k][a] = V[9 * (size_t)t + 3 * k + a];
+    for (int a = 0; a < 3 && p.n; ++a) {
+        double lo = p.v[0][a], hi = lo;
+        for (int i = 1; i < p.n; ++i) lo = std::min(lo, p.v[i][a]), hi = std::max(hi, p.v[i][a]);
+        if (lo < rlo[a]) {  // only planes that cut the polygon
+            clip_plane(p, a, rlo[a], false, q);
+            p = q;
         }
+        if (hi > rhi[a]) {
+            clip_plane(p, a, rhi[a], true, q);
+            p = q;
+        }
+    }
+    return p;
+}
+
+// The box of p within the region [rlo, rhi], rounded outward to float (so it
+// contains the exact part); empty if p is.
+Box poly_box(const Poly &p, const double rlo[3], const double rhi[3]) {
     Box b;
-    for (int i = 0; i < n; ++i)
+    if (p.n == 0) return b;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < p.n; ++i)
         for (int a = 0; a < 3; ++a) {
-            // clamp to the region, then round outward to float
-            const double x = std::min(std::max(poly[i][a], rlo[a]), rhi[a]);
-            float lo = (float)x, hi = lo;
-            if ((double)lo > x) lo = std::nextafter(lo, -INFINITY);
-            if ((double)hi < x) hi = std::nextafter(hi, INFINITY);
-            b.lo[a] = std::min(b.lo[a], lo);
-            b.hi[a] = std::max(b.hi[a], hi);
+            const double x = std::min(std::max(p.v[i][a], rlo[a]), rhi[a]);
+            lo[a] = std::min(lo[a], x);
+            hi[a] = std::max(hi[a], x);
         }
+    for (int a = 0; a < 3; ++a) {  // rounding is monotone: round the extremes outward
+        float l = (float)lo[a], h = (float)hi[a];
+        if ((double)l > lo[a]) l = std::nextafter(l, -INFINITY);
+        if ((double)h < hi[a]) h = std::nextafter(h, INFINITY);
+        b.lo[a] = l;
+        b.hi[a] = h;
+    }
     return b;
+}
+
+// Box of the part of triangle t inside region [rlo, rhi] (clipped in double,
+// rounded outward to float); empty if none.
+Box clip_tri(const float *V, int32_t t, const double rlo[3], const double rhi[3]) {
+    return poly_box(tri_in_box(V, t, rlo, rhi), rlo, rhi);
 }
 
 double overlap_area(const Box &a, const Box &b) {
@@ -315,12 +348,21 @@ struct SplitBuilder {
                         bb[b0].grow(r.box);
                         continue;
                     }
+                    // the triangle's part in the reference's box, cut at each bin boundary in turn
                     double rlo[3], rhi[3];
                     for (int k = 0; k < 3; ++k) rlo[k] = r.box.lo[k], rhi[k] = r.box.hi[k];
-                    for (int b = b0; b <= b1; ++b) {
+                    Poly rest = tri_in_box(V, r.tri, rlo, rhi), part, next;
+                    for (int b = b0; b <= b1 && rest.n; ++b) {
                         rlo[a] = std::max((double)r.box.lo[a], plane(b));
                         rhi[a] = std::min((double)r.box.hi[a], plane(b + 1));
-                        bb[b].grow(clip_tri(V, r.tri, rlo, rhi));
+                        if (b == b1) {
+                            bb[b].grow(poly_box(rest, rlo, rhi));
+                            break;
+                        }
+                        clip_plane(rest, a, rhi[a], true, part);
+                        clip_plane(rest, a, rhi[a], false, next);
+                        bb[b].grow(poly_box(part, rlo, rhi));
+                        rest = next;
                     }
                 }
                 Box acc;
