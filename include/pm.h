@@ -80,8 +80,11 @@ typedef struct {
                           split leaves children whose boxes overlap by more
                           than split_alpha x the scene box's surface area;
                           a triangle may then be referenced by several
-                          leaves (n_refs > n_tri).  0 = none (default);
-                          range [0, 1] */
+                          leaves (n_refs > n_tri; spatial splits stop
+                          adding references at 8 x n_tri, each subtree
+                          holding its share of that allowance, so the
+                          build stays deterministic).  0 = none
+                          (default); range [0, 1] */
 } pm_bvh_opts;
 
 /* BVH builders.  HOST_SAH: binned SAH on the host threads, then threading and

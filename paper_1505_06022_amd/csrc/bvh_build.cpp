@@ -272,7 +272,10 @@ struct SplitBuilder {
 
     // Builds the subtree of refs into out (node indices local to out) with its
     // leaves' triangle indices appended to leaf (leaf starts local to leaf).
-    int32_t build(std::vector<Ref> &refs, int depth, std::vector<TNode> &out, std::vector<int32_t> &leaf) {
+    // budget: references this subtree may add by spatial splits (its share of
+    // the whole build's allowance, so the result does not depend on threads)
+    int32_t build(std::vector<Ref> &refs, int depth, int64_t budget, std::vector<TNode> &out,
+                  std::vector<int32_t> &leaf) {
         int32_t ni = (int32_t)out.size();
         out.emplace_back();
         const int32_t count = (int32_t)refs.size();
@@ -332,7 +335,7 @@ struct SplitBuilder {
         double sbest = INFINITY;
         int saxis = -1;
         double splane = 0.0;
-        if (best_axis >= 0 && overlap_area(best_l, best_r) > min_overlap) {
+        if (budget > 0 && best_axis >= 0 && overlap_area(best_l, best_r) > min_overlap) {
             for (int a = 0; a < 3; ++a) {
                 const double lo = nb.lo[a], ext = (double)nb.hi[a] - lo;
                 if (!(ext > 0.0)) continue;
@@ -405,8 +408,9 @@ struct SplitBuilder {
                     if (br.lo[0] <= br.hi[0]) R.push_back({r.tri, br});
                 }
             }
-            // a spatial split must shrink both sides, or the object split is taken
-            if (L.empty() || R.empty() || (int32_t)L.size() == count || (int32_t)R.size() == count) {
+            // a spatial split must shrink both sides and stay within the budget, or the object split is taken
+            if (L.empty() || R.empty() || (int32_t)L.size() == count || (int32_t)R.size() == count ||
+                (int64_t)(L.size() + R.size()) - count > budget) {
                 L.clear();
                 R.clear();
                 saxis = -1;
@@ -431,13 +435,17 @@ struct SplitBuilder {
                 }
             }
         }
+        // the budget left is shared by the children in proportion to their sizes
+        const int64_t left_budget = budget - std::max<int64_t>(0, (int64_t)(L.size() + R.size()) - count);
+        const int64_t bl = left_budget * (int64_t)L.size() / (int64_t)(L.size() + R.size()), br = left_budget - bl;
         std::vector<Ref>().swap(refs);
         int32_t l, r;
         if (depth < par_depth && count > 50000) {
             std::vector<TNode> right_nodes;
             std::vector<int32_t> right_leaf;
-            auto fut = std::async(std::launch::async, [&]() { return build(R, depth + 1, right_nodes, right_leaf); });
-            l = build(L, depth + 1, out, leaf);
+            auto fut =
+                std::async(std::launch::async, [&]() { return build(R, depth + 1, br, right_nodes, right_leaf); });
+            l = build(L, depth + 1, bl, out, leaf);
             fut.get();
             const int32_t off = (int32_t)out.size(), loff = (int32_t)leaf.size();
             for (auto &nd : right_nodes) {
@@ -452,8 +460,8 @@ struct SplitBuilder {
             leaf.insert(leaf.end(), right_leaf.begin(), right_leaf.end());
             r = off;
         } else {
-            l = build(L, depth + 1, out, leaf);
-            r = build(R, depth + 1, out, leaf);
+            l = build(L, depth + 1, bl, out, leaf);
+            r = build(R, depth + 1, br, out, leaf);
         }
         out[ni].left = l;
         out[ni].right = r;
@@ -461,6 +469,9 @@ struct SplitBuilder {
         return ni;
     }
 };
+
+// Spatial splits may add at most this many references per triangle in all.
+constexpr int64_t kMaxExtraRefs = 7;
 
 inline uint32_t fbits(float f) {
     uint32_t u;
@@ -531,7 +542,7 @@ bool build_bvh_host(const float *verts, const uint32_t *mats, int64_t n_tri, con
         for (int64_t i = 0; i < n_tri; ++i) refs[i] = Ref{(int32_t)i, b.tb[i]};
         order.clear();
         order.reserve((size_t)(n_tri + n_tri / 2));
-        sb.build(refs, 0, tree, order);
+        sb.build(refs, 0, kMaxExtraRefs * n_tri, tree, order);
         if ((int64_t)order.size() >= (int64_t(1) << 28)) {
             err = "spatial splits made 2^28 or more triangle records: raise split_alpha";
             return false;
