@@ -237,7 +237,7 @@ PM_API int pm_trace_rays_ex(const pm_bvh *bvh, const float *rays, int64_t n, int
  * arrays, about 60 MB) is set aside on every device the library's code is
  * loaded on and held until the process ends; its address is looked up on the
  * first call on each device.  Every call on one device shares it and it keeps
- * the last call's contents (the bucket counters are cleared by a kernel at
+ * the last call's contents (the bucket counts are rewritten by kernels at
  * the start of each call): calls that overlap on one device, on different
  * streams or host threads, race and give wrong results.  Results equal those
  * of pm_trace_rays_ex with the same options.  The BVH must live on the current

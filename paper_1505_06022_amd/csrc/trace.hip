@@ -409,6 +409,90 @@ __global__ __launch_bounds__(kTraceBlock) void k_ray_scatter(const uint2 *__rest
     }
 }
 
+// Coarse bucketing without global atomics.  Each of up to kHistGroups
+// workgroups counts one contiguous chunk of the rays in a histogram in LDS
+// (the LDS atomic gives each ray its rank among the chunk's rays of its
+// bucket) and writes it as one row of a [chunk][bucket] table.  A scan down
+// each column turns the table into each chunk's offset within each bucket and
+// gives the bucket totals; the bucket scan turns those into bucket starts; the
+// scatter places ray i at start[bucket] + offset[chunk][bucket] + rank.  The
+// (bucket, rank) pairs carry the chunk in the bucket word's upper bits.
+constexpr uint32_t kHistGroups = 64;
+constexpr uint32_t kHistBlock = 1024;
+constexpr uint32_t kHistRays = 4;  // rays per thread whose loads go out together
+constexpr uint32_t kHistChunkBits = 15;  // bucket < 2^15 in the packed word
+static_assert(kOrderBucketsCoarse <= (1u << kHistChunkBits), "coarse bucket exceeds its packed field");
+
+__global__ __launch_bounds__(kHistBlock) void k_hist_count(const float4 *__restrict__ rays, uint32_t n, uint32_t chunk,
+                                                           OrderBox ob, int32_t force_set,
+                                                           uint32_t *__restrict__ table, uint2 *__restrict__ key_rank) {
+    __shared__ uint32_t h[kOrderBucketsCoarse];
+    for (uint32_t b = threadIdx.x; b < kOrderBucketsCoarse; b += kHistBlock) h[b] = 0u;
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    const uint32_t tag = blockIdx.x << kHistChunkBits;
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += kHistBlock * kHistRays) {
+        float4 r0[kHistRays], r1[kHistRays];
+#pragma unroll
+        for (uint32_t j = 0; j < kHistRays; ++j)
+            if (i + j * kHistBlock < i1) load_ray_nt(rays, i + j * kHistBlock, r0[j], r1[j]);
+#pragma unroll
+        for (uint32_t j = 0; j < kHistRays; ++j) {
+            const uint32_t ij = i + j * kHistBlock;
+            if (ij < i1) {
+                const uint32_t key = bucket_of(r0[j], r1[j], ob, force_set);
+                const NtUint2 kr = {key | tag, atomicAdd(&h[key], 1u)};
+                __builtin_nontemporal_store(kr, (NtUint2 *)(key_rank + ij));
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *row = table + (size_t)blockIdx.x * kOrderBucketsCoarse;
+    for (uint32_t b = threadIdx.x; b < kOrderBucketsCoarse; b += kHistBlock) row[b] = h[b];
+}
+
+// Column b of the table: exclusive running sums over the chunks, in place,
+// and the bucket's total in counts[b].
+__global__ __launch_bounds__(kTraceBlock) void k_hist_columns(uint32_t *__restrict__ table, uint32_t groups,
+                                                              uint32_t *__restrict__ counts) {
+    const uint32_t b = blockIdx.x * kTraceBlock + threadIdx.x;
+    if (b >= kOrderBucketsCoarse) return;
+    uint32_t sum = 0u;
+    for (uint32_t g0 = 0; g0 < groups; g0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j)
+            v[j] = g0 + j < groups ? table[(size_t)(g0 + j) * kOrderBucketsCoarse + b] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j) {
+            if (g0 + j < groups) table[(size_t)(g0 + j) * kOrderBucketsCoarse + b] = sum;
+            sum += v[j];
+        }
+    }
+    counts[b] = sum;
+}
+
+// start[bucket] + offset[chunk][bucket] + rank < n: the offsets of a bucket's
+// chunks and the ranks within a chunk count the bucket's rays without gaps.
+__global__ __launch_bounds__(kTraceBlock) void k_hist_scatter(const uint2 *__restrict__ key_rank, uint32_t n,
+                                                              const uint32_t *__restrict__ start,
+                                                              const uint32_t *__restrict__ table,
+                                                              uint32_t *__restrict__ perm) {
+    const uint32_t i0 = blockIdx.x * (kTraceBlock * kBucketRays) + threadIdx.x;
+    NtUint2 kr[kBucketRays];
+#pragma unroll
+    for (uint32_t j = 0; j < kBucketRays; ++j)
+        if (i0 + j * kTraceBlock < n) kr[j] = __builtin_nontemporal_load((const NtUint2 *)(key_rank + i0 + j * kTraceBlock));
+#pragma unroll
+    for (uint32_t j = 0; j < kBucketRays; ++j) {
+        const uint32_t i = i0 + j * kTraceBlock;
+        if (i < n) {
+            const uint32_t key = kr[j].x & ((1u << kHistChunkBits) - 1u), g = kr[j].x >> kHistChunkBits;
+            perm[start[key] + table[(size_t)g * kOrderBucketsCoarse + key] + kr[j].y] = i;
+        }
+    }
+}
+
 // Rays taken in the order of perm.
 template <bool kStats, int kWalk>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_perm(pmd::Bvh bvh, const float4 *__restrict__ rays,
@@ -606,6 +690,12 @@ struct BucketScratch {
     uint32_t *order;
 };
 constexpr size_t kOrderWords = (3 * (size_t)kOrderBucketsFine + 1 + kOrderBucketsFine / 4096 + 1 + 63) & ~size_t(63);
+// The coarse histogram table sits after the coarse bucket arrays (counts,
+// starts, fill cursors, scan block sums), within the fine arrays' words.
+constexpr size_t kOrderTableOffset = kOrderBucketsCoarse / 4096 + 1;
+static_assert(3 * (size_t)kOrderBucketsCoarse + 1 + kOrderTableOffset + (size_t)kHistGroups * kOrderBucketsCoarse <=
+                  kOrderWords,
+              "coarse histogram table exceeds the bucket scratch");
 
 constexpr size_t perm_words(uint64_t cap) { return 3 * (size_t)cap + 2; }
 
@@ -641,13 +731,27 @@ static int bucket_rays(const pm_bvh *b, const BucketScratch &sc, const float *ra
     }
     const uint32_t nn = (uint32_t)n;
     const uint32_t blocks = (uint32_t)((n + kTraceBlock * kBucketRays - 1) / (kTraceBlock * kBucketRays));
-    hipLaunchKernelGGL(k_fill_u32, dim3((nbk + 255) / 256), dim3(256), 0, s, counts, nbk, 0u);
     uint2 *key_rank = (uint2 *)(sc.perm + ((sc.perm_cap + 1) & ~uint64_t(1)));
-    hipLaunchKernelGGL(k_ray_count, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
-                       counts, key_rank);
-    launch_bucket_scan(counts, start, fill, bsum, nbk, s);
-    hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const uint2 *)key_rank, nn,
-                       (const uint32_t *)start, sc.perm);
+    if (reorder != 2) {
+        // histograms in LDS: one chunk of at least 4096 rays per workgroup, at most kHistGroups chunks
+        uint32_t *table = bsum + kOrderTableOffset;
+        const uint32_t groups = (uint32_t)std::min<int64_t>(kHistGroups, (n + 4095) / 4096);
+        const uint32_t chunk = (uint32_t)((n + groups - 1) / groups);
+        hipLaunchKernelGGL(k_hist_count, dim3(groups), dim3(kHistBlock), 0, s, (const float4 *)rays, nn, chunk, ob,
+                           link_set, table, key_rank);
+        hipLaunchKernelGGL(k_hist_columns, dim3((nbk + kTraceBlock - 1) / kTraceBlock), dim3(kTraceBlock), 0, s, table,
+                           groups, counts);
+        launch_bucket_scan(counts, start, fill, bsum, nbk, s);
+        hipLaunchKernelGGL(k_hist_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const uint2 *)key_rank, nn,
+                           (const uint32_t *)start, (const uint32_t *)table, sc.perm);
+    } else {
+        hipLaunchKernelGGL(k_fill_u32, dim3((nbk + 255) / 256), dim3(256), 0, s, counts, nbk, 0u);
+        hipLaunchKernelGGL(k_ray_count, dim3(blocks), dim3(kTraceBlock), 0, s, (const float4 *)rays, nn, ob, link_set,
+                           counts, key_rank);
+        launch_bucket_scan(counts, start, fill, bsum, nbk, s);
+        hipLaunchKernelGGL(k_ray_scatter, dim3(blocks), dim3(kTraceBlock), 0, s, (const uint2 *)key_rank, nn,
+                           (const uint32_t *)start, sc.perm);
+    }
     PM_HIP(hipGetLastError());
     return PM_OK;
 }
