@@ -817,7 +817,7 @@ def main():
                             for vn, vt, n in tb["per_batch"]],
         "roofline": {"bound": "hbm", "achieved": round(tb["achieved"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(tb["achieved"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "pm_trace_rays_multi call: k_ray_count + scan + k_ray_scatter, then one launch of "
+                     "kernel": "pm_trace_rays_multi call: k_hist_count + column and bucket scans + k_hist_scatter, then one launch of "
                                "k_trace_perm_then_tiles (the incoherent batch's postponed walk, then the camera "
                                "batch's packets over 8x8 pixel tiles)",
                      "bytes_per_launch": tb["per_launch_bytes"],
