@@ -70,6 +70,29 @@ def test_random_scenes_ragged_sizes(torch_cuda, oracle_lib, n_tri, n_rays, seed)
     _compare(h, t, h_ref, t_ref)
 
 
+@pytest.mark.parametrize("n_rays,one_bucket", [(4096, False), (4097, False), (262145, False), (50000, True)])
+def test_bucketing_chunk_boundaries_and_one_bucket(torch_cuda, oracle_lib, n_rays, one_bucket):
+    """The coarse bucketing counts the rays in up to 64 chunks of at least 4096 (one histogram in LDS per chunk):
+    one chunk, a second chunk of one ray, 64 chunks with a short last one, and rays that all share one bucket
+    (one origin, directions around +y).  Bucketed walks equal the per-ray walk, and sampled rays the brute force."""
+    _log(f"case: bucketing n_rays={n_rays} one_bucket={one_bucket}")
+    sc = scenes.small_soup(20000, 11, spread=0.03)
+    bvh = api.build_bvh(sc.verts, sc.tri_mat)
+    rays = scenes.random_rays(n_rays, 11)
+    if one_bucket:
+        rng = np.random.default_rng(11)
+        d = np.stack([rng.uniform(-0.5, 0.5, n_rays), np.ones(n_rays), rng.uniform(-0.5, 0.5, n_rays)], 1)
+        rays[:, 0:3] = np.array([0.5, 0.05, 0.5], np.float32)
+        rays[:, 4:7] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    h, t = _gpu_trace(torch_cuda, bvh, rays, kernel=1)
+    for kw in (dict(reorder=1), dict(kernel=4, refill=32, reorder=1, block=64)):
+        hb, tb = _gpu_trace(torch_cuda, bvh, rays, **kw)
+        assert np.array_equal(h, hb) and np.array_equal(t, tb)
+    pick = np.random.default_rng(12).choice(n_rays, min(n_rays, 2048), replace=False)
+    h_ref, t_ref = oracle_lib.trace_brute_force(sc.verts, rays[pick])
+    _compare(h[pick], t[pick], h_ref, t_ref)
+
+
 def test_every_link_set_and_stats_mode_agree(torch_cuda, oracle_lib):
     _log("case: forced link sets 0..5 and counters")
     sc = scenes.small_soup(3000, 7, spread=0.03)
