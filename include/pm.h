@@ -322,7 +322,8 @@ typedef struct {
                                   max_photon_bounces of replay scratch);
                                   needs gather_mode 0, at most 256 materials
                                   and fewer than 2^24 pixels */
-    int32_t photon_kernel;    /* PM_PHOTON_*: 0 = default (regeneration) */
+    int32_t photon_kernel;    /* PM_PHOTON_*: 0 = default (two-phase
+                                 regeneration; a batch member: regeneration) */
     int32_t refill;           /* regeneration: idle lanes of a wave that
                                  trigger taking new paths (1..64; 0 = 32) */
     int32_t single_link_set;  /* 0: each ray walks the link set of its
@@ -385,14 +386,23 @@ enum { PM_GATHER_EXACT = 0, PM_GATHER_STOCHASTIC = 1 };
  * started paths in its own slice of LDS; when lanes are idle and the queue
  * is short, the whole wavefront starts 64 new paths at once and appends
  * them, compacted by ballot rank, and every idle lane then takes a queued
- * path, so the lanes of a bounce step stay full. */
+ * path, so the lanes of a bounce step stay full.
+ * TWO_PHASE (the default of single-scene handles): regeneration in two
+ * launches.  The first stops once the path counter has run out and at most
+ * 32 lanes of a wavefront still hold a path; those paths wait in a queue in
+ * device memory (56 B per path, at most one per lane of the launch) and the
+ * second launch continues them.  A path that reflects inside a glass object
+ * can run to max_photon_bounces, so the last paths of a pass leave the device
+ * almost idle: on a pipelined handle the second launch runs on a stream of
+ * its own, beside the next iteration's first launch. */
 enum {
     PM_PHOTON_AUTO = 0,
     PM_PHOTON_PER_PATH = 1,
     PM_PHOTON_REGEN = 2,
     PM_PHOTON_PASSES = 3,
     PM_PHOTON_RAY_REGEN = 4,
-    PM_PHOTON_POOL = 5
+    PM_PHOTON_POOL = 5,
+    PM_PHOTON_TWO_PHASE = 6
 };
 
 /* Create a renderer: uploads the scene (building a BVH if desc->bvh is NULL)

@@ -94,7 +94,7 @@ class SppmStats(C.Structure):
                [(n, C.c_double) for n in ("ms_eye", "ms_photon", "ms_grid", "ms_gather", "ms_update", "ms_iteration")]
 
 
-PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN, PHOTON_PASSES, PHOTON_RAY_REGEN, PHOTON_POOL = 0, 1, 2, 3, 4, 5
+PHOTON_AUTO, PHOTON_PER_PATH, PHOTON_REGEN, PHOTON_PASSES, PHOTON_RAY_REGEN, PHOTON_POOL, PHOTON_TWO_PHASE = range(7)
 GATHER_EXACT, GATHER_STOCHASTIC = 0, 1
 
 

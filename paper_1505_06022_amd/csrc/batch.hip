@@ -463,7 +463,7 @@ int batch_create(const pm_scene_desc *const *descs, const pm_sppm_params *const 
         if (rc) return set_error("scene " + std::to_string(i) + ": " + last_error()), rc;
         if (params[i]->gather_mode != PM_GATHER_EXACT)
             return set_error("scene " + std::to_string(i) + ": a batch uses the exact gather"), PM_ERR_ARG;
-        if (params[i]->photon_kernel == PM_PHOTON_PASSES)
+        if (params[i]->photon_kernel == PM_PHOTON_PASSES || params[i]->photon_kernel == PM_PHOTON_TWO_PHASE)
             return set_error("scene " + std::to_string(i) + ": a batch schedules its own photon stage"), PM_ERR_ARG;
         if (params[i]->profile != 0)
             return set_error("scene " + std::to_string(i) + ": profiling applies to single-scene handles"), PM_ERR_ARG;

@@ -45,6 +45,19 @@ __global__ __launch_bounds__(kBlock) void k_photon_regen_stats(SppmDev d, uint32
     photon_regen_loop<false, true>(d, k, d.refill);
 }
 
+// Two-phase photon pass (PM_PHOTON_TWO_PHASE): regeneration that sets the
+// last paths of each wavefront aside once the path counter has run out, then
+// regeneration over the paths set aside.
+template <bool kStats>
+__global__ __launch_bounds__(kBlock) void k_photon_head(SppmDev d, uint32_t k, PathQueue q) {
+    photon_regen_loop<false, kStats, true, false>(d, k, d.refill, nullptr, nullptr, q);
+}
+
+template <bool kStats>
+__global__ __launch_bounds__(kBlock) void k_photon_tail(SppmDev d, uint32_t k, PathQueue q) {
+    photon_regen_loop<false, kStats, false, true>(d, k, d.refill, nullptr, nullptr, q);
+}
+
 // Regeneration from a queue of started paths in LDS (PM_PHOTON_POOL): each
 // wavefront owns kPoolWords x kPoolSlots words of the workgroup's LDS.
 template <bool kStats>
@@ -473,7 +486,8 @@ void sppm_free(pm_sppm *s) {
                     s->hp_nrm, s->store, s->store2, s->sorted, s->counters, s->r2max, s->cell_count, s->cell_start,
                     s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->adj_tab2,
                     s->mat_tab2, s->grad_mat,
-                    s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->stats, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank};
+                    s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->stats, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank,
+                    s->queue_mem};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : s->prof_ev)
@@ -483,6 +497,9 @@ void sppm_free(pm_sppm *s) {
         if (s->ev_scat[i]) (void)hipEventDestroy(s->ev_scat[i]);
     }
     if (s->phs) (void)hipStreamDestroy(s->phs);
+    for (int i = 0; i < 2; ++i)
+        if (s->ev_head[i]) (void)hipEventDestroy(s->ev_head[i]);
+    if (s->tails) (void)hipStreamDestroy(s->tails);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
     if (s->side) (void)hipStreamDestroy(s->side);
@@ -522,8 +539,8 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->store_factor < 1 || p->n_photons * p->store_factor > (int64_t(1) << 30))
         return set_error("store_factor must be >= 1 and the store below 2^30 photons"), PM_ERR_ARG;
     if (d->bvh && d->bvh->n_tri != d->n_tri) return set_error("bvh was built over a different triangle count"), PM_ERR_ARG;
-    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_POOL || p->refill < 0 || p->refill > 64)
-        return set_error("photon_kernel must be 0..5 and refill 0..64"), PM_ERR_ARG;
+    if (p->photon_kernel < 0 || p->photon_kernel > PM_PHOTON_TWO_PHASE || p->refill < 0 || p->refill > 64)
+        return set_error("photon_kernel must be 0..6 and refill 0..64"), PM_ERR_ARG;
     if (p->pass_threads < 0 || p->pass_threads > (1 << 26) || p->passes < 0 || p->passes > 1024)
         return set_error("pass_threads must be in [0, 2^26] and passes in [0, 1024]"), PM_ERR_ARG;
     if (p->photon_kernel != PM_PHOTON_PASSES && (p->pass_threads != 0 || p->passes != 0))
@@ -547,6 +564,14 @@ int sppm_validate(const pm_scene_desc *d, const pm_sppm_params *p) {
     if (p->record_iterations > 0 && (int64_t)d->width * d->height >= (int64_t(1) << 24))
         return set_error("the adjoint supports images below 2^24 pixels"), PM_ERR_ARG;
     return PM_OK;
+}
+
+// The photon schedule a handle runs: the default is the two-phase pass on
+// single-scene handles and regeneration for a batch member (whose photon
+// stage the batch schedules).
+static int32_t photon_kernel_of(const pm_sppm_params *p, bool own_grid) {
+    if (p->photon_kernel != PM_PHOTON_AUTO) return p->photon_kernel;
+    return own_grid ? PM_PHOTON_TWO_PHASE : PM_PHOTON_REGEN;
 }
 
 int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t st, bool own_grid, pm_sppm **out) {
@@ -627,6 +652,10 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         for (int i = 0; i < 2; ++i) {
             PM_HIPF(hipEventCreateWithFlags(&s->ev_ph[i], hipEventDisableTiming));
             PM_HIPF(hipEventCreateWithFlags(&s->ev_scat[i], hipEventDisableTiming));
+        }
+        if (photon_kernel_of(p, own_grid) == PM_PHOTON_TWO_PHASE) {
+            PM_HIPF(hipStreamCreateWithFlags(&s->tails, hipStreamNonBlocking));
+            for (int i = 0; i < 2; ++i) PM_HIPF(hipEventCreateWithFlags(&s->ev_head[i], hipEventDisableTiming));
         }
     }
     if (own_grid) {
@@ -755,7 +784,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     dv.P = s->P;
     dv.mask = T - 1u;
     dv.table_off = 0;
-    dv.photon_kernel = p->photon_kernel == PM_PHOTON_AUTO ? PM_PHOTON_REGEN : p->photon_kernel;
+    dv.photon_kernel = photon_kernel_of(p, own_grid);
     dv.refill = p->refill > 0 ? (uint32_t)p->refill : 32u;
     dv.force_set = p->single_link_set - 1;
     // Paired node requests pay off on one large scene (2.65 -> 2.55 ms per
@@ -777,6 +806,27 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         s->stream_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
         PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_pool<false>, kBlock, 0));
         s->pool_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_head<false>, kBlock, 0));
+        s->head_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_tail<false>, kBlock, 0));
+        s->tail_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+    }
+    if (dv.photon_kernel == PM_PHOTON_TWO_PHASE) {
+        // per store parity: a queue slot for every lane of the first launch
+        // (each parks at most one path), then the queue's two counters
+        const uint32_t S = (uint32_t)std::min<int64_t>(p->n_photons, (int64_t)s->head_grid * kBlock);
+        const size_t per = (size_t)56 * S + 256;
+        PM_HIPF(hipMalloc(&s->queue_mem, 2 * per));
+        for (int i = 0; i < 2; ++i) {
+            char *m = (char *)s->queue_mem + i * per;
+            PathQueue &q = s->queue[i];
+            q.s.g = (int4 *)m;
+            q.s.o = (float4 *)(m + (size_t)16 * S);
+            q.s.w = (float4 *)(m + (size_t)32 * S);
+            q.s.nb = (uint2 *)(m + (size_t)48 * S);
+            q.s.S = S;
+            q.cnt = (uint32_t *)(m + (size_t)56 * S);
+        }
     }
     dv.hp_pos = s->hp_pos;
     dv.hp_nrm = s->hp_nrm;
@@ -827,11 +877,28 @@ static SppmDev iteration_view(const pm_sppm *s, uint32_t k) {
     return dk;
 }
 
-// The photon pass of iteration k (its counters cleared first) on stream q.
-static int enqueue_photon(pm_sppm *s, const SppmDev &dk, uint32_t k, bool count, hipStream_t q) {
+// The photon pass of iteration k (its counters cleared first) on stream q;
+// the two-phase pass's second launch goes on stream tq (after the first).
+// The pass has ended once tq's work enqueued so far is done.
+static int enqueue_photon(pm_sppm *s, const SppmDev &dk, uint32_t k, bool count, hipStream_t q, hipStream_t tq) {
     const uint32_t np = (uint32_t)s->prm.n_photons;
     hipLaunchKernelGGL(k_photon_begin, dim3(1), dim3(64), 0, q, dk);
-    if (dk.photon_kernel == PM_PHOTON_RAY_REGEN) {
+    if (dk.photon_kernel == PM_PHOTON_TWO_PHASE) {
+        const PathQueue &pq = s->queue[s->store2 ? (k & 1u) : 0u];
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, q, pq.cnt, 2u, 0u);
+        if (count)
+            hipLaunchKernelGGL(k_photon_head<true>, dim3(s->head_grid), dim3(kBlock), 0, q, dk, k, pq);
+        else
+            hipLaunchKernelGGL(k_photon_head<false>, dim3(s->head_grid), dim3(kBlock), 0, q, dk, k, pq);
+        if (tq != q) {
+            PM_HIP(hipEventRecord(s->ev_head[k & 1u], q));
+            PM_HIP(hipStreamWaitEvent(tq, s->ev_head[k & 1u], 0));
+        }
+        if (count)
+            hipLaunchKernelGGL(k_photon_tail<true>, dim3(s->tail_grid), dim3(kBlock), 0, tq, dk, k, pq);
+        else
+            hipLaunchKernelGGL(k_photon_tail<false>, dim3(s->tail_grid), dim3(kBlock), 0, tq, dk, k, pq);
+    } else if (dk.photon_kernel == PM_PHOTON_RAY_REGEN) {
         if (count)
             hipLaunchKernelGGL(k_photon_stream_stats, dim3(s->stream_grid), dim3(kBlock), 0, q, dk, k);
         else
@@ -885,20 +952,23 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
     hipEvent_t *ev = s->prof_ev;
     const uint32_t k0 = (uint32_t)s->K;
     int rc;
+    // the two-phase pass's second launch runs on its own stream, so that the
+    // next pass's first launch can start beside it
+    hipStream_t tq = s->tails ? s->tails : s->phs;
     if (pipe) {
         PM_HIP(hipEventRecord(s->ev_fork, st));
         PM_HIP(hipStreamWaitEvent(s->phs, s->ev_fork, 0));
-        if ((rc = enqueue_photon(s, iteration_view(s, k0), k0, count, s->phs))) return rc;
-        PM_HIP(hipEventRecord(s->ev_ph[k0 & 1u], s->phs));
+        if ((rc = enqueue_photon(s, iteration_view(s, k0), k0, count, s->phs, tq))) return rc;
+        PM_HIP(hipEventRecord(s->ev_ph[k0 & 1u], tq));
     }
     for (int32_t it = 0; it < n_iter; ++it) {
         const uint32_t k = k0 + (uint32_t)it;
         const SppmDev dk = iteration_view(s, k);
         if (pipe && it + 1 < n_iter) {
-            // the next photon pass refills the store that the scatter of k - 1 read
+            // the next photon pass refills the store (and queue) that the scatter of k - 1 read
             if (it >= 1) PM_HIP(hipStreamWaitEvent(s->phs, s->ev_scat[(k + 1u) & 1u], 0));
-            if ((rc = enqueue_photon(s, iteration_view(s, k + 1u), k + 1u, count, s->phs))) return rc;
-            PM_HIP(hipEventRecord(s->ev_ph[(k + 1u) & 1u], s->phs));
+            if ((rc = enqueue_photon(s, iteration_view(s, k + 1u), k + 1u, count, s->phs, tq))) return rc;
+            PM_HIP(hipEventRecord(s->ev_ph[(k + 1u) & 1u], tq));
         }
         if (timed) PM_HIP(hipEventRecord(ev[0], st));
         // eye pass and R_max on the side stream, beside the photon pass: they
@@ -918,7 +988,7 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
         PM_HIP(hipEventRecord(s->ev_join, s->side));
         if (!pipe) {
             if (timed) PM_HIP(hipEventRecord(ev[3], st));
-            if ((rc = enqueue_photon(s, dk, k, count, st))) return rc;
+            if ((rc = enqueue_photon(s, dk, k, count, st, st))) return rc;
             if (timed) PM_HIP(hipEventRecord(ev[4], st));
         }
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);

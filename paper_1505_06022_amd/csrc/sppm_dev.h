@@ -316,6 +316,64 @@ __device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32
     photon_finish<kRecord>(d, P, mat_tab);
 }
 
+// Path state in device memory (56 B per slot, structure of arrays), used by
+// the one-bounce-per-pass schedule and by the two-phase photon pass.
+constexpr uint32_t kSlotIdle = 0xffffffffu;
+
+struct PassSlots {
+    int4 *g;     // [S] random stream state
+    float4 *o;   // [S] origin, flux
+    float4 *w;   // [S] direction, excluded triangle (int bits)
+    uint2 *nb;   // [S] path index (kSlotIdle: none), next bounce
+    uint32_t S;
+};
+
+__device__ __forceinline__ bool slot_load(const PassSlots &ps, uint32_t s, PhotonPath &P) {
+    const uint2 nb = ps.nb[s];
+    if (nb.x == kSlotIdle) return false;
+    const int4 g = ps.g[s];
+    const float4 o = ps.o[s], w = ps.w[s];
+    P.g = Rng{g.x, g.y, g.z, g.w};
+    P.org = v3(o.x, o.y, o.z);
+    P.phi = o.w;
+    P.dir = v3(w.x, w.y, w.z);
+    P.excl = __float_as_int(w.w);
+    P.n = nb.x;
+    P.b = (int32_t)nb.y;
+    P.last = -1;
+    return true;
+}
+
+__device__ __forceinline__ void slot_store(const PassSlots &ps, uint32_t s, const PhotonPath &P, bool live) {
+    if (live) {
+        ps.g[s] = make_int4(P.g.s0, P.g.s1, P.g.s2, P.g.s3);
+        ps.o[s] = make_float4(P.org.x, P.org.y, P.org.z, P.phi);
+        ps.w[s] = make_float4(P.dir.x, P.dir.y, P.dir.z, __int_as_float(P.excl));
+        ps.nb[s] = make_uint2(P.n, (uint32_t)P.b);
+    } else {
+        ps.nb[s] = make_uint2(kSlotIdle, 0u);
+    }
+}
+
+// Two-phase photon pass (PM_PHOTON_TWO_PHASE).  A path can reflect inside a
+// glass object up to the bounce limit, so the pass ends with a few long paths
+// on an almost idle device.  The first launch (regeneration) stops once the
+// path counter has run out and at most kParkLive lanes of a wavefront still
+// hold a path: those paths go to a queue in device memory and the wavefront
+// exits.  A second launch, on a stream of its own, continues the queued
+// paths, so the first launch of the next iteration can start beside it.
+// Each path consumes its random stream as in photon_elem, so the photons are
+// the same.
+#ifndef PM_PARK_LIVE
+#define PM_PARK_LIVE 32
+#endif
+constexpr uint32_t kParkLive = PM_PARK_LIVE;
+
+struct PathQueue {
+    PassSlots s;    // s.S slots: at least the first launch's lanes
+    uint32_t *cnt;  // [0] paths queued, [1] queued paths taken by the second launch
+};
+
 // Photon paths with regeneration (Sec. 3.3): persistent lanes trace one bounce
 // per step; a lane whose path ended takes the next path index from the
 // counter d.counters[2] once at least `refill` lanes of its wave are idle (or
@@ -323,22 +381,34 @@ __device__ __forceinline__ void photon_elem(const SppmDev &d, uint32_t k, uint32
 // bounded by max_bounces, so every wave exits once the counter passes n_paths.
 // Called by every lane of a wave; the wave's lanes must share one scene.
 // kRecord (adjoint replay): paths also write their rows of mat_tab / adj_tab
-// as in photon_elem.
-template <bool kRecord = false, bool kStats = false>
+// as in photon_elem.  kPark (first launch of the two-phase pass): once the
+// path counter has run out and at most kParkLive lanes hold a path, those
+// paths go to the queue and the wave stops.  kQueue (second launch): the
+// lanes take the queued paths (counted by queue.cnt[1]) instead of starting
+// new ones.
+template <bool kRecord = false, bool kStats = false, bool kPark = false, bool kQueue = false>
 __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, uint32_t refill,
                                                   uint16_t *__restrict__ mat_tab = nullptr,
-                                                  long long *__restrict__ adj_tab = nullptr) {
+                                                  long long *__restrict__ adj_tab = nullptr,
+                                                  PathQueue queue = PathQueue{}) {
     PhotonPath P;
     LaneStats ls;
     bool live = false, exhausted = false;
+    uint32_t n_queued = 0u;
+    if constexpr (kQueue) n_queued = queue.cnt[0];
     for (;;) {
         bool idle = !live && !exhausted;
         uint64_t idle_mask = __ballot(idle);
         uint64_t live_mask = __ballot(live);
         if (idle_mask != 0ull && (live_mask == 0ull || (uint32_t)__popcll(idle_mask) >= refill)) {
-            uint32_t n = wave_fetch_add(&d.counters[2], idle_mask, idle);
+            uint32_t n = wave_fetch_add(kQueue ? &queue.cnt[1] : &d.counters[2], idle_mask, idle);
             if (idle) {
-                if (n < d.n_paths) {
+                if constexpr (kQueue) {
+                    if (n < n_queued)
+                        live = slot_load(queue.s, n, P);
+                    else
+                        exhausted = true;
+                } else if (n < d.n_paths) {
                     live = photon_emit(d, k, n, P);
                     if (kStats) ls.paths++;
                     if (kRecord && !live) photon_finish<true>(d, P, mat_tab);
@@ -349,6 +419,15 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
             live_mask = __ballot(live);
         }
         if (live_mask == 0ull && __ballot(!exhausted) == 0ull) break;
+        if constexpr (kPark) {
+            if (__ballot(exhausted) != 0ull && (uint32_t)__popcll(live_mask) <= kParkLive) {
+                if (live_mask != 0ull) {
+                    const uint32_t v = wave_fetch_add(&queue.cnt[0], live_mask, live);
+                    if (live) slot_store(queue.s, v, P, true);
+                }
+                break;
+            }
+        }
         if (live) {
             live = photon_bounce<kRecord, kStats>(d, P, mat_tab, adj_tab, &ls);
             if (kRecord && !live) photon_finish<true>(d, P, mat_tab);
@@ -564,43 +643,6 @@ __device__ __forceinline__ void photon_regen_range(const SppmDev &d, uint32_t k,
 // next path index in the following pass and traces that path's first segment
 // there.  A slot's path state lives in memory between passes.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kSlotIdle = 0xffffffffu;
-
-struct PassSlots {
-    int4 *g;     // [S] random stream state
-    float4 *o;   // [S] origin, flux
-    float4 *w;   // [S] direction, excluded triangle (int bits)
-    uint2 *nb;   // [S] path index (kSlotIdle: none), next bounce
-    uint32_t S;
-};
-
-__device__ __forceinline__ bool slot_load(const PassSlots &ps, uint32_t s, PhotonPath &P) {
-    const uint2 nb = ps.nb[s];
-    if (nb.x == kSlotIdle) return false;
-    const int4 g = ps.g[s];
-    const float4 o = ps.o[s], w = ps.w[s];
-    P.g = Rng{g.x, g.y, g.z, g.w};
-    P.org = v3(o.x, o.y, o.z);
-    P.phi = o.w;
-    P.dir = v3(w.x, w.y, w.z);
-    P.excl = __float_as_int(w.w);
-    P.n = nb.x;
-    P.b = (int32_t)nb.y;
-    P.last = -1;
-    return true;
-}
-
-__device__ __forceinline__ void slot_store(const PassSlots &ps, uint32_t s, const PhotonPath &P, bool live) {
-    if (live) {
-        ps.g[s] = make_int4(P.g.s0, P.g.s1, P.g.s2, P.g.s3);
-        ps.o[s] = make_float4(P.org.x, P.org.y, P.org.z, P.phi);
-        ps.w[s] = make_float4(P.dir.x, P.dir.y, P.dir.z, __int_as_float(P.excl));
-        ps.nb[s] = make_uint2(P.n, (uint32_t)P.b);
-    } else {
-        ps.nb[s] = make_uint2(kSlotIdle, 0u);
-    }
-}
-
 // The path counter as one value for the whole wave (it only grows).
 __device__ __forceinline__ uint32_t paths_handed_out(const SppmDev &d) {
     const uint32_t c = __hip_atomic_load(&d.counters[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

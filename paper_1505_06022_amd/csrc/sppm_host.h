@@ -21,6 +21,8 @@ struct pm_sppm {
     uint32_t regen_grid_rec = 1;  // and of its recording variant (adjoint replay)
     uint32_t stream_grid = 1;     // workgroups of the ray-granularity regenerating photon kernel
     uint32_t pool_grid = 1;       // workgroups of the LDS-queue photon kernel
+    uint32_t head_grid = 1;       // workgroups of the two-phase pass's first launch
+    uint32_t tail_grid = 1;       // and of its second
     float phi0 = 0.0f;
     // device buffers
     int32_t *mat_type = nullptr;
@@ -35,6 +37,13 @@ struct pm_sppm {
     float4 *store2 = nullptr;
     hipStream_t phs = nullptr;
     hipEvent_t ev_ph[2] = {}, ev_scat[2] = {};
+    // two-phase photon pass (PM_PHOTON_TWO_PHASE): a queue per store parity
+    // for the paths set aside by the first launch; on a pipelined handle the
+    // second launch runs on its own stream after the first (event ev_head)
+    void *queue_mem = nullptr;
+    pmd::PathQueue queue[2] = {};
+    hipStream_t tails = nullptr;
+    hipEvent_t ev_head[2] = {};
     uint2 *key_rank = nullptr;  // exact gather: [cap] bucket and rank of each stored photon
     uint32_t *counters = nullptr;  // [8]: per photon store [0] photons stored, [1] sticky flags, [2] next path, [3] pass leftovers
     unsigned long long *r2max = nullptr;

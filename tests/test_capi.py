@@ -76,7 +76,7 @@ def test_host_validation_errors_without_gpu():
     assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
     assert b"alpha" in L.pm_last_error()
     # the one-bounce-per-pass photon schedule and its two knobs
-    for bad in (dict(photon_kernel=6), dict(photon_kernel=-1)):
+    for bad in (dict(photon_kernel=7), dict(photon_kernel=-1)):
         p = api.sppm_params(1024, **bad)
         assert L.pm_sppm_create(C.byref(args.desc), C.byref(p), None, C.byref(out)) == api.PM_ERR_ARG
         assert b"photon_kernel" in L.pm_last_error()

@@ -120,7 +120,7 @@ def test_specular_scene_parity(torch_cuda, oracle_lib):
 
 
 @pytest.mark.parametrize("photon_kernel,refill", [(1, 0), (2, 1), (2, 8), (2, 64), (4, 0), (4, 1), (4, 16), (4, 64),
-                                                  (5, 0)])
+                                                  (5, 0), (6, 0), (6, 1), (6, 64)])
 def test_photon_kernels_parity(torch_cuda, oracle_lib, photon_kernel, refill):
     """One path per lane, lanes regenerating paths, and lanes regenerating rays
     give the same photons and images."""
@@ -233,7 +233,7 @@ def test_determinism_across_schedules(torch_cuda):
     out = []
     for kw in (dict(), dict(), dict(photon_kernel=1), dict(photon_kernel=2, refill=1), dict(photon_kernel=3),
                dict(photon_kernel=3, pass_threads=333, passes=2), dict(photon_kernel=4), dict(photon_kernel=4, refill=5),
-               dict(photon_kernel=5)):
+               dict(photon_kernel=5), dict(photon_kernel=6), dict(photon_kernel=6, refill=3)):
         s = api.Sppm(sc, api.sppm_params(1 << 13, r0=0.03, seed=21, **kw))
         s.iterate(3)
         img = s.resolve().cpu().numpy()
@@ -460,7 +460,8 @@ def test_profile_counts_and_times(torch_cuda, oracle_lib):
     Np, K, r0, seed = 1 << 14, 3, 0.02, 5
     out = {}
     for prof, pk in ((0, 0), (api.PROFILE_COUNT, 0), (api.PROFILE_TIME, 0), (api.PROFILE_COUNT | api.PROFILE_TIME, 0),
-                     (api.PROFILE_COUNT | 8, 4), (api.PROFILE_COUNT | 16, 5)):
+                     (api.PROFILE_COUNT | 8, 4), (api.PROFILE_COUNT | 16, 5), (api.PROFILE_COUNT | 32, 2),
+                     (api.PROFILE_TIME | 64, 2)):
         s = api.Sppm(sc, api.sppm_params(Np, r0=r0, seed=seed, profile=prof & 3, photon_kernel=pk))
         s.iterate(K)
         img = s.resolve().cpu().numpy()
@@ -495,8 +496,9 @@ def test_profile_counts_and_times(torch_cuda, oracle_lib):
     for k in ("ms_eye", "ms_photon", "ms_grid", "ms_gather", "ms_update"):
         assert 0 < st[k] < st["ms_iteration"], k
     assert out[api.PROFILE_TIME][2]["eye_paths"] == 0      # counting was off there
-    # the ray-granularity and LDS-queue kernels walk the same rays and store the same photons
-    for key in (api.PROFILE_COUNT | 8, api.PROFILE_COUNT | 16):
+    # the ray-granularity, LDS-queue and single-launch regeneration kernels walk the same rays and store the
+    # same photons as the default two-phase pass
+    for key in (api.PROFILE_COUNT | 8, api.PROFILE_COUNT | 16, api.PROFILE_COUNT | 32):
         st4 = out[key][2]
         for k in ("photon_paths", "photon_rays", "photons_stored", "photon_box_tests", "photon_tri_tests"):
             assert st4[k] == out[api.PROFILE_COUNT][2][k], (key, k)
@@ -517,7 +519,7 @@ def test_spatial_split_bvh_gives_the_same_render_and_gradient(torch_cuda):
     plain = api.build_bvh(sc.verts, sc.tri_mat)
     split = api.build_bvh(sc.verts, sc.tri_mat, split_alpha=1e-4)
     assert split.info()["n_refs"] > split.info()["n_tri"] == plain.info()["n_refs"]
-    for kw in (dict(), dict(photon_kernel=1), dict(photon_kernel=3, pass_threads=4096, passes=4),
+    for kw in (dict(), dict(photon_kernel=1), dict(photon_kernel=2), dict(photon_kernel=3, pass_threads=4096, passes=4),
                dict(photon_kernel=4), dict(photon_kernel=5)):
         out = []
         for bvh in (plain, split):
