@@ -487,7 +487,7 @@ void sppm_free(pm_sppm *s) {
                     s->cell_fill, s->bsum, s->M, s->Phi, s->R2_hist, s->adj_tab, s->mat_tab, s->adj_tab2,
                     s->mat_tab2, s->grad_mat,
                     s->adj_wide, s->adj_max, s->adj_scale, s->le_part, s->stats, s->sh_key, s->sh_surv, s->slot_mem, s->key_rank,
-                    s->queue_mem};
+                    s->queue_mem, s->hp_pos2, s->hp_nrm2};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : s->prof_ev)
@@ -497,8 +497,11 @@ void sppm_free(pm_sppm *s) {
         if (s->ev_scat[i]) (void)hipEventDestroy(s->ev_scat[i]);
     }
     if (s->phs) (void)hipStreamDestroy(s->phs);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i) {
         if (s->ev_head[i]) (void)hipEventDestroy(s->ev_head[i]);
+        if (s->ev_eye[i]) (void)hipEventDestroy(s->ev_eye[i]);
+        if (s->ev_upd[i]) (void)hipEventDestroy(s->ev_upd[i]);
+    }
     if (s->tails) (void)hipStreamDestroy(s->tails);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     if (s->ev_join) (void)hipEventDestroy(s->ev_join);
@@ -652,7 +655,11 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         for (int i = 0; i < 2; ++i) {
             PM_HIPF(hipEventCreateWithFlags(&s->ev_ph[i], hipEventDisableTiming));
             PM_HIPF(hipEventCreateWithFlags(&s->ev_scat[i], hipEventDisableTiming));
+            PM_HIPF(hipEventCreateWithFlags(&s->ev_eye[i], hipEventDisableTiming));
+            PM_HIPF(hipEventCreateWithFlags(&s->ev_upd[i], hipEventDisableTiming));
         }
+        PM_HIPF(hipMalloc(&s->hp_pos2, sizeof(float4) * s->P));
+        PM_HIPF(hipMalloc(&s->hp_nrm2, sizeof(float4) * s->P));
         if (photon_kernel_of(p, own_grid) == PM_PHOTON_TWO_PHASE) {
             PM_HIPF(hipStreamCreateWithFlags(&s->tails, hipStreamNonBlocking));
             for (int i = 0; i < 2; ++i) PM_HIPF(hipEventCreateWithFlags(&s->ev_head[i], hipEventDisableTiming));
@@ -739,6 +746,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     }
     PM_HIPF(hipMemsetAsync(s->counters, 0, sizeof(uint32_t) * 8, st));
     PM_HIPF(hipMemsetAsync(s->hp_nrm, 0xff, sizeof(float4) * s->P, st));
+    if (s->hp_nrm2) PM_HIPF(hipMemsetAsync(s->hp_nrm2, 0xff, sizeof(float4) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->M, 0, sizeof(uint32_t) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->Phi, 0, sizeof(unsigned long long) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->r2max, 0, sizeof(unsigned long long), st));
@@ -868,12 +876,17 @@ int sppm_reset(pm_sppm *s, hipStream_t st) {
 }
 
 // Device view of iteration k: a pipelined handle alternates two photon stores
-// (each with its block of four counters) between consecutive iterations.
+// (each with its block of four counters) and two hit-point buffers between
+// consecutive iterations.
 static SppmDev iteration_view(const pm_sppm *s, uint32_t k) {
     SppmDev dk = s->dev;
     const uint32_t par = s->store2 ? (k & 1u) : 0u;
     dk.store = par ? s->store2 : s->store;
     dk.counters = s->counters + 4 * par;
+    if (par && s->hp_pos2) {
+        dk.hp_pos = s->hp_pos2;
+        dk.hp_nrm = s->hp_nrm2;
+    }
     return dk;
 }
 
@@ -955,11 +968,21 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
     // the two-phase pass's second launch runs on its own stream, so that the
     // next pass's first launch can start beside it
     hipStream_t tq = s->tails ? s->tails : s->phs;
+    auto eye_pass = [&](const SppmDev &dv, uint32_t kk, hipStream_t q) {
+        if (count)
+            hipLaunchKernelGGL(k_eye_stats, dim3(blocks_for(s->P)), dim3(kBlock), 0, q, dv, kk, 1);
+        else
+            hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, q, dv, kk, 1);
+    };
     if (pipe) {
+        // photon pass and eye pass of the first iteration, each on its stream
         PM_HIP(hipEventRecord(s->ev_fork, st));
         PM_HIP(hipStreamWaitEvent(s->phs, s->ev_fork, 0));
+        PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
         if ((rc = enqueue_photon(s, iteration_view(s, k0), k0, count, s->phs, tq))) return rc;
         PM_HIP(hipEventRecord(s->ev_ph[k0 & 1u], tq));
+        eye_pass(iteration_view(s, k0), k0, s->side);
+        PM_HIP(hipEventRecord(s->ev_eye[k0 & 1u], s->side));
     }
     for (int32_t it = 0; it < n_iter; ++it) {
         const uint32_t k = k0 + (uint32_t)it;
@@ -969,30 +992,37 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
             if (it >= 1) PM_HIP(hipStreamWaitEvent(s->phs, s->ev_scat[(k + 1u) & 1u], 0));
             if ((rc = enqueue_photon(s, iteration_view(s, k + 1u), k + 1u, count, s->phs, tq))) return rc;
             PM_HIP(hipEventRecord(s->ev_ph[(k + 1u) & 1u], tq));
+            // the next eye pass refills the hit points that the update of k - 1 read
+            if (it >= 1) PM_HIP(hipStreamWaitEvent(s->side, s->ev_upd[(k + 1u) & 1u], 0));
+            eye_pass(iteration_view(s, k + 1u), k + 1u, s->side);
+            PM_HIP(hipEventRecord(s->ev_eye[(k + 1u) & 1u], s->side));
         }
         if (timed) PM_HIP(hipEventRecord(ev[0], st));
-        // eye pass and R_max on the side stream, beside the photon pass: they
-        // share no data, and the eye pass's long specular paths would
-        // otherwise leave the device idle at its end
-        PM_HIP(hipEventRecord(s->ev_fork, st));
-        PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
-        if (timed) PM_HIP(hipEventRecord(ev[1], s->side));
-        hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, s->side, dk);
-        if (count)
-            hipLaunchKernelGGL(k_eye_stats, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 1);
-        else
-            hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 1);
-        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, dk,
-                           (const double *)s->R2);
-        if (timed) PM_HIP(hipEventRecord(ev[2], s->side));
-        PM_HIP(hipEventRecord(s->ev_join, s->side));
-        if (!pipe) {
+        if (pipe) {
+            // R_max over the radii after the update of k - 1 and the hit points of k
+            PM_HIP(hipStreamWaitEvent(st, s->ev_eye[k & 1u], 0));
+            hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, st, dk);
+            hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, st, dk,
+                               (const double *)s->R2);
+        } else {
+            // eye pass and R_max on the side stream, beside the photon pass:
+            // they share no data, and the eye pass's long specular paths would
+            // otherwise leave the device idle at its end
+            PM_HIP(hipEventRecord(s->ev_fork, st));
+            PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+            if (timed) PM_HIP(hipEventRecord(ev[1], s->side));
+            hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, s->side, dk);
+            eye_pass(dk, k, s->side);
+            hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, dk,
+                               (const double *)s->R2);
+            if (timed) PM_HIP(hipEventRecord(ev[2], s->side));
+            PM_HIP(hipEventRecord(s->ev_join, s->side));
             if (timed) PM_HIP(hipEventRecord(ev[3], st));
             if ((rc = enqueue_photon(s, dk, k, count, st, st))) return rc;
             if (timed) PM_HIP(hipEventRecord(ev[4], st));
         }
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
-        PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+        if (!pipe) PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
         if (pipe) PM_HIP(hipStreamWaitEvent(st, s->ev_ph[k & 1u], 0));
         if (timed) PM_HIP(hipEventRecord(ev[5], st));
         if (dk.gather_mode == PM_GATHER_STOCHASTIC) {
@@ -1020,6 +1050,7 @@ int sppm_iterate(pm_sppm *s, int32_t n_iter, hipStream_t st) {
         if (timed) PM_HIP(hipEventRecord(ev[7], st));
         double *hist = (int32_t)k < s->rec_iters ? s->R2_hist + (size_t)k * s->P : nullptr;
         hipLaunchKernelGGL(k_update, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk, hist);
+        if (pipe) PM_HIP(hipEventRecord(s->ev_upd[k & 1u], st));
         PM_HIP(hipGetLastError());
         if (timed) {  // wait for the iteration and add its stage times
             PM_HIP(hipEventRecord(ev[8], st));
@@ -1388,10 +1419,10 @@ int sppm_views(pm_sppm *s, pm_sppm_views *v) {
     v->R2 = s->R2;
     v->tau = s->tau;
     v->D = s->D;
-    v->hp_pos = (float *)s->hp_pos;
-    v->hp_nrm = (float *)s->hp_nrm;
-    // the last iteration's photon store and counters (a pipelined handle alternates two)
+    // the last iteration's hit points, photon store and counters (a pipelined handle alternates two of each)
     const uint32_t par = (s->store2 && s->K > 0) ? (uint32_t)((s->K - 1) & 1) : 0u;
+    v->hp_pos = (float *)(par ? s->hp_pos2 : s->hp_pos);
+    v->hp_nrm = (float *)(par ? s->hp_nrm2 : s->hp_nrm);
     v->photons = (float *)(par ? s->store2 : s->store);
     v->photon_count = s->counters + 4 * par;
     v->gather_M = s->M;

@@ -41,6 +41,11 @@ struct pm_sppm {
     // for the paths set aside by the first launch; on a pipelined handle the
     // second launch runs on its own stream after the first (event ev_head)
     void *queue_mem = nullptr;
+    // a second hit-point buffer (pipelined handles): the eye pass of k + 1
+    // writes it while the range query and update of k read the first; events
+    // per buffer: eye pass done, update done
+    float4 *hp_pos2 = nullptr, *hp_nrm2 = nullptr;
+    hipEvent_t ev_eye[2] = {}, ev_upd[2] = {};
     pmd::PathQueue queue[2] = {};
     hipStream_t tails = nullptr;
     hipEvent_t ev_head[2] = {};
