@@ -58,6 +58,20 @@ __global__ __launch_bounds__(kBlock) void k_photon_tail(SppmDev d, uint32_t k, P
     photon_regen_loop<false, kStats, false, true>(d, k, d.refill, nullptr, nullptr, q);
 }
 
+// The same two launches, recording each path's stored-photon materials for
+// the adjoint (a queued path keeps its row of the tables).
+__global__ __launch_bounds__(kBlock) void k_photon_head_rec(SppmDev d, uint32_t k, PathQueue q,
+                                                            uint16_t *__restrict__ mat_tab,
+                                                            long long *__restrict__ adj_tab) {
+    photon_regen_loop<true, false, true, false>(d, k, d.refill, mat_tab, adj_tab, q);
+}
+
+__global__ __launch_bounds__(kBlock) void k_photon_tail_rec(SppmDev d, uint32_t k, PathQueue q,
+                                                            uint16_t *__restrict__ mat_tab,
+                                                            long long *__restrict__ adj_tab) {
+    photon_regen_loop<true, false, false, true>(d, k, d.refill, mat_tab, adj_tab, q);
+}
+
 // Regeneration from a queue of started paths in LDS (PM_PHOTON_POOL): each
 // wavefront owns kPoolWords x kPoolSlots words of the workgroup's LDS.
 template <bool kStats>
@@ -647,7 +661,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     PM_HIPF(hipMalloc(&s->hp_nrm, sizeof(float4) * s->P));
     PM_HIPF(hipMalloc(&s->store, sizeof(float4) * 2 * (size_t)cap64));
     PM_HIPF(hipMalloc(&s->counters, sizeof(uint32_t) * 8));
-    PM_HIPF(hipMalloc(&s->r2max, sizeof(unsigned long long)));
+    PM_HIPF(hipMalloc(&s->r2max, sizeof(unsigned long long) * 2));  // one per iteration parity
     if (own_grid && !(p->profile & PM_PROFILE_TIME)) {
         // a second photon store and a photon stream: consecutive iterations overlap
         PM_HIPF(hipMalloc(&s->store2, sizeof(float4) * 2 * (size_t)cap64));
@@ -749,7 +763,7 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
     if (s->hp_nrm2) PM_HIPF(hipMemsetAsync(s->hp_nrm2, 0xff, sizeof(float4) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->M, 0, sizeof(uint32_t) * s->P, st));
     PM_HIPF(hipMemsetAsync(s->Phi, 0, sizeof(unsigned long long) * s->P, st));
-    PM_HIPF(hipMemsetAsync(s->r2max, 0, sizeof(unsigned long long), st));
+    PM_HIPF(hipMemsetAsync(s->r2max, 0, sizeof(unsigned long long) * 2, st));
 
     SceneDev &sc = s->dev.sc;
     sc.bvh = make_device_bvh(b);
@@ -818,11 +832,16 @@ int sppm_create_ex(const pm_scene_desc *d, const pm_sppm_params *p, hipStream_t 
         s->head_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
         PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_tail<false>, kBlock, 0));
         s->tail_grid = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_head_rec, kBlock, 0));
+        s->head_grid_rec = (uint32_t)std::max(1, cus * std::max(1, per_cu));
+        PM_HIPF(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_photon_tail_rec, kBlock, 0));
+        s->tail_grid_rec = (uint32_t)std::max(1, cus * std::max(1, per_cu));
     }
     if (dv.photon_kernel == PM_PHOTON_TWO_PHASE) {
         // per store parity: a queue slot for every lane of the first launch
         // (each parks at most one path), then the queue's two counters
-        const uint32_t S = (uint32_t)std::min<int64_t>(p->n_photons, (int64_t)s->head_grid * kBlock);
+        const uint32_t S = (uint32_t)std::min<int64_t>(
+            p->n_photons, (int64_t)std::max(s->head_grid, s->head_grid_rec) * kBlock);
         const size_t per = (size_t)56 * S + 256;
         PM_HIPF(hipMalloc(&s->queue_mem, 2 * per));
         for (int i = 0; i < 2; ++i) {
@@ -876,13 +895,14 @@ int sppm_reset(pm_sppm *s, hipStream_t st) {
 }
 
 // Device view of iteration k: a pipelined handle alternates two photon stores
-// (each with its block of four counters) and two hit-point buffers between
-// consecutive iterations.
+// (each with its block of four counters), two hit-point buffers and two R_max
+// accumulators between consecutive iterations.
 static SppmDev iteration_view(const pm_sppm *s, uint32_t k) {
     SppmDev dk = s->dev;
     const uint32_t par = s->store2 ? (k & 1u) : 0u;
     dk.store = par ? s->store2 : s->store;
     dk.counters = s->counters + 4 * par;
+    dk.r2max = s->r2max + par;
     if (par && s->hp_pos2) {
         dk.hp_pos = s->hp_pos2;
         dk.hp_nrm = s->hp_nrm2;
@@ -1152,22 +1172,56 @@ static int adjoint_overlapped(pm_sppm *s, const float *g, hipStream_t st) {
     auto mat_of = [&](uint32_t k) { return (k & 1u) ? s->mat_tab2 : s->mat_tab; };
     auto tab_of = [&](uint32_t k) { return (k & 1u) ? s->adj_tab2 : s->adj_tab; };
     auto max_of = [&](uint32_t k) { return s->adj_max + 2 * (k & 1u); };
-    auto replay = [&](uint32_t k) -> int {  // on the photon stream
+    // the replayed photon pass: on the photon stream, or (two-phase handles)
+    // its first launch there and the second on the tail stream, beside the
+    // first launch of the next replay; the flux maximum follows the pass
+    const bool two = s->dev.photon_kernel == PM_PHOTON_TWO_PHASE && s->tails;
+    hipStream_t tq = two ? s->tails : s->phs;
+    auto replay = [&](uint32_t k) -> int {
         const SppmDev dk = iteration_view(s, k);
         hipLaunchKernelGGL(k_photon_begin, dim3(1), dim3(64), 0, s->phs, dk);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s->phs, (uint32_t *)(max_of(k) + 1), 2u, 0u);
-        hipLaunchKernelGGL(k_photon_regen_rec, dim3(s->regen_grid_rec), dim3(kBlock), 0, s->phs, dk, k, mat_of(k),
-                           tab_of(k));
-        hipLaunchKernelGGL(k_adj_phimax, dim3(std::min<uint32_t>(ph_blocks, kAdjMaxBlocks)), dim3(kBlock), 0, s->phs,
-                           dk, max_of(k));
+        if (two) {
+            const PathQueue &pq = s->queue[k & 1u];
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s->phs, pq.cnt, 2u, 0u);
+            hipLaunchKernelGGL(k_photon_head_rec, dim3(s->head_grid_rec), dim3(kBlock), 0, s->phs, dk, k, pq,
+                               mat_of(k), tab_of(k));
+            PM_HIP(hipEventRecord(s->ev_head[k & 1u], s->phs));
+            PM_HIP(hipStreamWaitEvent(tq, s->ev_head[k & 1u], 0));
+            hipLaunchKernelGGL(k_photon_tail_rec, dim3(s->tail_grid_rec), dim3(kBlock), 0, tq, dk, k, pq, mat_of(k),
+                               tab_of(k));
+        } else {
+            hipLaunchKernelGGL(k_photon_regen_rec, dim3(s->regen_grid_rec), dim3(kBlock), 0, s->phs, dk, k,
+                               mat_of(k), tab_of(k));
+        }
+        hipLaunchKernelGGL(k_adj_phimax, dim3(std::min<uint32_t>(ph_blocks, kAdjMaxBlocks)), dim3(kBlock), 0, tq, dk,
+                           max_of(k));
         PM_HIP(hipGetLastError());
-        PM_HIP(hipEventRecord(s->ev_ph[k & 1u], s->phs));
+        PM_HIP(hipEventRecord(s->ev_ph[k & 1u], tq));
+        return PM_OK;
+    };
+    // the replayed eye pass, R_max (over the recorded radii) and max |G| wk of
+    // iteration k, on the side stream, into the hit-point buffer, R_max
+    // accumulator and maxima of k's parity
+    auto eye_chain = [&](uint32_t k) -> int {
+        const SppmDev dk = iteration_view(s, k);
+        const double *R2k = s->R2_hist + (size_t)k * s->P;
+        hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, s->side, dk);
+        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 0);
+        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, dk, R2k);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s->side, (uint32_t *)max_of(k), 2u, 0u);
+        hipLaunchKernelGGL(k_adj_gmax, dim3(std::min<uint32_t>(blocks_for(s->P), kAdjMaxBlocks)), dim3(kBlock), 0,
+                           s->side, dk, R2k, g, Kd, max_of(k));
+        PM_HIP(hipGetLastError());
+        PM_HIP(hipEventRecord(s->ev_eye[k & 1u], s->side));
         return PM_OK;
     };
     PM_HIP(hipEventRecord(s->ev_fork, st));
     PM_HIP(hipStreamWaitEvent(s->phs, s->ev_fork, 0));
+    PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
     int rc = replay(0);
     if (rc) return rc;
+    if ((rc = eye_chain(0))) return rc;
     for (uint32_t k = 0; k < K; ++k) {
         const SppmDev dk = iteration_view(s, k);
         const double *R2k = s->R2_hist + (size_t)k * s->P;
@@ -1175,20 +1229,14 @@ static int adjoint_overlapped(pm_sppm *s, const float *g, hipStream_t st) {
             // the replay of k + 1 reuses the store and tables that iteration k - 1 read
             if (k >= 1) PM_HIP(hipStreamWaitEvent(s->phs, s->ev_scat[(k + 1u) & 1u], 0));
             if ((rc = replay(k + 1))) return rc;
+            // and its eye pass the hit points, R_max and maxima that the range query of k - 1 read
+            if (k >= 1) PM_HIP(hipStreamWaitEvent(s->side, s->ev_upd[(k + 1u) & 1u], 0));
+            if ((rc = eye_chain(k + 1))) return rc;
         }
-        PM_HIP(hipEventRecord(s->ev_fork, st));
-        PM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
-        hipLaunchKernelGGL(k_rmax_clear, dim3(1), dim3(64), 0, s->side, dk);
-        hipLaunchKernelGGL(k_eye, dim3(blocks_for(s->P)), dim3(kBlock), 0, s->side, dk, k, 0);
-        hipLaunchKernelGGL(k_rmax, dim3(std::min(blocks_for(s->P), kRmaxBlocks)), dim3(kBlock), 0, s->side, dk, R2k);
-        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s->side, (uint32_t *)max_of(k), 2u, 0u);
-        hipLaunchKernelGGL(k_adj_gmax, dim3(std::min<uint32_t>(blocks_for(s->P), kAdjMaxBlocks)), dim3(kBlock), 0,
-                           s->side, dk, R2k, g, Kd, max_of(k));
-        PM_HIP(hipEventRecord(s->ev_join, s->side));
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(T)), dim3(kBlock), 0, st, s->cell_count, T, 0u);
         hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(4 * s->n_mat)), dim3(kBlock), 0, st, (uint32_t *)s->adj_wide,
                            (uint32_t)(4 * s->n_mat), 0u);
-        PM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+        PM_HIP(hipStreamWaitEvent(st, s->ev_eye[k & 1u], 0));
         PM_HIP(hipStreamWaitEvent(st, s->ev_ph[k & 1u], 0));
         hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(64), 0, st, (const unsigned long long *)max_of(k), s->adj_scale);
         hipLaunchKernelGGL(k_count, dim3(ph_blocks), dim3(kBlock), 0, st, dk, s->cell_count);
@@ -1198,6 +1246,7 @@ static int adjoint_overlapped(pm_sppm *s, const float *g, hipStream_t st) {
         hipLaunchKernelGGL(k_gather_adj, dim3(blocks_for(s->P)), dim3(kBlock), 0, st, dk, R2k,
                            (const uint32_t *)s->cell_start, (const float4 *)s->sorted, g, Kd,
                            (const double *)s->adj_scale, tab_of(k), s->n_mat, s->adj_wide);
+        PM_HIP(hipEventRecord(s->ev_upd[k & 1u], st));
         hipLaunchKernelGGL(k_path_adj, dim3(blocks_for(np)), dim3(kBlock), 0, st, (const uint16_t *)mat_of(k),
                            (const long long *)tab_of(k), np, mb, s->n_mat, s->adj_wide);
         PM_HIP(hipEventRecord(s->ev_scat[k & 1u], st));

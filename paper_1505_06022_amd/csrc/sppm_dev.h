@@ -404,10 +404,13 @@ __device__ __forceinline__ void photon_regen_loop(const SppmDev &d, uint32_t k, 
             uint32_t n = wave_fetch_add(kQueue ? &queue.cnt[1] : &d.counters[2], idle_mask, idle);
             if (idle) {
                 if constexpr (kQueue) {
-                    if (n < n_queued)
+                    if (n < n_queued) {
                         live = slot_load(queue.s, n, P);
-                    else
+                        // recording: a live path's last written bounce is the one before its next
+                        if (kRecord) P.last = P.b - 1;
+                    } else {
                         exhausted = true;
+                    }
                 } else if (n < d.n_paths) {
                     live = photon_emit(d, k, n, P);
                     if (kStats) ls.paths++;

@@ -23,6 +23,8 @@ struct pm_sppm {
     uint32_t pool_grid = 1;       // workgroups of the LDS-queue photon kernel
     uint32_t head_grid = 1;       // workgroups of the two-phase pass's first launch
     uint32_t tail_grid = 1;       // and of its second
+    uint32_t head_grid_rec = 1;   // the same two launches recording for the adjoint replay
+    uint32_t tail_grid_rec = 1;
     float phi0 = 0.0f;
     // device buffers
     int32_t *mat_type = nullptr;
