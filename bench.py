@@ -488,7 +488,8 @@ def sppm_bench(args, torch, api, scenes):
                                  "photons_per_s": round(64 * Np / (full_ms * 1e-3), 1)},
                     roofline=roof, tbvh=tbvh, stochastic_hashing=sh, pass_schedule=schedule,
                     workload="procedural 250,094 triangles, 1280x720, 2^20 photons/iteration")
-    runs = [("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
+    runs = [("two_phase (default)", dict(photon_kernel=6)), ("two_phase_refill16", dict(photon_kernel=6, refill=16)),
+            ("per_path", dict(photon_kernel=1)), ("regen_refill8", dict(photon_kernel=2, refill=8)),
             ("regen_refill16", dict(photon_kernel=2, refill=16)), ("regen_refill32", dict(photon_kernel=2, refill=32))]
     runs += [(f"ray_regen_refill{r}", dict(photon_kernel=4, refill=r)) for r in (4, 8, 16, 24, 32, 48)]
     runs += [("lds_queue", dict(photon_kernel=5))]
